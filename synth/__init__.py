@@ -1,0 +1,211 @@
+"""Seeded synthetic inputs for the triangle survey (edge lists, edge
+timestamps, vertex labels, batch parameters).
+
+This module produces raw inputs only and holds none of the survey's
+arithmetic.  Both the CPU oracle tests and the GPU path take their inputs
+from here, so the two sides see identical bytes.  The generator itself is
+plain C (``tpgen.c``) driven through ctypes; every value is a function of
+(seed, stream, index) only.
+
+Workloads follow the paper's synthetic family: R-MAT graphs (Evaluation,
+Datasets and Weak Scaling subsections) with a=0.57, b=0.19, c=0.19, d=0.05,
+edge factor 16, undirected; edge timestamps as edge metadata (the Reddit
+closure-time study) and small integer vertex labels (the labelled-triangle
+examples of the Callback Examples subsection).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tpgen.c")
+_LIB = os.path.join(_HERE, "libtpgen.so")
+
+# R-MAT quadrant thresholds floor(p * 2^32) for a=0.57, a+b=0.76, a+b+c=0.95.
+RMAT_THR = ((57 << 32) // 100, (76 << 32) // 100, (95 << 32) // 100)
+# Zipf(s=1.2) over labels 0..7: cumulative thresholds floor(CDF_k * 2^32),
+# k = 0..6, with p_k proportional to (k+1)^-1.2.
+ZIPF12_L8_THR = (1840948827, 2642268346, 3134870392, 3483664971,
+                 3750521426, 3964938920, 4143145637)
+MASTER_SEED = 2107123300
+
+_lib = None
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libtpgen.so with gcc (OpenMP)."""
+    cmd = ["gcc", "-O3", "-march=x86-64-v2", "-fopenmp", "-fPIC", "-shared",
+           "-std=c11", "-Wall", "-o", _LIB + ".tmp", _SRC]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    u64, u32, p = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p
+    lib.tpgen_draw.restype = u64
+    lib.tpgen_draw.argtypes = [u64, u32, u64]
+    lib.tpgen_rmat.argtypes = [u64, u32, u64, u32, u32, u32, p, p]
+    lib.tpgen_er.argtypes = [u64, u32, u64, p, p]
+    lib.tpgen_ts_uniform.argtypes = [u64, u64, u32, p]
+    lib.tpgen_ts_bursty.argtypes = [u64, u64, u32, p]
+    lib.tpgen_labels_uniform.argtypes = [u64, u32, u32, p]
+    lib.tpgen_labels_cdf.argtypes = [u64, u32, p, u32, p]
+    lib.tpgen_batch_params.argtypes = [u64, u32, u32, u32, u32, u32,
+                                       ctypes.POINTER(u64), ctypes.POINTER(u32),
+                                       ctypes.POINTER(u32), ctypes.POINTER(u32)]
+    _lib = lib
+    return lib
+
+
+def draw(seed: int, stream: int, index: int) -> int:
+    return int(_load().tpgen_draw(seed, stream, index))
+
+
+@dataclass
+class GraphSpec:
+    """Recipe of one synthetic graph."""
+    kind: str = "rmat"          # "rmat" | "er"
+    scale: int = 12             # n = 2^scale vertices
+    edge_factor: int = 16       # raw edges = edge_factor * n
+    seed: int = MASTER_SEED
+    ts: tuple = ("uniform", 20)     # ("uniform", bits) | ("bursty", n_bursts) | ("zero",)
+    labels: tuple = ("uniform", 4)  # ("uniform", L) | ("zipf12", 8) | ("zero",)
+
+    @property
+    def n(self) -> int:
+        return 1 << self.scale
+
+    @property
+    def n_edges(self) -> int:
+        return self.edge_factor << self.scale
+
+
+def _ptr(a) -> int:
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    return int(a)
+
+
+def fill_edges(spec: GraphSpec, src, dst) -> None:
+    """Write the spec's raw edges into src/dst (numpy arrays or host pointers)."""
+    lib = _load()
+    if spec.kind == "rmat":
+        lib.tpgen_rmat(spec.seed, spec.scale, spec.n_edges, *RMAT_THR, _ptr(src), _ptr(dst))
+    elif spec.kind == "er":
+        lib.tpgen_er(spec.seed, spec.n, spec.n_edges, _ptr(src), _ptr(dst))
+    else:
+        raise ValueError(spec.kind)
+
+
+def fill_ts(spec: GraphSpec, ts) -> None:
+    lib = _load()
+    kind = spec.ts[0]
+    if kind == "uniform":
+        lib.tpgen_ts_uniform(spec.seed, spec.n_edges, spec.ts[1], _ptr(ts))
+    elif kind == "bursty":
+        lib.tpgen_ts_bursty(spec.seed, spec.n_edges, spec.ts[1], _ptr(ts))
+    elif kind == "zero":
+        ctypes.memset(_ptr(ts), 0, 4 * spec.n_edges)
+    else:
+        raise ValueError(kind)
+
+
+def fill_labels(spec: GraphSpec, lab) -> None:
+    lib = _load()
+    kind = spec.labels[0]
+    if kind == "uniform":
+        lib.tpgen_labels_uniform(spec.seed, spec.n, spec.labels[1], _ptr(lab))
+    elif kind == "zipf12":
+        thr = (ctypes.c_uint32 * 7)(*ZIPF12_L8_THR)
+        lib.tpgen_labels_cdf(spec.seed, spec.n, ctypes.addressof(thr), 8, _ptr(lab))
+    elif kind == "zero":
+        ctypes.memset(_ptr(lab), 0, spec.n)
+    else:
+        raise ValueError(kind)
+
+
+def n_labels(spec: GraphSpec) -> int:
+    return 1 if spec.labels[0] == "zero" else int(spec.labels[1])
+
+
+def generate(spec: GraphSpec) -> dict:
+    """Return numpy arrays src, dst, ts (uint32[M]) and vlab (uint8[n])."""
+    M, n = spec.n_edges, spec.n
+    src = np.empty(M, np.uint32)
+    dst = np.empty(M, np.uint32)
+    ts = np.empty(M, np.uint32)
+    vlab = np.empty(n, np.uint8)
+    fill_edges(spec, src, dst)
+    fill_ts(spec, ts)
+    fill_labels(spec, vlab)
+    return dict(n=n, src=src, dst=dst, ts=ts, vlab=vlab)
+
+
+# --------------------------------------------------------------------------
+# The five workloads.  Survey outputs are named by plain strings here; the
+# binding and the oracle wrapper each translate them into their own form.
+# --------------------------------------------------------------------------
+
+@dataclass
+class Workload:
+    number: int
+    name: str
+    graph: GraphSpec | None
+    outputs: tuple = ()
+    n_labels: int = 4
+    spread_lt: int = 0
+    extra: dict = field(default_factory=dict)
+
+
+def workload(number: int, scale: int | None = None) -> Workload:
+    """Workload 1..5.  `scale` overrides the graph scale (same recipe)."""
+    seed = MASTER_SEED + number
+    if number == 1:
+        g = GraphSpec("rmat", scale or 12, 16, seed, ("uniform", 20), ("uniform", 4))
+        return Workload(1, "rmat-s%d-uniform" % g.scale, g, ("count", "close_hist", "label_table"), 4)
+    if number == 2:
+        g = GraphSpec("rmat", scale or 22, 16, seed, ("uniform", 30), ("zipf12", 8))
+        return Workload(2, "rmat-s%d-zipf" % g.scale, g, ("count", "close_hist", "label_table"), 8)
+    if number == 3:
+        g = GraphSpec("rmat", scale or 26, 16, seed, ("bursty", 64), ("uniform", 4))
+        return Workload(3, "rmat-s%d-bursty" % g.scale, g,
+                        ("count", "close_hist", "label_table", "spread_count"), 4, spread_lt=1 << 16)
+    if number == 4:
+        return Workload(4, "batch-20000", None, ("count", "close_hist"), 8,
+                        extra=dict(n_graphs=20000, scale_lo=6, scale_hi=16, ef_lo=4, ef_hi=32))
+    if number == 5:
+        g = GraphSpec("rmat", scale or 28, 16, seed, ("bursty", 64), ("uniform", 8))
+        return Workload(5, "served-rmat-s%d" % g.scale, g, ("count", "close_hist", "label_table"), 8,
+                        extra=dict(pool_scale_lo=16, pool_scale_hi=20))
+    raise ValueError(number)
+
+
+def batch_graph_spec(g: int, master: int = MASTER_SEED + 4, scale_lo: int = 6, scale_hi: int = 16,
+                     ef_lo: int = 4, ef_hi: int = 32) -> GraphSpec:
+    """Recipe of graph g of the batched workload: R-MAT or Erdos-Renyi 50/50,
+    scale uniform in [scale_lo, scale_hi], edge factor uniform in
+    [ef_lo, ef_hi], timestamps uniform on [0, 2^20), labels uniform 0..7."""
+    lib = _load()
+    sg = ctypes.c_uint64()
+    kind = ctypes.c_uint32()
+    sc = ctypes.c_uint32()
+    ef = ctypes.c_uint32()
+    lib.tpgen_batch_params(master, g, scale_lo, scale_hi, ef_lo, ef_hi,
+                           ctypes.byref(sg), ctypes.byref(kind), ctypes.byref(sc), ctypes.byref(ef))
+    return GraphSpec("er" if kind.value else "rmat", sc.value, ef.value, sg.value,
+                     ("uniform", 20), ("uniform", 8))
