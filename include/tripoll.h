@@ -1,0 +1,262 @@
+/*
+ * tripoll.h -- C ABI of the MI355X (gfx950) metadata triangle survey.
+ *
+ * The operation is the triangle survey of Steil et al., "TriPoll: Computing
+ * Surveys of Triangles in Massive-Scale Temporal Graphs with Metadata":
+ * every triangle of an undirected graph decorated with vertex and edge
+ * metadata is found exactly once on the degree-ordered directed graph
+ * (Preliminaries; Graph Storage subsection), and the six metadata items of
+ * each triangle are handed to a callback that reduces them into counters
+ * (Algorithm 1; Callback Examples subsection).  The arbitrary callback of the
+ * paper is replaced here by a closed menu of reductions (TP_OUT_*) and
+ * prefilters (TP_FILT_*); results are the counters' final values.
+ *
+ * Metadata carried: one uint32 time per edge and one uint8 label per vertex.
+ *
+ * Conventions for every entry point:
+ *   - The return value is a tp_status; nothing aborts or throws across the
+ *     ABI.  On a non-OK status, tripoll_last_error() returns a message for
+ *     the calling thread and the caller's output arguments are untouched.
+ *   - Input arrays are borrowed for the duration of the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is ordered on that stream; calls documented as synchronous return
+ *     only after their work has completed.
+ *   - Objects returned through `**out` are owned by the caller and released
+ *     with the matching *_free call.  A graph is immutable after it is built
+ *     and may be surveyed concurrently from several streams.
+ *   - All counters are uint64 and exact.
+ */
+#ifndef TRIPOLL_H
+#define TRIPOLL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TP_OK = 0,
+    TP_ERR_INVALID = 1,     /* bad argument or input (id >= n, label >= n_labels, ...) */
+    TP_ERR_OOM = 2,         /* device or host allocation failed; nothing leaked */
+    TP_ERR_DEVICE = 3,      /* a HIP call failed */
+    TP_ERR_BUSY = 4,        /* server queue or slot table full */
+    TP_ERR_UNSUPPORTED = 5, /* valid but not supported (e.g. no gfx950 device) */
+    TP_ERR_NOT_FOUND = 6    /* unknown handle or ticket */
+} tp_status;
+
+/* Where the arrays of a tp_edge_list live. */
+#define TP_MEM_HOST 0u
+#define TP_MEM_DEVICE 1u
+
+/* Tie-break `hash` of the degree order (Preliminaries): vertices of equal
+ * degree are ordered by hash(v).  Survey results do not depend on it. */
+#define TP_TIE_MIX 0u /* a bijective integer mix of the vertex id (default) */
+#define TP_TIE_ID 1u  /* the vertex id itself */
+
+/*
+ * A raw undirected edge list (Preliminaries: the input graph is undirected;
+ * Datasets subsection: a multigraph keeps the chronologically first edge).
+ * Edges may repeat, in either direction; self-loops are allowed and ignored.
+ * Each unordered pair {u,v} becomes one edge whose time is the minimum over
+ * all of its copies.
+ *   n_vertices    ids are in [0, n_vertices); n_vertices < 2^32 - 1
+ *   n_edges       number of raw edges (uint64)
+ *   src, dst      uint32[n_edges]
+ *   edge_time     uint32[n_edges], or NULL: every time is 0 (the paper's
+ *                 dummy metadata for plain counting, Triangle Counting
+ *                 subsection of the evaluation)
+ *   vertex_label  uint8[n_vertices], or NULL: every label is 0
+ *   mem_space     TP_MEM_HOST or TP_MEM_DEVICE, for all four arrays
+ *   tie_hash      TP_TIE_MIX or TP_TIE_ID
+ */
+typedef struct {
+    uint32_t n_vertices;
+    uint32_t mem_space;
+    uint64_t n_edges;
+    const uint32_t *src;
+    const uint32_t *dst;
+    const uint32_t *edge_time;
+    const uint8_t *vertex_label;
+    uint32_t tie_hash;
+    uint32_t reserved;
+} tp_edge_list;
+
+typedef struct tp_graph tp_graph;
+
+/* Graph statistics.  Degrees are of the cleaned simple graph; d+ is the
+ * out-degree in the degree-ordered directed graph; wedges = |W+| = sum over
+ * v of C(d+(v), 2), the wedge checks of the survey (Preliminaries). */
+typedef struct {
+    uint64_t n_vertices;
+    uint64_t n_raw_edges;
+    uint64_t n_self_loops;
+    uint64_t n_edges;          /* unique undirected edges m */
+    uint64_t d_max;
+    uint64_t dplus_max;
+    uint64_t wedges;           /* |W+| */
+    uint64_t probes;           /* wedge checks the survey issues (|W+| minus wedges whose
+                                  middle vertex has no out-edge, which cannot close) */
+    uint64_t n_targets;        /* vertices q with at least one wedge to check */
+    uint64_t n_tiles;          /* work tiles of the survey plan */
+    uint64_t device_bytes;     /* HBM held by the graph */
+    uint32_t max_label;
+    uint32_t reserved;
+    float phase_ms[8];         /* device time of the build phases: 0 validate+canonicalise,
+                                  1 sort by pair, 2 dedup, 3 degree+order, 4 orient+sort,
+                                  5 CSR+metadata, 6 in-edge index, 7 survey plan */
+    float build_ms;            /* sum of phase_ms */
+} tp_graph_stats;
+
+/*
+ * Build the degree-ordered directed graph with co-located metadata
+ * (Preliminaries; Graph Storage subsection, Adj+^m(u) with meta(u,v) and
+ * meta(v) stored beside each out-neighbour v).  Synchronous.
+ *   edges   the raw edge list (see tp_edge_list); borrowed
+ *   stream  hipStream_t as void*
+ *   out     receives a new graph on TP_OK
+ * Errors: TP_ERR_INVALID for NULL pointers with n_edges > 0, an id >= n, or
+ * n_vertices >= 2^32 - 1; TP_ERR_OOM; TP_ERR_DEVICE.
+ */
+tp_status tripoll_build(const tp_edge_list *edges, void *stream, tp_graph **out);
+
+/* Statistics of a built graph (host struct, filled synchronously). */
+tp_status tripoll_graph_stats(const tp_graph *g, tp_graph_stats *out);
+
+/* Release a graph and its device memory.  NULL is accepted. */
+tp_status tripoll_graph_free(tp_graph *g);
+
+/*
+ * Copy the oriented graph to host arrays, for inspection and tests.  Any
+ * pointer may be NULL to skip that array.  Vertices are numbered by their
+ * position in the degree order (rank); row v of the CSR lists the
+ * out-neighbours of rank v in increasing rank.
+ *   rowptr   uint64[n+1]    col  uint32[m]  (ranks)
+ *   etime    uint32[m]      time of each oriented edge
+ *   tlabel   uint8[m]       label of each edge's target
+ *   rank_to_id uint32[n]    original id of each rank
+ *   rank_label uint8[n]     label of each rank
+ */
+tp_status tripoll_graph_export(const tp_graph *g, uint64_t *rowptr, uint32_t *col, uint32_t *etime,
+                               uint8_t *tlabel, uint32_t *rank_to_id, uint8_t *rank_label);
+
+/* ------------------------------------------------------------------------ */
+/* Survey                                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Reductions (the callback of Algorithm 1), selected as a bitmask.  For each
+ * triangle with edge times t1 <= t2 <= t3 and vertex labels a <= b <= c:
+ *   COUNT        triangles += 1                         (Algorithm 2)
+ *   CLOSE_HIST   close_hist[bin(t3 - t1)] += 1           (Algorithm 4, closing time)
+ *   LABEL_TABLE  label_table[C(c+2,3)+C(b+1,2)+a] += 1   (label-multiset survey)
+ *   SPREAD_COUNT spread_count += (t3 - t1 < spread_lt)
+ *   OPEN_CLOSE   open_close[32*bin(t2 - t1) + bin(t3 - t1)] += 1 (Algorithm 4, joint)
+ * with bin(D) = 0 for D <= 1 and min(31, ceil(log2 D)) otherwise, computed
+ * exactly in integers.  The triangle count is always produced. */
+#define TP_OUT_COUNT 0x01u
+#define TP_OUT_CLOSE_HIST 0x02u
+#define TP_OUT_LABEL_TABLE 0x04u
+#define TP_OUT_SPREAD_COUNT 0x08u
+#define TP_OUT_OPEN_CLOSE 0x10u
+
+/* Prefilters applied before every reduction (the conditional of the
+ * callbacks in Algorithms 3 and 4):
+ *   WINDOW      keep triangles whose three edge times all lie in [t_lo, t_hi]
+ *   LABEL_MASK  keep triangles whose label-multiset index has its bit set */
+#define TP_FILT_WINDOW 0x01u
+#define TP_FILT_LABEL_MASK 0x02u
+
+#define TP_MAX_LABELS 16u
+#define TP_TABLE_MAX 816u /* C(16+2, 3) */
+
+/* Intersection strategy (tests and tuning).  AUTO picks per target vertex. */
+#define TP_STRAT_AUTO 0u
+#define TP_STRAT_GLOBAL_SEARCH 1u /* binary search of Adj+(q) in HBM for every target */
+
+typedef struct {
+    uint32_t outputs;        /* TP_OUT_* bitmask */
+    uint32_t filters;        /* TP_FILT_* bitmask */
+    uint32_t n_labels;       /* L in 1..16, labels must be < L when LABEL_TABLE or
+                                LABEL_MASK is used; the table has C(L+2,3) entries */
+    uint32_t strategy;       /* TP_STRAT_* */
+    uint64_t spread_lt;      /* SPREAD_COUNT threshold */
+    uint64_t t_lo, t_hi;     /* WINDOW bounds, closed; t_lo <= t_hi */
+    uint64_t label_mask[13]; /* LABEL_MASK bitset over multiset indices */
+} tp_survey_spec;
+
+/* Host result.  Unrequested outputs are zero. */
+typedef struct {
+    uint64_t triangles;      /* triangles passing the filters */
+    uint64_t spread_count;
+    uint64_t probes;         /* wedge checks performed */
+    uint64_t close_hist[32];
+    uint64_t label_table[TP_TABLE_MAX];
+    uint64_t open_close[32 * 32];
+    float kernel_ms;         /* device time of the intersection kernels */
+    float total_ms;          /* device time of the whole survey call */
+} tp_survey_result;
+
+/* Word layout of a device result buffer (uint64[TP_RESULT_WORDS]).  The
+ * last TP_RW_SCRATCH_WORDS words are work counters used by the survey
+ * itself; their content is unspecified. */
+#define TP_RW_TRIANGLES 0u
+#define TP_RW_SPREAD 1u
+#define TP_RW_PROBES 2u
+#define TP_RW_HIST 3u
+#define TP_RW_TABLE (TP_RW_HIST + 32u)
+#define TP_RW_OPEN_CLOSE (TP_RW_TABLE + TP_TABLE_MAX)
+#define TP_RW_SCRATCH (TP_RW_OPEN_CLOSE + 1024u)
+#define TP_RW_SCRATCH_WORDS 4u
+#define TP_RESULT_WORDS (TP_RW_SCRATCH + TP_RW_SCRATCH_WORDS)
+
+/*
+ * Survey a graph (Algorithm 1 with the reductions above).  Synchronous: the
+ * result is on the host when it returns.
+ * Errors: TP_ERR_INVALID for NULL arguments, n_labels outside 1..16, a graph
+ * label >= n_labels when labels are used, or t_lo > t_hi; TP_ERR_DEVICE.
+ */
+tp_status tripoll_survey(const tp_graph *g, const tp_survey_spec *spec, tp_survey_result *out,
+                         void *stream);
+
+/*
+ * As tripoll_survey, but enqueued on `stream` without waiting and without
+ * allocating.  `dev_out` is a device buffer of TP_RESULT_WORDS uint64 owned by
+ * the caller; it is overwritten (zeroed, then accumulated) by work ordered on
+ * `stream`, and must not be shared by surveys in flight at the same time.
+ */
+tp_status tripoll_survey_async(const tp_graph *g, const tp_survey_spec *spec, uint64_t *dev_out,
+                               void *stream);
+
+/*
+ * Enumerate every triangle (the full-enumeration use of the callback,
+ * Introduction).  Writes up to `capacity` records of 9 uint32 each into the
+ * device buffer `dev_records`: original ids a, b, c (the triangle's pivot,
+ * middle and top vertex in the degree order), the times of edges ab, ac, bc,
+ * and the labels of a, b, c.  *n_found receives the number of triangles,
+ * which may exceed capacity (then only `capacity` records were written).
+ * Synchronous.
+ */
+tp_status tripoll_enumerate(const tp_graph *g, uint32_t *dev_records, uint64_t capacity,
+                            uint64_t *n_found, void *stream);
+
+/* Colex index of the label multiset {a, b, c} (any order). */
+uint32_t tripoll_msidx(uint32_t a, uint32_t b, uint32_t c);
+
+/* Return the device memory cached by the library's allocator to the driver
+ * (blocks kept after graphs and temporaries were released). */
+tp_status tripoll_trim(void);
+
+/* Bytes currently cached by the allocator on the current device. */
+tp_status tripoll_cached_bytes(uint64_t *out);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *tripoll_last_error(void);
+
+/* Library version string. */
+const char *tripoll_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRIPOLL_H */

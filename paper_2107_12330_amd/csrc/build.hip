@@ -1,0 +1,580 @@
+// build.hip -- graph builder: raw edge list -> degree-ordered directed graph
+// with co-located metadata, its in-edge index and the survey's tile plan.
+//
+// Phases (all device-resident after the upload):
+//   0 canonicalise: (u,v,t) -> key (min<<b | max), self-loops to a sentinel
+//   1 radix sort of (key, t)
+//   2 dedup: one edge per pair with the minimum time (the chronologically
+//     first copy, Datasets subsection)
+//   3 degree d(v) of the simple graph, then the order <+ (Preliminaries):
+//     sort of (d(v), hash(v)) gives every vertex its rank
+//   4 orient each edge from the lower to the higher rank and sort by
+//     (source rank, target rank): rows ascend in the order <+
+//   5 CSR with the time of each edge and the label of its target stored
+//     beside it (Adj+^m of the Graph Storage subsection)
+//   6 in-edge index: for every target q the list of (p, slot of q in p's row)
+//     whose remaining row is non-empty -- the work the survey streams
+//   7 plan: split each target's list into tiles and class targets by d+(q)
+#include <algorithm>
+#include <memory>
+
+#include "graph.hpp"
+#include "plan.hpp"
+
+using namespace tp;
+
+namespace {
+
+constexpr int kB = 256;
+
+__device__ __forceinline__ uint64_t pair_key(uint32_t lo, uint32_t hi, int nb)
+{
+    return ((uint64_t)lo << nb) | hi;
+}
+
+// ------------------------------------------------------------ phase 0
+
+__global__ void k_canon(const uint32_t *src, const uint32_t *dst, const uint32_t *ts, size_t M, uint32_t n,
+                        int nb, uint64_t sentinel, uint64_t *keys, uint32_t *vals, unsigned long long *bad,
+                        unsigned long long *loops)
+{
+    unsigned long long nbad = 0, nloop = 0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < M; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t a = src[i], b = dst[i];
+        const bool ok = a < n && b < n;
+        nbad += ok ? 0 : 1;
+        uint64_t k;
+        if (!ok || a == b) {
+            k = sentinel;
+            nloop += (ok && a == b) ? 1 : 0;
+        } else {
+            k = a < b ? pair_key(a, b, nb) : pair_key(b, a, nb);
+        }
+        keys[i] = k;
+        vals[i] = ts ? ts[i] : 0u;
+    }
+    nbad = wave_sum(nbad);
+    nloop = wave_sum(nloop);
+    if (lane_id() == 0) {
+        if (nbad) atomicAdd(bad, nbad);
+        if (nloop) atomicAdd(loops, nloop);
+    }
+}
+
+// ------------------------------------------------------------ phase 2
+
+constexpr int kCompItems = 16;
+constexpr size_t kCompTile = (size_t)kB * kCompItems;
+
+__device__ __forceinline__ bool is_head(const uint64_t *keys, size_t i)
+{
+    return i == 0 || keys[i] != keys[i - 1];
+}
+
+__global__ __launch_bounds__(kB) void k_dedup_count(const uint64_t *keys, size_t n, uint64_t *tile_cnt)
+{
+    __shared__ uint64_t tmp[kB / kWave];
+    const size_t base = blockIdx.x * kCompTile + (size_t)threadIdx.x * kCompItems;
+    uint64_t c = 0;
+    for (int j = 0; j < kCompItems; ++j) {
+        const size_t i = base + j;
+        if (i < n && is_head(keys, i)) ++c;
+    }
+    uint64_t tot;
+    (void)block_excl_scan<kB>(c, tmp, tot);
+    if (threadIdx.x == 0) tile_cnt[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kB) void k_dedup_write(const uint64_t *keys, const uint32_t *vals, size_t n,
+                                                    const uint64_t *tile_off, uint64_t *ukey, uint32_t *uts)
+{
+    __shared__ uint64_t tmp[kB / kWave];
+    const size_t base = blockIdx.x * kCompTile + (size_t)threadIdx.x * kCompItems;
+    uint64_t c = 0;
+    for (int j = 0; j < kCompItems; ++j) {
+        const size_t i = base + j;
+        if (i < n && is_head(keys, i)) ++c;
+    }
+    uint64_t tot;
+    uint64_t pos = tile_off[blockIdx.x] + block_excl_scan<kB>(c, tmp, tot);
+    for (int j = 0; j < kCompItems; ++j) {
+        const size_t i = base + j;
+        if (i < n && is_head(keys, i)) {
+            const uint64_t k = keys[i];
+            uint32_t t = vals[i];
+            for (size_t x = i + 1; x < n && keys[x] == k; ++x) t = min(t, vals[x]);
+            ukey[pos] = k;
+            uts[pos] = t;
+            ++pos;
+        }
+    }
+}
+
+// ------------------------------------------------------------ phase 3
+
+__global__ void k_degree(const uint64_t *ukey, size_t m, int nb, uint32_t *deg)
+{
+    const uint64_t mask = (1ull << nb) - 1;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
+        const uint64_t k = ukey[i];
+        atomicAdd(&deg[k >> nb], 1u);
+        atomicAdd(&deg[k & mask], 1u);
+    }
+}
+
+template <class T>
+__global__ void k_max(const T *x, size_t n, unsigned long long *out)
+{
+    unsigned long long mx = 0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        mx = max(mx, (unsigned long long)x[i]);
+    mx = wave_max(mx);
+    if (lane_id() == 0 && mx) atomicMax(out, mx);
+}
+
+// A bijection of [0, 2^nb): xor-shifts and odd multiplications modulo 2^nb.
+__device__ __forceinline__ uint32_t tie_mix(uint32_t x, int nb)
+{
+    const uint64_t mask = (nb >= 32) ? 0xffffffffull : ((1ull << nb) - 1);
+    const int s = (nb + 1) / 2;
+    uint64_t y = x;
+    y ^= y >> s;
+    y = (y * 0x9e3779b1ull) & mask;
+    y ^= y >> s;
+    y = (y * 0x85ebca6bull) & mask;
+    y ^= y >> s;
+    return (uint32_t)y;
+}
+
+__global__ void k_rank_keys(const uint32_t *deg, uint32_t n, int nb, uint32_t tie, uint64_t *rkey, uint32_t *rval)
+{
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t h = tie == TP_TIE_ID ? (uint32_t)v : tie_mix((uint32_t)v, nb);
+        rkey[v] = ((uint64_t)deg[v] << nb) | h;
+        rval[v] = (uint32_t)v;
+    }
+}
+
+__global__ void k_rank_scatter(const uint32_t *perm, uint32_t n, const uint8_t *vlab, uint32_t *rank, uint8_t *rlab)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t v = perm[i];
+        rank[v] = (uint32_t)i;
+        rlab[i] = vlab ? vlab[v] : 0;
+    }
+}
+
+// ------------------------------------------------------------ phase 4
+
+__global__ void k_orient(const uint64_t *ukey, const uint32_t *uts, size_t m, int nb, const uint32_t *rank,
+                         uint64_t *okey, uint32_t *ots, uint32_t *dplus)
+{
+    const uint64_t mask = (1ull << nb) - 1;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
+        const uint64_t k = ukey[i];
+        const uint32_t a = rank[k >> nb], b = rank[k & mask];
+        const uint32_t s = min(a, b), t = max(a, b);
+        okey[i] = pair_key(s, t, nb);
+        ots[i] = uts[i];
+        atomicAdd(&dplus[s], 1u);
+    }
+}
+
+// ------------------------------------------------------------ phase 5
+
+__global__ void k_csr(const uint64_t *okey, size_t m, int nb, const uint8_t *rlab, uint32_t *col, uint8_t *tlab,
+                      uint32_t *srow)
+{
+    const uint64_t mask = (1ull << nb) - 1;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
+        const uint64_t k = okey[i];
+        const uint32_t t = (uint32_t)(k & mask);
+        col[i] = t;
+        tlab[i] = rlab[t];
+        srow[i] = (uint32_t)(k >> nb);
+    }
+}
+
+__global__ void k_row_stats(const uint64_t *rowptr, uint32_t n, unsigned long long *wedges,
+                            unsigned long long *dplus_max)
+{
+    unsigned long long w = 0, mx = 0;
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
+        const uint64_t d = rowptr[v + 1] - rowptr[v];
+        w += d ? d * (d - 1) / 2 : 0;
+        mx = max(mx, (unsigned long long)d);
+    }
+    w = wave_sum(w);
+    mx = wave_max(mx);
+    if (lane_id() == 0) {
+        if (w) atomicAdd(wedges, w);
+        if (mx) atomicMax(dplus_max, mx);
+    }
+}
+
+// ------------------------------------------------------------ phase 6
+
+// The wedges (p, q, r) of the oriented edge p -> q at slot k are the slots
+// after k in p's row; they can close only if q has out-neighbours.
+__device__ __forceinline__ uint32_t rest_len(const uint64_t *rowptr, uint32_t s, size_t k)
+{
+    return (uint32_t)(rowptr[s + 1] - k - 1);
+}
+
+__global__ void k_in_count(const uint32_t *srow, const uint32_t *col, const uint64_t *rowptr, size_t m,
+                           uint32_t *incnt, unsigned long long *work)
+{
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < m; k += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t s = srow[k], t = col[k];
+        const uint32_t len = rest_len(rowptr, s, k);
+        if (len > 0 && rowptr[t + 1] > rowptr[t]) {
+            atomicAdd(&incnt[t], 1u);
+            atomicAdd(&work[t], (unsigned long long)len);
+        }
+    }
+}
+
+__global__ void k_in_scatter(const uint32_t *srow, const uint32_t *col, const uint32_t *ets, const uint64_t *rowptr,
+                             const uint8_t *rlab, size_t m, const uint64_t *cptr, uint32_t *cursor, InRec *rec)
+{
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < m; k += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t s = srow[k], t = col[k];
+        const uint32_t len = rest_len(rowptr, s, k);
+        if (len > 0 && rowptr[t + 1] > rowptr[t]) {
+            const uint64_t at = cptr[t] + atomicAdd(&cursor[t], 1u);
+            InRec r;
+            r.k_lo = (uint32_t)k;
+            r.k_hi_lab = (uint32_t)((k >> 32) & 0xffffffu) | ((uint32_t)rlab[s] << 24);
+            r.len = len;
+            r.t_pq = ets[k];
+            rec[at] = r;
+        }
+    }
+}
+
+// ------------------------------------------------------------ phase 7
+
+__device__ __forceinline__ int class_of(uint64_t dq)
+{
+    return dq <= kSmallMaxDeg ? kClassSmall : (dq <= kLargeMaxDeg ? kClassLarge : kClassHuge);
+}
+
+__device__ __forceinline__ uint32_t tiles_of(uint64_t cnt, uint64_t work)
+{
+    if (cnt == 0) return 0;
+    const uint64_t a = (cnt + kTileRecords - 1) / kTileRecords;
+    const uint64_t b = (work + kTileWork - 1) / kTileWork;
+    uint64_t t = a > b ? a : b;
+    if (t > cnt) t = cnt;
+    return (uint32_t)t;
+}
+
+__global__ void k_plan_count(const uint64_t *cptr, const unsigned long long *work, const uint64_t *rowptr,
+                             uint32_t n, uint32_t *tcnt /* [3][n] */)
+{
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+        const uint64_t cnt = cptr[q + 1] - cptr[q];
+        const int c = class_of(rowptr[q + 1] - rowptr[q]);
+        const uint32_t t = tiles_of(cnt, work[q]);
+        for (int i = 0; i < kNumClasses; ++i) tcnt[(size_t)i * n + q] = (i == c) ? t : 0u;
+    }
+}
+
+__global__ void k_plan_write(const uint64_t *cptr, const uint64_t *tile_off, const uint32_t *tcnt, uint32_t n,
+                             TileDesc *tiles)
+{
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t t = tcnt[q];
+        if (!t) continue;
+        const uint64_t c0 = cptr[q], cnt = cptr[q + 1] - c0;
+        const uint64_t base = tile_off[q];
+        for (uint32_t j = 0; j < t; ++j) {
+            const uint64_t a = c0 + cnt * j / t, b = c0 + cnt * (j + 1) / t;
+            TileDesc d;
+            d.q = (uint32_t)q;
+            d.cnt = (uint32_t)(b - a);
+            d.e0 = a;
+            tiles[base + j] = d;
+        }
+    }
+}
+
+__global__ void k_work_stats(const unsigned long long *work, uint32_t n, unsigned long long *sum,
+                             unsigned long long *nonzero)
+{
+    unsigned long long w = 0, c = 0;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+        w += work[q];
+        c += work[q] ? 1 : 0;
+    }
+    w = wave_sum(w);
+    c = wave_sum(c);
+    if (lane_id() == 0) {
+        if (w) atomicAdd(sum, w);
+        if (c) atomicAdd(nonzero, c);
+    }
+}
+
+template <class T>
+T read_scalar(const T *dev, hipStream_t s)
+{
+    T v;
+    TP_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+template <class T>
+const T *to_device(const T *p, size_t n, uint32_t space, DArray<T> &hold, hipStream_t s)
+{
+    if (!p || space == TP_MEM_DEVICE) return p;
+    hold.reset(n, s);
+    if (n) TP_HIP(hipMemcpyAsync(hold.get(), p, n * sizeof(T), hipMemcpyHostToDevice, s));
+    return hold.get();
+}
+
+}  // namespace
+
+// ================================================================ build
+
+static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out)
+{
+    if (!el || !out) fail(TP_ERR_INVALID, "tripoll_build: NULL argument");
+    if (el->mem_space != TP_MEM_HOST && el->mem_space != TP_MEM_DEVICE)
+        fail(TP_ERR_INVALID, "tripoll_build: mem_space must be TP_MEM_HOST or TP_MEM_DEVICE");
+    if (el->tie_hash != TP_TIE_MIX && el->tie_hash != TP_TIE_ID)
+        fail(TP_ERR_INVALID, "tripoll_build: unknown tie_hash");
+    if (el->n_vertices == 0 || el->n_vertices >= 0xffffffffu)
+        fail(TP_ERR_INVALID, "tripoll_build: n_vertices must be in [1, 2^32-1)");
+    if (el->n_edges > 0 && (!el->src || !el->dst)) fail(TP_ERR_INVALID, "tripoll_build: NULL src/dst");
+
+    const uint32_t n = el->n_vertices;
+    const size_t M = el->n_edges;
+    const int nb = std::max(1, bits_for((uint64_t)n - 1));
+    const uint64_t sentinel = (2 * nb >= 64) ? ~0ull : ((1ull << (2 * nb)) - 1);
+
+    auto g = std::make_unique<tp_graph>();
+    TP_HIP(hipGetDevice(&g->device));
+    g->n = n;
+    g->nbits = (uint32_t)nb;
+
+    hipEvent_t ev[9];
+    for (auto &e : ev) TP_HIP(hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() { for (int i = 0; i < 9; ++i) (void)hipEventDestroy(e[i]); }
+    } evg{ev};
+    TP_HIP(hipEventRecord(ev[0], s));
+
+    // ---- phase 0: upload and canonicalise
+    DArray<uint32_t> h_src, h_dst, h_ts;
+    DArray<uint8_t> h_lab;
+    const uint32_t *src = to_device(el->src, M, el->mem_space, h_src, s);
+    const uint32_t *dst = to_device(el->dst, M, el->mem_space, h_dst, s);
+    const uint32_t *ts = to_device(el->edge_time, M, el->mem_space, h_ts, s);
+    const uint8_t *vlab = to_device(el->vertex_label, n, el->mem_space, h_lab, s);
+
+    // bad ids, self-loops, d_max, max label, wedges, d+_max, probes, active targets
+    DArray<unsigned long long> counters(8, s);
+    TP_HIP(hipMemsetAsync(counters.get(), 0, 8 * sizeof(unsigned long long), s));
+    unsigned long long *c_bad = counters.get(), *c_loop = c_bad + 1, *c_dmax = c_bad + 2, *c_lab = c_bad + 3,
+                       *c_wedge = c_bad + 4, *c_dpmax = c_bad + 5;
+
+    const size_t Mcap = std::max<size_t>(M, 1);
+    DArray<uint64_t> keyA(Mcap, s), keyB(Mcap, s);
+    DArray<uint32_t> valA(Mcap, s), valB(Mcap, s);
+    if (M) {
+        k_canon<<<grid_for(M, kB), kB, 0, s>>>(src, dst, ts, M, n, nb, sentinel, keyA.get(), valA.get(), c_bad,
+                                               c_loop);
+        TP_CHECK_LAUNCH();
+    }
+    unsigned long long hc[2];
+    TP_HIP(hipMemcpyAsync(hc, counters.get(), 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    if (hc[0]) fail(TP_ERR_INVALID, "tripoll_build: " + std::to_string(hc[0]) + " edge endpoints >= n_vertices");
+    h_src.release();
+    h_dst.release();
+    h_ts.release();
+    const size_t Mv = M - (size_t)hc[1];  // edges that are not self-loops
+    g->stats.n_raw_edges = M;
+    g->stats.n_self_loops = hc[1];
+    TP_HIP(hipEventRecord(ev[1], s));
+
+    // ---- phase 1: sort by pair
+    const bool sorted_in_b = radix_sort_pairs(keyA.get(), valA.get(), keyB.get(), valB.get(), M, 2 * nb, s);
+    uint64_t *skey = sorted_in_b ? keyB.get() : keyA.get();
+    uint32_t *sval = sorted_in_b ? valB.get() : valA.get();
+    uint64_t *fkey = sorted_in_b ? keyA.get() : keyB.get();  // free buffers
+    uint32_t *fval = sorted_in_b ? valA.get() : valB.get();
+    TP_HIP(hipEventRecord(ev[2], s));
+
+    // ---- phase 2: dedup keeping the earliest time
+    uint64_t m = 0;
+    {
+        const size_t nt = std::max<size_t>(1, (Mv + kCompTile - 1) / kCompTile);
+        DArray<uint64_t> toff(nt + 1, s);
+        if (Mv) {
+            k_dedup_count<<<(unsigned)nt, kB, 0, s>>>(skey, Mv, toff.get());
+            TP_CHECK_LAUNCH();
+        } else {
+            TP_HIP(hipMemsetAsync(toff.get(), 0, sizeof(uint64_t), s));
+        }
+        scan_u64(toff.get(), toff.get(), nt, true, s);
+        m = read_scalar(toff.get() + nt, s);
+        if (Mv) {
+            k_dedup_write<<<(unsigned)nt, kB, 0, s>>>(skey, sval, Mv, toff.get(), fkey, fval);
+            TP_CHECK_LAUNCH();
+        }
+    }
+    uint64_t *ukey = fkey;
+    uint32_t *uts = fval;
+    g->m = m;
+    g->stats.n_edges = m;
+    TP_HIP(hipEventRecord(ev[3], s));
+
+    // ---- phase 3: degree and the order <+
+    DArray<uint32_t> rank(n, s);
+    {
+        DArray<uint32_t> deg(n, s);
+        TP_HIP(hipMemsetAsync(deg.get(), 0, n * sizeof(uint32_t), s));
+        if (m) {
+            k_degree<<<grid_for(m, kB), kB, 0, s>>>(ukey, m, nb, deg.get());
+            TP_CHECK_LAUNCH();
+        }
+        k_max<uint32_t><<<grid_for(n, kB), kB, 0, s>>>(deg.get(), n, c_dmax);
+        TP_CHECK_LAUNCH();
+        if (vlab) {
+            k_max<uint8_t><<<grid_for(n, kB), kB, 0, s>>>(vlab, n, c_lab);
+            TP_CHECK_LAUNCH();
+        }
+        unsigned long long mx[2];
+        TP_HIP(hipMemcpyAsync(mx, c_dmax, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+        g->stats.d_max = mx[0];
+        g->stats.max_label = (uint32_t)mx[1];
+        // sort keys (d(v), hash(v)) with the vertex as value
+        DArray<uint64_t> rkeyA(n, s), rkeyB(n, s);
+        DArray<uint32_t> rvalA(n, s), rvalB(n, s);
+        k_rank_keys<<<grid_for(n, kB), kB, 0, s>>>(deg.get(), n, nb, el->tie_hash, rkeyA.get(), rvalA.get());
+        TP_CHECK_LAUNCH();
+        const int rbits = nb + bits_for(mx[0]);
+        const bool rb = radix_sort_pairs(rkeyA.get(), rvalA.get(), rkeyB.get(), rvalB.get(), n, rbits, s);
+        g->perm = rb ? std::move(rvalB) : std::move(rvalA);
+        g->rlab.reset(n, s);
+        k_rank_scatter<<<grid_for(n, kB), kB, 0, s>>>(g->perm.get(), n, vlab, rank.get(), g->rlab.get());
+        TP_CHECK_LAUNCH();
+    }
+    h_lab.release();
+    TP_HIP(hipEventRecord(ev[4], s));
+
+    // ---- phase 4: orient and sort by (source rank, target rank)
+    DArray<uint32_t> dplus(n, s);
+    TP_HIP(hipMemsetAsync(dplus.get(), 0, n * sizeof(uint32_t), s));
+    if (m) {
+        k_orient<<<grid_for(m, kB), kB, 0, s>>>(ukey, uts, m, nb, rank.get(), skey, sval, dplus.get());
+        TP_CHECK_LAUNCH();
+    }
+    rank.release();
+    const bool ob = radix_sort_pairs(skey, sval, ukey, uts, m, 2 * nb, s);
+    uint64_t *okey = ob ? ukey : skey;
+    uint32_t *ots = ob ? uts : sval;
+    uint32_t *spare_val = ob ? sval : uts;
+    TP_HIP(hipEventRecord(ev[5], s));
+
+    // ---- phase 5: CSR with co-located metadata
+    g->rowptr.reset((size_t)n + 1, s);
+    scan_u32_to_u64(dplus.get(), g->rowptr.get(), n, s);
+    dplus.release();
+    g->col.reset(std::max<uint64_t>(m, 1), s);
+    g->tlab.reset(std::max<uint64_t>(m, 1), s);
+    g->ets.reset(std::max<uint64_t>(m, 1), s);
+    uint32_t *srow = spare_val;
+    if (m) {
+        k_csr<<<grid_for(m, kB), kB, 0, s>>>(okey, m, nb, g->rlab.get(), g->col.get(), g->tlab.get(), srow);
+        TP_CHECK_LAUNCH();
+        TP_HIP(hipMemcpyAsync(g->ets.get(), ots, m * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    }
+    k_row_stats<<<grid_for(n, kB), kB, 0, s>>>(g->rowptr.get(), n, c_wedge, c_dpmax);
+    TP_CHECK_LAUNCH();
+    // the key buffers are no longer needed; srow lives in one value buffer
+    keyA.release();
+    keyB.release();
+    TP_HIP(hipEventRecord(ev[6], s));
+
+    // ---- phase 6: in-edge index
+    DArray<unsigned long long> work(n, s);
+    DArray<uint64_t> cptr((size_t)n + 1, s);
+    {
+        DArray<uint32_t> incnt(n, s);
+        TP_HIP(hipMemsetAsync(incnt.get(), 0, n * sizeof(uint32_t), s));
+        TP_HIP(hipMemsetAsync(work.get(), 0, n * sizeof(unsigned long long), s));
+        if (m) {
+            k_in_count<<<grid_for(m, kB), kB, 0, s>>>(srow, g->col.get(), g->rowptr.get(), m, incnt.get(),
+                                                      work.get());
+            TP_CHECK_LAUNCH();
+        }
+        scan_u32_to_u64(incnt.get(), cptr.get(), n, s);
+        g->n_in = read_scalar(cptr.get() + n, s);
+        g->inrec.reset(std::max<uint64_t>(g->n_in, 1), s);
+        TP_HIP(hipMemsetAsync(incnt.get(), 0, n * sizeof(uint32_t), s));
+        if (m) {
+            k_in_scatter<<<grid_for(m, kB), kB, 0, s>>>(srow, g->col.get(), g->ets.get(), g->rowptr.get(),
+                                                        g->rlab.get(), m, cptr.get(), incnt.get(),
+                                                        g->inrec.get());
+            TP_CHECK_LAUNCH();
+        }
+    }
+    valA.release();
+    valB.release();
+    TP_HIP(hipEventRecord(ev[7], s));
+
+    // ---- phase 7: tile plan per class
+    {
+        DArray<uint32_t> tcnt((size_t)kNumClasses * n, s);
+        k_plan_count<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), work.get(), g->rowptr.get(), n, tcnt.get());
+        TP_CHECK_LAUNCH();
+        for (int c = 0; c < kNumClasses; ++c) {
+            DArray<uint64_t> toff((size_t)n + 1, s);
+            scan_u32_to_u64(tcnt.get() + (size_t)c * n, toff.get(), n, s);
+            const uint64_t nt = read_scalar(toff.get() + n, s);
+            g->n_tiles[c] = nt;
+            g->tiles[c].reset(std::max<uint64_t>(nt, 1), s);
+            if (nt) {
+                k_plan_write<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), toff.get(), tcnt.get() + (size_t)c * n, n,
+                                                            g->tiles[c].get());
+                TP_CHECK_LAUNCH();
+            }
+        }
+    }
+    // probes = sum of the work of all targets; active targets = targets with work
+    k_work_stats<<<grid_for(n, kB), kB, 0, s>>>(work.get(), n, c_bad + 6, c_bad + 7);
+    TP_CHECK_LAUNCH();
+    TP_HIP(hipEventRecord(ev[8], s));
+    TP_HIP(hipStreamSynchronize(s));
+
+    unsigned long long hs[8];
+    TP_HIP(hipMemcpy(hs, counters.get(), 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    g->stats.n_vertices = n;
+    g->stats.wedges = hs[4];
+    g->stats.dplus_max = hs[5];
+    g->stats.probes = hs[6];
+    g->stats.n_targets = hs[7];
+    g->stats.n_tiles = g->n_tiles[0] + g->n_tiles[1] + g->n_tiles[2];
+    float total = 0.f;
+    for (int i = 0; i < 8; ++i) {
+        float t = 0.f;
+        TP_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+        g->stats.phase_ms[i] = t;
+        total += t;
+    }
+    g->stats.build_ms = total;
+    g->stats.device_bytes = g->rowptr.bytes() + g->col.bytes() + g->ets.bytes() + g->tlab.bytes() +
+                            g->rlab.bytes() + g->perm.bytes() + g->inrec.bytes() + g->tiles[0].bytes() +
+                            g->tiles[1].bytes() + g->tiles[2].bytes();
+    *out = g.release();
+}
+
+extern "C" tp_status tripoll_build(const tp_edge_list *edges, void *stream, tp_graph **out)
+{
+    return guard([&] { build_impl(edges, (hipStream_t)stream, out); });
+}

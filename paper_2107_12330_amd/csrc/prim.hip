@@ -1,0 +1,388 @@
+// prim.hip -- library runtime pieces and device primitives for gfx950:
+// per-thread error state, the caching device allocator, exclusive scans and
+// a stable LSD radix sort of (uint64 key, uint32 value) pairs.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+
+#include "tp_internal.hpp"
+
+namespace tp {
+
+// ================================================================ errors
+
+static thread_local std::string g_last_error;
+
+void fail(tp_status st, const std::string &msg) { throw Error{st, msg}; }
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+void clear_last_error() { g_last_error.clear(); }
+const char *last_error_cstr() { return g_last_error.c_str(); }
+
+// ================================================================ allocator
+
+namespace {
+
+struct Pool {
+    std::mutex mu;
+    std::multimap<size_t, void *> free_blocks;        // size -> block
+    std::unordered_map<void *, size_t> live;          // block -> size
+    size_t cached = 0;
+};
+
+Pool &pool_for_current_device()
+{
+    static std::mutex m;
+    static std::map<int, Pool *> pools;
+    int dev = 0;
+    TP_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(m);
+    Pool *&p = pools[dev];
+    if (!p) p = new Pool();  // lives until process exit
+    return *p;
+}
+
+size_t round_size(size_t bytes)
+{
+    const size_t small = 512, big = size_t(2) << 20;
+    return bytes < big ? (bytes + small - 1) / small * small : (bytes + big - 1) / big * big;
+}
+
+void trim_locked(Pool &p)
+{
+    for (auto &kv : p.free_blocks) (void)hipFree(kv.second);
+    p.free_blocks.clear();
+    p.cached = 0;
+}
+
+}  // namespace
+
+void *dev_alloc(size_t bytes)
+{
+    Pool &p = pool_for_current_device();
+    const size_t sz = round_size(bytes ? bytes : 1);
+    std::lock_guard<std::mutex> lk(p.mu);
+    auto it = p.free_blocks.lower_bound(sz);
+    // reuse a cached block when it is not much larger than the request
+    if (it != p.free_blocks.end() && it->first <= sz + sz / 4 + (size_t(8) << 20)) {
+        void *ptr = it->second;
+        p.live[ptr] = it->first;
+        p.cached -= it->first;
+        p.free_blocks.erase(it);
+        return ptr;
+    }
+    void *ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, sz);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        trim_locked(p);
+        e = hipMalloc(&ptr, sz);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation ? TP_ERR_OOM : TP_ERR_DEVICE,
+             "device allocation of " + std::to_string(sz) + " bytes failed: " + hipGetErrorString(e));
+    }
+    p.live[ptr] = sz;
+    return ptr;
+}
+
+void dev_release(void *ptr, hipStream_t stream)
+{
+    if (!ptr) return;
+    // the block may still be in use by work on `stream`
+    (void)hipStreamSynchronize(stream);
+    Pool &p = pool_for_current_device();
+    std::lock_guard<std::mutex> lk(p.mu);
+    auto it = p.live.find(ptr);
+    if (it == p.live.end()) return;
+    p.free_blocks.emplace(it->second, ptr);
+    p.cached += it->second;
+    p.live.erase(it);
+}
+
+void dev_trim()
+{
+    Pool &p = pool_for_current_device();
+    std::lock_guard<std::mutex> lk(p.mu);
+    trim_locked(p);
+}
+
+size_t dev_cached_bytes()
+{
+    Pool &p = pool_for_current_device();
+    std::lock_guard<std::mutex> lk(p.mu);
+    return p.cached;
+}
+
+// ================================================================ fill
+
+template <class T>
+__global__ void fill_kernel(T *p, T v, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <class T>
+void fill(T *p, T v, size_t n, hipStream_t s)
+{
+    if (!n) return;
+    fill_kernel<T><<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+    TP_CHECK_LAUNCH();
+}
+template void fill<uint32_t>(uint32_t *, uint32_t, size_t, hipStream_t);
+template void fill<uint64_t>(uint64_t *, uint64_t, size_t, hipStream_t);
+template void fill<uint8_t>(uint8_t *, uint8_t, size_t, hipStream_t);
+
+// ================================================================ scan
+
+namespace {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 16;
+constexpr size_t kScanTile = (size_t)kScanBlock * kScanItems;
+
+template <class Tin>
+__global__ __launch_bounds__(kScanBlock) void scan_reduce_kernel(const Tin *in, uint64_t *partial, size_t n)
+{
+    __shared__ uint64_t tmp[kScanBlock / kWave];
+    const size_t base = blockIdx.x * kScanTile;
+    uint64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const size_t i = base + (size_t)j * kScanBlock + threadIdx.x;
+        if (i < n) s += (uint64_t)in[i];
+    }
+    s = wave_sum(s);
+    if (lane_id() == 0) tmp[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < kScanBlock / kWave; ++w) t += tmp[w];
+        partial[blockIdx.x] = t;
+    }
+}
+
+// Each thread owns kScanItems consecutive elements.
+template <class Tin>
+__global__ __launch_bounds__(kScanBlock) void scan_block_kernel(const Tin *in, uint64_t *out, size_t n,
+                                                                 const uint64_t *partial, uint64_t *total_out)
+{
+    __shared__ uint64_t tmp[kScanBlock / kWave];
+    const size_t base = blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+    uint64_t v[kScanItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const size_t i = base + j;
+        v[j] = i < n ? (uint64_t)in[i] : 0;
+        s += v[j];
+    }
+    uint64_t tot;
+    uint64_t pre = block_excl_scan<kScanBlock>(s, tmp, tot);
+    pre += partial ? partial[blockIdx.x] : 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const size_t i = base + j;
+        if (i < n) out[i] = pre;
+        pre += v[j];
+    }
+    if (total_out && blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanBlock - 1) *total_out = pre;
+}
+
+template <class Tin>
+void scan_impl(const Tin *in, uint64_t *out, size_t n, uint64_t *total_out, hipStream_t s)
+{
+    if (n == 0) {
+        if (total_out) TP_HIP(hipMemsetAsync(total_out, 0, sizeof(uint64_t), s));
+        return;
+    }
+    const size_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 1) {
+        scan_block_kernel<Tin><<<1, kScanBlock, 0, s>>>(in, out, n, nullptr, total_out);
+        TP_CHECK_LAUNCH();
+        return;
+    }
+    DArray<uint64_t> partial(nb, s);
+    scan_reduce_kernel<Tin><<<(unsigned)nb, kScanBlock, 0, s>>>(in, partial.get(), n);
+    TP_CHECK_LAUNCH();
+    scan_impl<uint64_t>(partial.get(), partial.get(), nb, nullptr, s);
+    scan_block_kernel<Tin><<<(unsigned)nb, kScanBlock, 0, s>>>(in, out, n, partial.get(), total_out);
+    TP_CHECK_LAUNCH();
+}
+
+}  // namespace
+
+void scan_u64(const uint64_t *in, uint64_t *out, size_t n, bool with_total, hipStream_t s)
+{
+    scan_impl<uint64_t>(in, out, n, with_total ? out + n : nullptr, s);
+}
+
+void scan_u32_to_u64(const uint32_t *in, uint64_t *out, size_t n, hipStream_t s)
+{
+    scan_impl<uint32_t>(in, out, n, out + n, s);
+}
+
+// ================================================================ radix sort
+//
+// Reduce-then-scan LSD radix sort, 8-bit digits.  A fixed number of blocks
+// each own a contiguous chunk of tiles (4096 keys).  Per pass:
+//   1. upsweep: digit histogram of each block's chunk -> hist[digit][block]
+//   2. exclusive scan of hist (digit-major), giving each (digit, block) its
+//      first output position
+//   3. downsweep: per tile, each wave ranks its quarter of the tile stably
+//      with ballot-based digit matching; the tile is reordered in LDS by
+//      digit and written out in digit runs, so stores are contiguous.
+
+namespace {
+
+constexpr int kSortBlock = 256;
+constexpr int kSortWaves = kSortBlock / kWave;
+constexpr int kSortRounds = 16;                           // keys per lane
+constexpr int kSortTile = kSortBlock * kSortRounds;       // 4096
+constexpr int kRadix = 256;
+constexpr unsigned kMaxSortBlocks = 2048;
+
+__device__ __forceinline__ unsigned digit_of(uint64_t k, int shift) { return (unsigned)(k >> shift) & 0xffu; }
+
+__global__ __launch_bounds__(kSortBlock) void radix_upsweep(const uint64_t *keys, size_t n, int shift,
+                                                            size_t tiles_per_block, uint64_t *hist)
+{
+    __shared__ unsigned cnt[kRadix];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const size_t t0 = blockIdx.x * tiles_per_block;
+    const size_t lo = t0 * kSortTile;
+    const size_t hi = std::min(n, (t0 + tiles_per_block) * kSortTile);
+    for (size_t i = lo + threadIdx.x; i < hi; i += kSortBlock) atomicAdd(&cnt[digit_of(keys[i], shift)], 1u);
+    __syncthreads();
+    hist[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortBlock) void radix_downsweep(const uint64_t *keys_in, const uint32_t *vals_in,
+                                                              uint64_t *keys_out, uint32_t *vals_out, size_t n,
+                                                              int shift, size_t tiles_per_block,
+                                                              const uint64_t *offsets)
+{
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ uint32_t sval[kSortTile];
+    __shared__ unsigned wcnt[kSortWaves][kRadix];  // per-wave running count, then per-wave base
+    __shared__ unsigned tstart[kRadix];
+    __shared__ unsigned tcount[kRadix];
+    __shared__ uint64_t grun[kRadix];              // next output position of each digit
+    __shared__ unsigned scan_tmp[kSortWaves];
+
+    const int w = threadIdx.x / kWave;
+    const unsigned lane = lane_id();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    grun[threadIdx.x] = offsets[(size_t)threadIdx.x * gridDim.x + blockIdx.x];
+    for (int i = 0; i < kSortWaves; ++i) wcnt[i][threadIdx.x] = 0;
+    __syncthreads();
+
+    const size_t t0 = blockIdx.x * tiles_per_block;
+    for (size_t t = t0; t < t0 + tiles_per_block; ++t) {
+        const size_t tile_lo = t * kSortTile;
+        if (tile_lo >= n) break;
+        const size_t wave_lo = tile_lo + (size_t)w * (kSortTile / kSortWaves);
+
+        uint64_t k[kSortRounds];
+        uint32_t v[kSortRounds];
+        unsigned rnk[kSortRounds];
+        unsigned dg[kSortRounds];
+        bool ok[kSortRounds];
+#pragma unroll
+        for (int r = 0; r < kSortRounds; ++r) {
+            const size_t i = wave_lo + (size_t)r * kWave + lane;
+            ok[r] = i < n;
+            k[r] = ok[r] ? keys_in[i] : 0;
+            v[r] = (ok[r] && vals_in) ? vals_in[i] : 0;
+            dg[r] = digit_of(k[r], shift);
+        }
+        // stable rank of every key among equal digits of this wave's quarter
+#pragma unroll
+        for (int r = 0; r < kSortRounds; ++r) {
+            uint64_t peers = __ballot(ok[r]);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (dg[r] >> b) & 1u;
+                const uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            unsigned before = 0;
+            if (ok[r]) {
+                before = wcnt[w][dg[r]];
+                rnk[r] = before + (unsigned)__popcll(peers & lt_mask);
+            }
+            // the lowest lane of each digit group advances the running count;
+            // same-wave LDS accesses are performed in program order
+            if (ok[r] && (peers & lt_mask) == 0) wcnt[w][dg[r]] = before + (unsigned)__popcll(peers);
+        }
+        __syncthreads();
+        // per-digit totals, wave bases and tile starts
+        {
+            const unsigned d = threadIdx.x;
+            unsigned tot = 0;
+            for (int i = 0; i < kSortWaves; ++i) {
+                const unsigned c = wcnt[i][d];
+                wcnt[i][d] = tot;
+                tot += c;
+            }
+            tcount[d] = tot;
+            unsigned total;
+            tstart[d] = block_excl_scan<kSortBlock>(tot, scan_tmp, total);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kSortRounds; ++r) {
+            if (ok[r]) {
+                const unsigned pos = tstart[dg[r]] + wcnt[w][dg[r]] + rnk[r];
+                skey[pos] = k[r];
+                sval[pos] = v[r];
+            }
+        }
+        __syncthreads();
+        const unsigned valid = (unsigned)std::min<size_t>(kSortTile, n - tile_lo);
+        for (unsigned i = threadIdx.x; i < valid; i += kSortBlock) {
+            const uint64_t key = skey[i];
+            const unsigned d = digit_of(key, shift);
+            const uint64_t dst = grun[d] + (i - tstart[d]);
+            keys_out[dst] = key;
+            if (vals_out) vals_out[dst] = sval[i];
+        }
+        __syncthreads();
+        grun[threadIdx.x] += tcount[threadIdx.x];
+        for (int i = 0; i < kSortWaves; ++i) wcnt[i][threadIdx.x] = 0;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+bool radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, size_t n, int bits,
+                      hipStream_t s)
+{
+    if (n <= 1 || bits <= 0) return false;
+    const size_t tiles = (n + kSortTile - 1) / kSortTile;
+    const unsigned nb = (unsigned)std::min<size_t>(tiles, kMaxSortBlocks);
+    const size_t tpb = (tiles + nb - 1) / nb;
+    DArray<uint64_t> hist((size_t)kRadix * nb, s);
+    bool in_alt = false;
+    for (int shift = 0; shift < bits; shift += 8) {
+        const uint64_t *ki = in_alt ? keys_alt : keys;
+        const uint32_t *vi = in_alt ? vals_alt : vals;
+        uint64_t *ko = in_alt ? keys : keys_alt;
+        uint32_t *vo = in_alt ? vals : vals_alt;
+        radix_upsweep<<<nb, kSortBlock, 0, s>>>(ki, n, shift, tpb, hist.get());
+        TP_CHECK_LAUNCH();
+        scan_u64(hist.get(), hist.get(), (size_t)kRadix * nb, false, s);
+        radix_downsweep<<<nb, kSortBlock, 0, s>>>(ki, vals ? vi : nullptr, ko, vals ? vo : nullptr, n, shift, tpb,
+                                                  hist.get());
+        TP_CHECK_LAUNCH();
+        in_alt = !in_alt;
+    }
+    return in_alt;
+}
+
+}  // namespace tp

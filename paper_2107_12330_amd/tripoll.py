@@ -1,0 +1,284 @@
+"""ctypes binding of libtripoll (include/tripoll.h): argument marshalling only.
+
+Every function named ``tripoll_*`` here calls the C entry point of the same
+name.  The helpers below them (``make_spec``, ``Graph``, ``build_graph``,
+``survey``) only pack Python values into the C structs and unpack results;
+all computation happens in the library's HIP kernels.  Loading fails loudly
+when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtripoll.so")
+
+# ------------------------------------------------------------------ constants
+TP_OK, TP_ERR_INVALID, TP_ERR_OOM, TP_ERR_DEVICE, TP_ERR_BUSY, TP_ERR_UNSUPPORTED, TP_ERR_NOT_FOUND = range(7)
+STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OOM", 3: "DEVICE", 4: "BUSY", 5: "UNSUPPORTED", 6: "NOT_FOUND"}
+TP_MEM_HOST, TP_MEM_DEVICE = 0, 1
+TP_TIE_MIX, TP_TIE_ID = 0, 1
+TP_OUT_COUNT, TP_OUT_CLOSE_HIST, TP_OUT_LABEL_TABLE, TP_OUT_SPREAD_COUNT, TP_OUT_OPEN_CLOSE = 1, 2, 4, 8, 16
+TP_FILT_WINDOW, TP_FILT_LABEL_MASK = 1, 2
+TP_STRAT_AUTO, TP_STRAT_GLOBAL_SEARCH = 0, 1
+TP_MAX_LABELS = 16
+TP_TABLE_MAX = 816
+TP_RW_TRIANGLES, TP_RW_SPREAD, TP_RW_PROBES, TP_RW_HIST = 0, 1, 2, 3
+TP_RW_TABLE = TP_RW_HIST + 32
+TP_RW_OPEN_CLOSE = TP_RW_TABLE + TP_TABLE_MAX
+TP_RW_SCRATCH = TP_RW_OPEN_CLOSE + 1024
+TP_RESULT_WORDS = TP_RW_SCRATCH + 4
+
+OUT_BITS = {"count": TP_OUT_COUNT, "close_hist": TP_OUT_CLOSE_HIST, "label_table": TP_OUT_LABEL_TABLE,
+            "spread_count": TP_OUT_SPREAD_COUNT, "open_close": TP_OUT_OPEN_CLOSE}
+
+
+class tp_edge_list(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_uint32), ("mem_space", ctypes.c_uint32), ("n_edges", ctypes.c_uint64),
+                ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("edge_time", ctypes.c_void_p),
+                ("vertex_label", ctypes.c_void_p), ("tie_hash", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class tp_graph_stats(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_uint64), ("n_raw_edges", ctypes.c_uint64),
+                ("n_self_loops", ctypes.c_uint64), ("n_edges", ctypes.c_uint64), ("d_max", ctypes.c_uint64),
+                ("dplus_max", ctypes.c_uint64), ("wedges", ctypes.c_uint64), ("probes", ctypes.c_uint64),
+                ("n_targets", ctypes.c_uint64), ("n_tiles", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
+                ("max_label", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("phase_ms", ctypes.c_float * 8), ("build_ms", ctypes.c_float)]
+
+
+class tp_survey_spec(ctypes.Structure):
+    _fields_ = [("outputs", ctypes.c_uint32), ("filters", ctypes.c_uint32), ("n_labels", ctypes.c_uint32),
+                ("strategy", ctypes.c_uint32), ("spread_lt", ctypes.c_uint64), ("t_lo", ctypes.c_uint64),
+                ("t_hi", ctypes.c_uint64), ("label_mask", ctypes.c_uint64 * 13)]
+
+
+class tp_survey_result(ctypes.Structure):
+    _fields_ = [("triangles", ctypes.c_uint64), ("spread_count", ctypes.c_uint64), ("probes", ctypes.c_uint64),
+                ("close_hist", ctypes.c_uint64 * 32), ("label_table", ctypes.c_uint64 * TP_TABLE_MAX),
+                ("open_close", ctypes.c_uint64 * 1024), ("kernel_ms", ctypes.c_float),
+                ("total_ms", ctypes.c_float)]
+
+
+class TripollError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+_lib = None
+
+# symbol -> (restype, argtypes)
+_P = ctypes.c_void_p
+SIGNATURES = {
+    "tripoll_build": (ctypes.c_int, [ctypes.POINTER(tp_edge_list), _P, ctypes.POINTER(_P)]),
+    "tripoll_graph_stats": (ctypes.c_int, [_P, ctypes.POINTER(tp_graph_stats)]),
+    "tripoll_graph_free": (ctypes.c_int, [_P]),
+    "tripoll_graph_export": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "tripoll_survey": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), ctypes.POINTER(tp_survey_result), _P]),
+    "tripoll_survey_async": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, _P]),
+    "tripoll_enumerate": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64), _P]),
+    "tripoll_msidx": (ctypes.c_uint32, [ctypes.c_uint32] * 3),
+    "tripoll_trim": (ctypes.c_int, []),
+    "tripoll_cached_bytes": (ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64)]),
+    "tripoll_last_error": (ctypes.c_char_p, []),
+    "tripoll_version": (ctypes.c_char_p, []),
+}
+
+
+def load():
+    """Load libtripoll.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libtripoll.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != TP_OK:
+        raise TripollError(status, load().tripoll_last_error().decode())
+
+
+# ------------------------------------------------------------------ raw entry points
+
+def tripoll_build(edges: tp_edge_list, stream=None) -> int:
+    g = _P()
+    _check(load().tripoll_build(ctypes.byref(edges), stream, ctypes.byref(g)))
+    return g.value
+
+
+def tripoll_graph_stats(g: int) -> tp_graph_stats:
+    st = tp_graph_stats()
+    _check(load().tripoll_graph_stats(g, ctypes.byref(st)))
+    return st
+
+
+def tripoll_graph_free(g: int) -> None:
+    _check(load().tripoll_graph_free(g))
+
+
+def tripoll_graph_export(g, rowptr=None, col=None, etime=None, tlabel=None, rank_to_id=None, rank_label=None):
+    ptr = lambda a: None if a is None else a.ctypes.data
+    _check(load().tripoll_graph_export(g, ptr(rowptr), ptr(col), ptr(etime), ptr(tlabel), ptr(rank_to_id),
+                                       ptr(rank_label)))
+
+
+def tripoll_survey(g: int, spec: tp_survey_spec, stream=None) -> tp_survey_result:
+    res = tp_survey_result()
+    _check(load().tripoll_survey(g, ctypes.byref(spec), ctypes.byref(res), stream))
+    return res
+
+
+def tripoll_survey_async(g: int, spec: tp_survey_spec, dev_out: int, stream=None) -> None:
+    _check(load().tripoll_survey_async(g, ctypes.byref(spec), dev_out, stream))
+
+
+def tripoll_enumerate(g: int, dev_records: int, capacity: int, stream=None) -> int:
+    n = ctypes.c_uint64(0)
+    _check(load().tripoll_enumerate(g, dev_records, capacity, ctypes.byref(n), stream))
+    return n.value
+
+
+def tripoll_msidx(a: int, b: int, c: int) -> int:
+    return int(load().tripoll_msidx(a, b, c))
+
+
+def tripoll_trim() -> None:
+    _check(load().tripoll_trim())
+
+
+def tripoll_cached_bytes() -> int:
+    v = ctypes.c_uint64(0)
+    _check(load().tripoll_cached_bytes(ctypes.byref(v)))
+    return v.value
+
+
+def tripoll_version() -> str:
+    return load().tripoll_version().decode()
+
+
+# ------------------------------------------------------------------ marshalling helpers
+
+def table_size(n_labels: int) -> int:
+    return (n_labels + 2) * (n_labels + 1) * n_labels // 6
+
+
+def make_spec(outputs=("count",), n_labels=4, spread_lt=0, window=None, label_mask=None,
+              strategy=TP_STRAT_AUTO) -> tp_survey_spec:
+    sp = tp_survey_spec()
+    sp.outputs = sum(OUT_BITS[o] for o in outputs)
+    sp.n_labels = n_labels
+    sp.strategy = strategy
+    sp.spread_lt = spread_lt
+    if window is not None:
+        sp.filters |= TP_FILT_WINDOW
+        sp.t_lo, sp.t_hi = int(window[0]), int(window[1])
+    if label_mask is not None:
+        sp.filters |= TP_FILT_LABEL_MASK
+        for idx in label_mask:
+            sp.label_mask[idx // 64] |= 1 << (idx % 64)
+    return sp
+
+
+def result_dict(res: tp_survey_result, n_labels: int = 16) -> dict:
+    return dict(triangles=int(res.triangles), spread_count=int(res.spread_count), probes=int(res.probes),
+                close_hist=np.frombuffer(bytes(res.close_hist), np.uint64).copy(),
+                label_table=np.frombuffer(bytes(res.label_table), np.uint64)[:table_size(n_labels)].copy(),
+                open_close=np.frombuffer(bytes(res.open_close), np.uint64).reshape(32, 32).copy(),
+                kernel_ms=float(res.kernel_ms), total_ms=float(res.total_ms))
+
+
+def words_dict(words: np.ndarray, n_labels: int = 16) -> dict:
+    """Unpack a device result buffer (TP_RESULT_WORDS uint64) copied to host."""
+    w = np.asarray(words, np.uint64)
+    return dict(triangles=int(w[TP_RW_TRIANGLES]), spread_count=int(w[TP_RW_SPREAD]),
+                probes=int(w[TP_RW_PROBES]), close_hist=w[TP_RW_HIST:TP_RW_HIST + 32].copy(),
+                label_table=w[TP_RW_TABLE:TP_RW_TABLE + table_size(n_labels)].copy(),
+                open_close=w[TP_RW_OPEN_CLOSE:TP_RW_OPEN_CLOSE + 1024].reshape(32, 32).copy())
+
+
+def stats_dict(st: tp_graph_stats) -> dict:
+    d = {f: getattr(st, f) for f, _ in tp_graph_stats._fields_ if f not in ("phase_ms", "reserved")}
+    d["phase_ms"] = list(st.phase_ms)
+    return d
+
+
+def _addr(a):
+    """Address of a numpy array or a torch tensor (host or device)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    return int(a.data_ptr())
+
+
+def edge_list(n, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX, device=None) -> tp_edge_list:
+    """Pack arrays into a tp_edge_list.  `device` True for device tensors;
+    by default inferred from the arrays (numpy = host)."""
+    if device is None:
+        device = not isinstance(src, np.ndarray)
+    el = tp_edge_list()
+    el.n_vertices = n
+    el.mem_space = TP_MEM_DEVICE if device else TP_MEM_HOST
+    el.n_edges = len(src)
+    el.src, el.dst, el.edge_time, el.vertex_label = _addr(src), _addr(dst), _addr(ts), _addr(vlab)
+    el.tie_hash = tie
+    return el
+
+
+class Graph:
+    """Owning handle of a built graph (released by close() or on exit)."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def stats(self) -> dict:
+        return stats_dict(tripoll_graph_stats(self.handle))
+
+    def close(self):
+        if self.handle:
+            tripoll_graph_free(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_graph(n, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX, stream=None) -> Graph:
+    return Graph(tripoll_build(edge_list(n, src, dst, ts, vlab, tie), stream))
+
+
+def survey(graph: Graph, stream=None, n_labels=4, **spec_kw) -> dict:
+    res = tripoll_survey(graph.handle, make_spec(n_labels=n_labels, **spec_kw), stream)
+    return result_dict(res, n_labels)
+
+
+def export(graph: Graph) -> dict:
+    st = graph.stats()
+    n, m = st["n_vertices"], st["n_edges"]
+    out = dict(rowptr=np.empty(n + 1, np.uint64), col=np.empty(m, np.uint32), etime=np.empty(m, np.uint32),
+               tlabel=np.empty(m, np.uint8), rank_to_id=np.empty(n, np.uint32), rank_label=np.empty(n, np.uint8))
+    tripoll_graph_export(graph.handle, **out)
+    return out
