@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Benchmark of the metadata triangle survey on one MI355X.
+
+One step is one pass of the whole hot path over the resident raw edge list:
+build the degree-ordered directed graph (canonicalise, sort, dedup with the
+earliest time, degree order, orient, CSR with co-located metadata, in-edge
+index, tile plan), survey it (intersection kernels with the fused reducer)
+and read the counters back.  The raw edges are generated once (seeded
+synthetic R-MAT input) and are resident in HBM before the timed region.
+
+Prints one JSON line.  `value` is triangles surveyed per second of whole
+steps.  The `roofline` object covers the dominant survey kernel: its
+algorithmic bytes per launch divided by its average launch time, measured
+with HIP events recorded on the stream the kernel is launched on.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "triangles surveyed/s + HBM GB/s at R-MAT scale 26; p50/p99 survey latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2107_12330_amd", "csrc", "survey.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "survey_traffic.json")
+CLASS_NAMES = ("survey_kernel<11,META> (d+(q) <= 1024, LDS hash)", "survey_kernel<13,META> (d+(q) <= 4096, LDS hash)",
+               "survey_kernel<0,META> (d+(q) > 4096, HBM binary search)")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("survey.hip", "graph.hpp", "plan.hpp", "tp_internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2107_12330_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(st: dict, c: int, meta: bool) -> int:
+    """Bytes the survey of class c must move, per launch.
+    Per wedge check: the candidate r (4 B) and, for metadata surveys, the
+    time of edge (p, r) that travels with it (4 B) -- the payload of a push in
+    Algorithm 1.  Per staged out-list entry of a target: id, and for metadata
+    surveys its edge time and target label (4 or 9 B).  Per in-edge record
+    16 B, per tile 16 B descriptor + 16 B of row pointers."""
+    per_probe = 8 if meta else 4
+    per_staged = 9 if meta else 4
+    return (per_probe * st["class_probes"][c] + per_staged * st["class_staged"][c] + 16 * st["class_records"][c]
+            + 32 * st["class_tiles"][c])
+
+
+def load_traffic(meta: bool, workload_name: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source and this workload."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_source_hash() or rec.get("workload") != workload_name:
+        return None
+    key = "meta" if meta else "count"
+    return rec.get(key, {}).get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(scale: int, threads: int) -> dict:
+    """The oracle (clean + survey) on a bounded sample: the same recipe at a
+    smaller R-MAT scale, timed on this host's cores."""
+    import oracle
+    import synth
+    w = synth.workload(3, scale=scale)
+    g = synth.generate(w.graph)
+    t0 = time.perf_counter()
+    u, v, t = oracle.clean(g["n"], g["src"], g["dst"], g["ts"])
+    r = oracle.survey_clean(g["n"], u, v, t, g["vlab"], outputs=w.outputs, n_labels=4, spread_lt=w.spread_lt,
+                            threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": r["triangles"] / dt, "unit": "triangles/s", "cores": threads, "kind": "oracle",
+            "sample": "full oracle pipeline (single-threaded clean, then orient + survey on %d threads, same "
+                      "outputs) on R-MAT scale %d of the same recipe: %d triangles in %.2f s"
+                      % (threads, scale, r["triangles"], dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=3, choices=(1, 2, 3))
+    ap.add_argument("--scale", type=int, default=None, help="override the R-MAT scale (same recipe)")
+    ap.add_argument("--count-only", action="store_true", help="survey the triangle count only")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-scale", type=int, default=21)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(the survey shards by splitting the work prefix, see the design notes)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2107_12330_amd import tripoll as tp
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    sptr = stream.cuda_stream
+
+    w = synth.workload(args.workload, scale=args.scale)
+    gs = w.graph
+    log("generating %s: n=%d raw edges=%d" % (w.name, gs.n, gs.n_edges))
+    t0 = time.perf_counter()
+    g = synth.generate(gs)
+    log("generated in %.1f s; uploading" % (time.perf_counter() - t0))
+    dev = {k: torch.from_numpy(g[k]).to("cuda") for k in ("src", "dst", "ts", "vlab")}
+    torch.cuda.synchronize()
+    del g
+    outputs = ("count",) if args.count_only else w.outputs
+    meta = not args.count_only
+    spec = tp.make_spec(outputs=outputs, n_labels=w.n_labels, spread_lt=w.spread_lt)
+    el = tp.edge_list(gs.n, dev["src"], dev["dst"], dev["ts"], dev["vlab"], device=True)
+
+    if args.copy_calibration:
+        # a plain copy of known size: 4 GiB read + 4 GiB written
+        a = torch.empty(1 << 30, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: %d bytes read, %d bytes written per copy" % (a.numel() * 4, b.numel() * 4))
+        del a, b
+
+    def step():
+        h = tp.tripoll_build(el, sptr)
+        try:
+            st = tp.stats_dict(tp.tripoll_graph_stats(h))
+            res = tp.tripoll_survey(h, spec, sptr)
+        finally:
+            tp.tripoll_graph_free(h)
+        return st, tp.result_dict(res, w.n_labels)
+
+    for i in range(args.warmup):
+        st, r = step()
+        log("warmup %d: build %.1f ms, survey %.1f ms, %d triangles" % (i, st["build_ms"], r["total_ms"],
+                                                                      r["triangles"]))
+
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    per = []
+    for i in range(args.steps):
+        s0 = time.perf_counter()
+        st, r = step()
+        per.append((time.perf_counter() - s0, st, r))
+        log("step %d: %.1f ms (build %.1f, survey %.1f kernel %.1f), %d triangles" % (
+            i, per[-1][0] * 1e3, st["build_ms"], r["total_ms"], r["kernel_ms"], r["triangles"]))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    gpu_ms = ev0.elapsed_time(ev1)
+
+    st, r = per[-1][1], per[-1][2]
+    tri = r["triangles"]
+    for _, _, rr in per:
+        assert rr["triangles"] == tri
+    ms_per_step = wall * 1e3 / args.steps
+    survey_ms = [rr["total_ms"] for _, _, rr in per]
+    kernel_ms = [rr["kernel_ms"] for _, _, rr in per]
+    build_ms = [s["build_ms"] for _, s, _ in per]
+
+    # dominant survey kernel
+    cls_ms = [statistics.mean(rr["class_ms"][c] for _, _, rr in per) for c in range(3)]
+    c = int(np.argmax(cls_ms))
+    alg = algorithmic_bytes(st, c, meta)
+    achieved = alg / (cls_ms[c] * 1e-3) / 1e9
+    traffic = load_traffic(meta, w.name)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": CLASS_NAMES[c].replace("META", "true" if meta else "false"),
+                "kernel_ms": round(cls_ms[c], 3), "algorithmic_bytes": int(alg),
+                "wedge_checks": int(st["class_probes"][c])}
+
+    out = {
+        "metric": METRIC,
+        "value": tri / (ms_per_step * 1e-3),
+        "unit": "triangles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "kind": gs.kind, "scale": gs.scale, "edge_factor": gs.edge_factor,
+                   "rmat_abcd": [0.57, 0.19, 0.19, 0.05], "timestamps": list(gs.ts), "labels": list(gs.labels),
+                   "outputs": list(outputs), "spread_lt": w.spread_lt, "seed": gs.seed,
+                   "raw_edges": gs.n_edges, "vertices": gs.n, "edges": st["n_edges"],
+                   "step": "build (canonicalise, sort, dedup, order, orient, CSR, in-edge index, plan) + survey"},
+        "result": {"triangles": tri, "wedges": st["wedges"], "wedge_checks": r["probes"],
+                   "spread_count": r["spread_count"], "d_max": st["d_max"], "dplus_max": st["dplus_max"]},
+        "survey": {
+            "triangles_per_s": tri / (statistics.median(survey_ms) * 1e-3),
+            "wedge_checks_per_s": r["probes"] / (statistics.median(survey_ms) * 1e-3),
+            "survey_ms_p50": statistics.median(survey_ms),
+            "survey_ms_p99": float(np.percentile(survey_ms, 99)),
+            "kernel_ms_p50": statistics.median(kernel_ms),
+            "class_ms": [round(x, 3) for x in cls_ms],
+            "build_ms_p50": statistics.median(build_ms),
+            "build_phase_ms": [round(x, 2) for x in st["phase_ms"]],
+            "gpu_ms_per_step": round(gpu_ms / args.steps, 3),
+        },
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        # the host's CPU share for this GPU: OMP_NUM_THREADS when set, else the visible cores (at most 16)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, len(os.sched_getaffinity(0)))
+        log("cpu baseline: oracle at scale %d on %d threads" % (args.cpu_scale, threads))
+        out["cpu_baseline"] = cpu_baseline(args.cpu_scale, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -106,6 +106,12 @@ typedef struct {
                                   1 sort by pair, 2 dedup, 3 degree+order, 4 orient+sort,
                                   5 CSR+metadata, 6 in-edge index, 7 survey plan */
     float build_ms;            /* sum of phase_ms */
+    uint32_t reserved2;
+    /* survey plan per target class (0: d+(q) <= 1024, 1: <= 4096, 2: larger) */
+    uint64_t class_tiles[3];   /* tiles */
+    uint64_t class_records[3]; /* in-edge records (one per oriented edge p -> q) */
+    uint64_t class_staged[3];  /* sum over tiles of d+(q): out-list entries loaded per survey */
+    uint64_t class_probes[3];  /* wedge checks */
 } tp_graph_stats;
 
 /*
@@ -172,6 +178,8 @@ tp_status tripoll_graph_export(const tp_graph *g, uint64_t *rowptr, uint32_t *co
 /* Intersection strategy (tests and tuning).  AUTO picks per target vertex. */
 #define TP_STRAT_AUTO 0u
 #define TP_STRAT_GLOBAL_SEARCH 1u /* binary search of Adj+(q) in HBM for every target */
+#define TP_STRAT_TABLE_STRESS 2u  /* LDS tables with one placement attempt per key: exercises
+                                     the stash and the HBM fallback (slow; for tests) */
 
 typedef struct {
     uint32_t outputs;        /* TP_OUT_* bitmask */
@@ -194,6 +202,8 @@ typedef struct {
     uint64_t open_close[32 * 32];
     float kernel_ms;         /* device time of the intersection kernels */
     float total_ms;          /* device time of the whole survey call */
+    float class_ms[3];       /* device time of the kernel of each target class */
+    uint32_t reserved;
 } tp_survey_result;
 
 /* Word layout of a device result buffer (uint64[TP_RESULT_WORDS]).  The

@@ -112,13 +112,28 @@ __global__ __launch_bounds__(kB) void k_dedup_write(const uint64_t *keys, const 
 
 // ------------------------------------------------------------ phase 3
 
+// d(v) over the unique pairs (sorted by lower endpoint): each wave adds one
+// count per run of equal lower endpoints, so hubs see few atomics.
 __global__ void k_degree(const uint64_t *ukey, size_t m, int nb, uint32_t *deg)
 {
     const uint64_t mask = (1ull << nb) - 1;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
-        const uint64_t k = ukey[i];
-        atomicAdd(&deg[k >> nb], 1u);
-        atomicAdd(&deg[k & mask], 1u);
+    const unsigned lane = lane_id();
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t base = blockIdx.x * (size_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < m; base += stride) {
+        const size_t i = base + lane;
+        const bool ok = i < m;
+        const uint64_t k = ok ? ukey[i] : ~0ull;
+        const uint64_t lo = k >> nb;
+        const uint64_t prev = __shfl_up(lo, 1, kWave);
+        const bool head = ok && (lane == 0 || prev != lo);
+        const uint64_t heads = __ballot(head);
+        const uint32_t valid = (uint32_t)__popcll(__ballot(ok));  // valid lanes are a prefix
+        if (head) {
+            const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
+            const uint32_t next = above ? (uint32_t)__ffsll((long long)above) - 1 : valid;
+            atomicAdd(&deg[lo], next - lane);
+        }
+        if (ok) atomicAdd(&deg[k & mask], 1u);
     }
 }
 
@@ -221,33 +236,54 @@ __device__ __forceinline__ uint32_t rest_len(const uint64_t *rowptr, uint32_t s,
     return (uint32_t)(rowptr[s + 1] - k - 1);
 }
 
-__global__ void k_in_count(const uint32_t *srow, const uint32_t *col, const uint64_t *rowptr, size_t m,
-                           uint32_t *incnt, unsigned long long *work)
+// Key of each oriented edge for the in-edge sort: (q << kbits) | k, with q
+// replaced by n (sorted past every target) when the edge has no wedge to
+// check.  Counts the edges kept.
+__global__ void k_in_keys(const uint32_t *srow, const uint32_t *col, const uint64_t *rowptr, size_t m, int kbits,
+                          uint32_t n, uint64_t *key, unsigned long long *kept)
 {
+    unsigned long long c = 0;
     for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < m; k += (size_t)gridDim.x * blockDim.x) {
         const uint32_t s = srow[k], t = col[k];
-        const uint32_t len = rest_len(rowptr, s, k);
-        if (len > 0 && rowptr[t + 1] > rowptr[t]) {
-            atomicAdd(&incnt[t], 1u);
-            atomicAdd(&work[t], (unsigned long long)len);
-        }
+        const bool ok = rest_len(rowptr, s, k) > 0 && rowptr[t + 1] > rowptr[t];
+        key[k] = ((uint64_t)(ok ? t : n) << kbits) | k;
+        c += ok ? 1 : 0;
     }
+    c = wave_sum(c);
+    if (lane_id() == 0 && c) atomicAdd(kept, c);
 }
 
-__global__ void k_in_scatter(const uint32_t *srow, const uint32_t *col, const uint32_t *ets, const uint64_t *rowptr,
-                             const uint8_t *rlab, size_t m, const uint64_t *cptr, uint32_t *cursor, InRec *rec)
+// In-edges and wedge checks of every target (the sum of the remaining row
+// lengths of its in-edges).  In-edges of one target are consecutive, so each
+// wave adds one partial sum per run of equal targets.
+__global__ void k_in_work(const uint64_t *key, const uint32_t *piv, uint64_t n_in, int kbits,
+                          const uint64_t *rowptr, unsigned long long *work, uint32_t *count)
 {
-    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < m; k += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t s = srow[k], t = col[k];
-        const uint32_t len = rest_len(rowptr, s, k);
-        if (len > 0 && rowptr[t + 1] > rowptr[t]) {
-            const uint64_t at = cptr[t] + atomicAdd(&cursor[t], 1u);
-            InRec r;
-            r.k_lo = (uint32_t)k;
-            r.k_hi_lab = (uint32_t)((k >> 32) & 0xffffffu) | ((uint32_t)rlab[s] << 24);
-            r.len = len;
-            r.t_pq = ets[k];
-            rec[at] = r;
+    const uint64_t kmask = (1ull << kbits) - 1;
+    const unsigned lane = lane_id();
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t base = blockIdx.x * (size_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < n_in; base += stride) {
+        const size_t i = base + lane;
+        const bool ok = i < n_in;
+        uint64_t t = ~0ull, len = 0;
+        if (ok) {
+            const uint64_t kk = key[i];
+            t = kk >> kbits;
+            len = rowptr[piv[i] + 1] - (kk & kmask) - 1;
+        }
+        const uint64_t tprev = __shfl_up(t, 1, kWave);
+        const bool head = ok && (lane == 0 || tprev != t);
+        const uint64_t heads = __ballot(head);
+        const uint64_t incl = wave_incl_scan(len);
+        // the lane where this lane's run starts, and the prefix before it
+        const uint64_t upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
+        const int start = 63 - __clzll(upto);
+        const uint64_t before = __shfl(incl - len, start, kWave);
+        const uint64_t tnext = __shfl_down(t, 1, kWave);
+        const bool last = ok && (lane == 63 || i + 1 >= n_in || tnext != t);
+        if (last) {
+            atomicAdd(&work[t], (unsigned long long)(incl - before));
+            atomicAdd(&count[t], lane - (unsigned)start + 1u);
         }
     }
 }
@@ -289,11 +325,12 @@ __global__ void k_plan_write(const uint64_t *cptr, const uint64_t *tile_off, con
         const uint64_t c0 = cptr[q], cnt = cptr[q + 1] - c0;
         const uint64_t base = tile_off[q];
         for (uint32_t j = 0; j < t; ++j) {
-            const uint64_t a = c0 + cnt * j / t, b = c0 + cnt * (j + 1) / t;
             TileDesc d;
             d.q = (uint32_t)q;
-            d.cnt = (uint32_t)(b - a);
-            d.e0 = a;
+            d.cnt = (uint32_t)((cnt - j + t - 1) / t);  // records j, j + t, ... of the target
+            d.e0 = c0 + j;
+            d.stride = t;
+            d.pad = 0;
             tiles[base + j] = d;
         }
     }
@@ -312,6 +349,36 @@ __global__ void k_work_stats(const unsigned long long *work, uint32_t n, unsigne
     if (lane_id() == 0) {
         if (w) atomicAdd(sum, w);
         if (c) atomicAdd(nonzero, c);
+    }
+}
+
+// Per-class totals of the plan: records, staged out-list entries, probes.
+__global__ void k_plan_stats(const uint64_t *cptr, const unsigned long long *work, const uint64_t *rowptr,
+                             const uint32_t *tcnt, uint32_t n, unsigned long long *out /* [3][3] */)
+{
+    unsigned long long rec[kNumClasses] = {0, 0, 0}, stg[kNumClasses] = {0, 0, 0}, prb[kNumClasses] = {0, 0, 0};
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+        const uint64_t dq = rowptr[q + 1] - rowptr[q];
+        const int c = class_of(dq);
+        const uint32_t t = tcnt[(size_t)c * n + q];
+        if (!t) continue;
+#pragma unroll
+        for (int i = 0; i < kNumClasses; ++i) {
+            if (i == c) {
+                rec[i] += cptr[q + 1] - cptr[q];
+                stg[i] += (unsigned long long)t * dq;
+                prb[i] += work[q];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kNumClasses; ++i) {
+        const unsigned long long a = wave_sum(rec[i]), b = wave_sum(stg[i]), c = wave_sum(prb[i]);
+        if (lane_id() == 0) {
+            if (a) atomicAdd(&out[0 * kNumClasses + i], a);
+            if (b) atomicAdd(&out[1 * kNumClasses + i], b);
+            if (c) atomicAdd(&out[2 * kNumClasses + i], c);
+        }
     }
 }
 
@@ -485,9 +552,13 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out)
     g->rowptr.reset((size_t)n + 1, s);
     scan_u32_to_u64(dplus.get(), g->rowptr.get(), n, s);
     dplus.release();
-    g->col.reset(std::max<uint64_t>(m, 1), s);
+    // col and ets carry kRowPad zeroed slots past the end: the survey loads a
+    // whole wave of slots from any row start
+    g->col.reset(m + kRowPad, s);
     g->tlab.reset(std::max<uint64_t>(m, 1), s);
-    g->ets.reset(std::max<uint64_t>(m, 1), s);
+    g->ets.reset(m + kRowPad, s);
+    TP_HIP(hipMemsetAsync(g->col.get() + m, 0, kRowPad * sizeof(uint32_t), s));
+    TP_HIP(hipMemsetAsync(g->ets.get() + m, 0, kRowPad * sizeof(uint32_t), s));
     uint32_t *srow = spare_val;
     if (m) {
         k_csr<<<grid_for(m, kB), kB, 0, s>>>(okey, m, nb, g->rlab.get(), g->col.get(), g->tlab.get(), srow);
@@ -496,34 +567,47 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out)
     }
     k_row_stats<<<grid_for(n, kB), kB, 0, s>>>(g->rowptr.get(), n, c_wedge, c_dpmax);
     TP_CHECK_LAUNCH();
-    // the key buffers are no longer needed; srow lives in one value buffer
-    keyA.release();
-    keyB.release();
     TP_HIP(hipEventRecord(ev[6], s));
 
-    // ---- phase 6: in-edge index
+    // ---- phase 6: in-edge index, a sort of the oriented edges by target
     DArray<unsigned long long> work(n, s);
     DArray<uint64_t> cptr((size_t)n + 1, s);
     {
+        int kbits = std::max(1, bits_for(m));
+        if (kbits + nb + 1 > 64) fail(TP_ERR_UNSUPPORTED, "tripoll_build: graph too large for the in-edge keys");
+        g->kbits = (uint32_t)kbits;
+        uint64_t *ikey = keyA.get(), *ikey_alt = keyB.get();
+        uint32_t *ival = srow, *ival_alt = (srow == valA.get()) ? valB.get() : valA.get();
+        DArray<unsigned long long> kept(1, s);
+        TP_HIP(hipMemsetAsync(kept.get(), 0, sizeof(unsigned long long), s));
+        if (m) {
+            k_in_keys<<<grid_for(m, kB), kB, 0, s>>>(srow, g->col.get(), g->rowptr.get(), m, kbits, n, ikey,
+                                                     kept.get());
+            TP_CHECK_LAUNCH();
+        }
+        g->n_in = read_scalar(kept.get(), s);
+        const bool alt = radix_sort_pairs(ikey, ival, ikey_alt, ival_alt, m, nb + 1, s, kbits);
+        if (alt) {
+            std::swap(ikey, ikey_alt);
+            std::swap(ival, ival_alt);
+        }
+        // keep the sorted buffers as the index; the others go back to the pool
+        DArray<uint64_t> &kk = (ikey == keyA.get()) ? keyA : keyB;
+        DArray<uint32_t> &vv = (ival == valA.get()) ? valA : valB;
+        g->inkey = std::move(kk);
+        g->inp = std::move(vv);
         DArray<uint32_t> incnt(n, s);
         TP_HIP(hipMemsetAsync(incnt.get(), 0, n * sizeof(uint32_t), s));
         TP_HIP(hipMemsetAsync(work.get(), 0, n * sizeof(unsigned long long), s));
-        if (m) {
-            k_in_count<<<grid_for(m, kB), kB, 0, s>>>(srow, g->col.get(), g->rowptr.get(), m, incnt.get(),
-                                                      work.get());
+        if (g->n_in) {
+            k_in_work<<<grid_for(g->n_in, kB), kB, 0, s>>>(g->inkey.get(), g->inp.get(), g->n_in, kbits,
+                                                           g->rowptr.get(), work.get(), incnt.get());
             TP_CHECK_LAUNCH();
         }
         scan_u32_to_u64(incnt.get(), cptr.get(), n, s);
-        g->n_in = read_scalar(cptr.get() + n, s);
-        g->inrec.reset(std::max<uint64_t>(g->n_in, 1), s);
-        TP_HIP(hipMemsetAsync(incnt.get(), 0, n * sizeof(uint32_t), s));
-        if (m) {
-            k_in_scatter<<<grid_for(m, kB), kB, 0, s>>>(srow, g->col.get(), g->ets.get(), g->rowptr.get(),
-                                                        g->rlab.get(), m, cptr.get(), incnt.get(),
-                                                        g->inrec.get());
-            TP_CHECK_LAUNCH();
-        }
     }
+    keyA.release();
+    keyB.release();
     valA.release();
     valB.release();
     TP_HIP(hipEventRecord(ev[7], s));
@@ -545,6 +629,20 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out)
                 TP_CHECK_LAUNCH();
             }
         }
+        DArray<unsigned long long> pst(3 * kNumClasses, s);
+        TP_HIP(hipMemsetAsync(pst.get(), 0, 3 * kNumClasses * sizeof(unsigned long long), s));
+        k_plan_stats<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), work.get(), g->rowptr.get(), tcnt.get(), n,
+                                                    pst.get());
+        TP_CHECK_LAUNCH();
+        unsigned long long h[3 * kNumClasses];
+        TP_HIP(hipMemcpyAsync(h, pst.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+        for (int c = 0; c < kNumClasses; ++c) {
+            g->stats.class_tiles[c] = g->n_tiles[c];
+            g->stats.class_records[c] = h[c];
+            g->stats.class_staged[c] = h[kNumClasses + c];
+            g->stats.class_probes[c] = h[2 * kNumClasses + c];
+        }
     }
     // probes = sum of the work of all targets; active targets = targets with work
     k_work_stats<<<grid_for(n, kB), kB, 0, s>>>(work.get(), n, c_bad + 6, c_bad + 7);
@@ -557,6 +655,9 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out)
     g->stats.n_vertices = n;
     g->stats.wedges = hs[4];
     g->stats.dplus_max = hs[5];
+    // the survey packs a position in Adj+(q) into 22 bits; d+ <= sqrt(2m) keeps
+    // this far away for any graph that fits in memory
+    if (hs[5] >= (1ull << 22)) fail(TP_ERR_UNSUPPORTED, "tripoll_build: out-degree above 2^22 in the oriented graph");
     g->stats.probes = hs[6];
     g->stats.n_targets = hs[7];
     g->stats.n_tiles = g->n_tiles[0] + g->n_tiles[1] + g->n_tiles[2];
@@ -569,7 +670,8 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out)
     }
     g->stats.build_ms = total;
     g->stats.device_bytes = g->rowptr.bytes() + g->col.bytes() + g->ets.bytes() + g->tlab.bytes() +
-                            g->rlab.bytes() + g->perm.bytes() + g->inrec.bytes() + g->tiles[0].bytes() +
+                            g->rlab.bytes() + g->perm.bytes() + g->inkey.bytes() + g->inp.bytes() +
+                            g->tiles[0].bytes() +
                             g->tiles[1].bytes() + g->tiles[2].bytes();
     *out = g.release();
 }

@@ -3,25 +3,21 @@
 
 #include "tp_internal.hpp"
 
-// One tile of survey work: `cnt` consecutive in-edge records of target q,
-// starting at record e0.
+// One tile of survey work: `cnt` in-edge records of target q, records e0,
+// e0 + stride, e0 + 2 stride, ...  (the tiles of a target interleave, so
+// each gets a fair share of long and short rows).
 struct TileDesc {
     uint32_t q;
     uint32_t cnt;
     uint64_t e0;
+    uint32_t stride;
+    uint32_t pad;
 };
 
-// In-edge record of target q for the oriented edge p -> q stored at CSR slot
-// k of p's row: the wedges (p,q,r) to check are the rest of p's row after k.
-//   w0 = k bits 0..31, w1 = k bits 32..55 | label(p) << 24,
-//   w2 = length of the rest of p's row, w3 = time of edge (p,q).
-struct InRec {
-    uint32_t k_lo;
-    uint32_t k_hi_lab;
-    uint32_t len;
-    uint32_t t_pq;
-};
-
+// In-edge index: one entry per oriented edge p -> q whose remaining row is
+// non-empty, sorted by q.  The key holds q above bit `kbits` and the CSR
+// slot k of the edge in p's row below it; the wedges (p, q, r) to check are
+// the slots after k in p's row.  A second array holds p.
 // Target classes of the survey plan, by d+(q).
 enum { kClassSmall = 0, kClassLarge = 1, kClassHuge = 2, kNumClasses = 3 };
 
@@ -37,7 +33,9 @@ struct tp_graph {
     tp::DArray<uint8_t> tlab;     // [m] label of each target
     tp::DArray<uint8_t> rlab;     // [n] label by rank
     tp::DArray<uint32_t> perm;    // [n] rank -> original id
-    tp::DArray<InRec> inrec;      // [n_in] in-edge records grouped by target
+    uint32_t kbits = 1;           // bits of a CSR slot in an in-edge key
+    tp::DArray<uint64_t> inkey;   // [n_in] (q << kbits) | k, sorted by q
+    tp::DArray<uint32_t> inp;     // [n_in] pivot p of each in-edge
     tp::DArray<TileDesc> tiles[kNumClasses];
     uint64_t n_tiles[kNumClasses] = {0, 0, 0};
     tp_graph_stats stats{};

@@ -7,16 +7,22 @@
 namespace tp {
 
 // Targets q are split into classes by d+(q): the class decides how Adj+(q)
-// is searched.  Small and large targets keep an open-addressing hash of
-// Adj+(q) in LDS with at most 50% load; huge ones are searched in HBM.
-constexpr uint32_t kSmallMaxDeg = 1024;  // hash of <= 2048 slots
-constexpr uint32_t kLargeMaxDeg = 4096;  // hash of <= 8192 slots
-constexpr int kSmallLogSlots = 11;
-constexpr int kLargeLogSlots = 13;
+// is searched.  Small and large targets keep a two-table cuckoo hash of
+// Adj+(q) in LDS (each table 2^k >= 1.25 d+(q) slots, so the load stays at
+// most 0.4, plus a small stash); huge ones are searched in HBM.
+constexpr uint32_t kSmallMaxDeg = 819;   // tables of <= 1024 slots
+constexpr uint32_t kLargeMaxDeg = 3276;  // tables of <= 4096 slots
+constexpr int kSmallLogSlots = 10;
+constexpr int kLargeLogSlots = 12;
+constexpr uint32_t kStash = 32;          // keys the cuckoo insertion could not place
 
 // A tile holds at most kTileRecords in-edge records of one target and about
 // kTileWork wedge checks.
-constexpr uint32_t kTileRecords = 512;
-constexpr uint64_t kTileWork = 65536;
+constexpr uint32_t kTileRecords = 1024;
+constexpr uint64_t kTileWork = 262144;
+
+// Slots of padding after the last oriented edge in the target and time
+// arrays, so that a wave may load 64 consecutive slots from any row start.
+constexpr uint64_t kRowPad = 64;
 
 }  // namespace tp

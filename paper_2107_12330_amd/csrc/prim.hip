@@ -361,7 +361,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_downsweep(const uint64_t *ke
 }  // namespace
 
 bool radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, size_t n, int bits,
-                      hipStream_t s)
+                      hipStream_t s, int begin_bit)
 {
     if (n <= 1 || bits <= 0) return false;
     const size_t tiles = (n + kSortTile - 1) / kSortTile;
@@ -369,7 +369,7 @@ bool radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32
     const size_t tpb = (tiles + nb - 1) / nb;
     DArray<uint64_t> hist((size_t)kRadix * nb, s);
     bool in_alt = false;
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int shift = begin_bit; shift < begin_bit + bits; shift += 8) {
         const uint64_t *ki = in_alt ? keys_alt : keys;
         const uint32_t *vi = in_alt ? vals_alt : vals;
         uint64_t *ko = in_alt ? keys : keys_alt;

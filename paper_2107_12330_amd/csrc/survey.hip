@@ -30,11 +30,22 @@ using namespace tp;
 
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / kWave;
-constexpr int kUnroll = 8;
+constexpr int kSmallBlock = 256;   // 4 waves share a small target's tables
+constexpr int kLargeBlock = 1024;  // 16 waves share a large target's tables
+constexpr int kUnroll = 8;         // rows of 64 candidates per batch; two batches in flight
+constexpr uint32_t kRing = 128;    // per-wave ring of queued hits: slot|label(p), time(p,r), time(p,q), p
+constexpr uint64_t kChunk = 4;     // tiles claimed at a time by a workgroup
+constexpr int kRsrcWord3 = 0x00020000;  // buffer resource word 3 for raw 32-bit loads on CDNA
 constexpr uint32_t kEmpty = 0xffffffffu;
-constexpr uint32_t kHashMul = 0x9e3779b1u;  // Fibonacci hashing
+constexpr uint32_t kMaxKicks = 64;  // cuckoo displacements before a key goes to the stash
+
+// The two cuckoo hash functions (multiplicative, with a pre-mix for the
+// second so the two are unrelated), each onto 2^log_s slots.
+__device__ __forceinline__ uint32_t hash0(uint32_t r, uint32_t log_s) { return (r * 0x9e3779b1u) >> (32 - log_s); }
+__device__ __forceinline__ uint32_t hash1(uint32_t r, uint32_t log_s)
+{
+    return ((r ^ (r >> 16)) * 0x85ebca6bu) >> (32 - log_s);
+}
 
 struct SurveyParams {
     const uint64_t *rowptr;
@@ -42,7 +53,9 @@ struct SurveyParams {
     const uint32_t *ets;
     const uint8_t *tlab;
     const uint8_t *rlab;
-    const InRec *inrec;
+    const uint64_t *inkey;    // sorted in-edge keys (q << kbits) | k
+    const uint32_t *inp;      // pivot of each in-edge
+    uint32_t kbits;
     const TileDesc *tiles;
     uint64_t n_tiles;
     unsigned long long *tile_counter;
@@ -50,7 +63,12 @@ struct SurveyParams {
     uint32_t outputs, filters;
     uint32_t table_words;     // entries of the label table in LDS (0 if unused)
     uint32_t oc_words;        // 1024 if OPEN_CLOSE else 0
-    uint64_t spread_lt, t_lo, t_hi;
+    uint32_t t_lo32, t_hi32;  // window, clamped to the uint32 time range
+    uint32_t spread_le;       // spread counter: close <= spread_le ...
+    uint32_t spread_any;      // ... and spread_lt > 0
+    uint32_t window_empty;    // window lies above every uint32 time
+    uint32_t lut_shift;       // labels < 2^lut_shift index the multiset table (0 if unused)
+    uint32_t max_kicks;       // cuckoo displacements per key before the stash
     uint64_t label_mask[13];
     // enumeration
     uint32_t *enum_out;
@@ -60,16 +78,17 @@ struct SurveyParams {
     uint32_t n;
 };
 
-// LDS layout (dynamic): [hash keys][hash times][hash labels][record starts]
-// [record prefix][record times][record labels][counters].
+// LDS layout (dynamic): [hash keys][hash times][hash labels][hit rings]
+// [counters][label lut].
 struct LdsLayout {
     uint32_t slots;
-    size_t off_hts, off_hlab, off_rk, off_rpre, off_rts, off_rlab, off_cnt, total;
+    size_t off_hts, off_hlab, off_ring, off_cnt, off_lut, total;
 };
 
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-__host__ __device__ inline LdsLayout lds_layout(uint32_t slots, bool meta, uint32_t counter_words)
+__host__ __device__ inline LdsLayout lds_layout(uint32_t slots, bool meta, uint32_t counter_words, int waves,
+                                                uint32_t lut_shift)
 {
     LdsLayout L;
     L.slots = slots;
@@ -78,23 +97,17 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t slots, bool meta, uint3
     if (meta) o += (size_t)slots * 4;
     L.off_hlab = o;
     if (meta) o += slots;
-    o = align_up(o, 8);
-    L.off_rk = o;
-    o += (size_t)kTileRecords * 8;
-    L.off_rpre = o;
-    o += (size_t)(kTileRecords + 16) * 4;
-    L.off_rts = o;
-    if (meta) o += (size_t)kTileRecords * 4;
-    L.off_rlab = o;
-    if (meta) o += kTileRecords;
-    o = align_up(o, 8);
+    o = align_up(o, 16);
+    L.off_ring = o;
+    if (meta) o += (size_t)waves * kRing * 16;
     L.off_cnt = o;
     o += (size_t)counter_words * 8;
+    L.off_lut = o;
+    if (meta) o += (size_t)2 << (3 * lut_shift);
     L.total = o;
     return L;
 }
 
-// counters in LDS: [hist 32][table table_words][open_close oc_words]
 __host__ __device__ inline uint32_t counter_words(uint32_t table_words, uint32_t oc_words)
 {
     return 32 + table_words + oc_words;
@@ -123,18 +136,21 @@ struct Hit {
 };
 
 // Reduce one triangle into the workgroup's counters.  Returns 1 if it passed
-// the filters.
+// the filters.  `lut` maps the labels (a, b, c), packed in lut_shift-bit
+// fields, to the label-multiset index.
 __device__ __forceinline__ uint32_t reduce_hit(const SurveyParams &P, const Hit &h, unsigned long long *cnt,
-                                               const uint64_t *mask_lds, unsigned long long &spread)
+                                               const uint64_t *mask_lds, const uint16_t *lut, uint32_t &spread)
 {
     const uint32_t f = P.filters;
     if (f & TP_FILT_WINDOW) {
-        if (h.t_pq < P.t_lo || h.t_pq > P.t_hi || h.t_pr < P.t_lo || h.t_pr > P.t_hi || h.t_qr < P.t_lo ||
-            h.t_qr > P.t_hi)
+        if (P.window_empty) return 0;
+        if (h.t_pq < P.t_lo32 || h.t_pq > P.t_hi32 || h.t_pr < P.t_lo32 || h.t_pr > P.t_hi32 ||
+            h.t_qr < P.t_lo32 || h.t_qr > P.t_hi32)
             return 0;
     }
     uint32_t idx = 0;
-    if ((P.outputs & TP_OUT_LABEL_TABLE) || (f & TP_FILT_LABEL_MASK)) idx = multiset_index(h.l_p, h.l_q, h.l_r);
+    if ((P.outputs & TP_OUT_LABEL_TABLE) || (f & TP_FILT_LABEL_MASK))
+        idx = lut[(((h.l_p << P.lut_shift) | h.l_q) << P.lut_shift) | h.l_r];
     if (f & TP_FILT_LABEL_MASK) {
         if (!((mask_lds[idx >> 6] >> (idx & 63)) & 1ull)) return 0;
     }
@@ -143,7 +159,7 @@ __device__ __forceinline__ uint32_t reduce_hit(const SurveyParams &P, const Hit 
     const uint32_t close = t3 - t1;
     if (P.outputs & TP_OUT_CLOSE_HIST) atomicAdd(&cnt[close_bin(close)], 1ull);
     if (P.outputs & TP_OUT_LABEL_TABLE) atomicAdd(&cnt[32 + idx], 1ull);
-    if (P.outputs & TP_OUT_SPREAD_COUNT) spread += ((uint64_t)close < P.spread_lt) ? 1ull : 0ull;
+    if (P.outputs & TP_OUT_SPREAD_COUNT) spread += (P.spread_any && close <= P.spread_le) ? 1u : 0u;
     if (P.outputs & TP_OUT_OPEN_CLOSE) {
         const uint32_t t2 = h.t_pq + h.t_pr + h.t_qr - t1 - t3;  // exact in uint32 arithmetic mod 2^32
         atomicAdd(&cnt[32 + P.table_words + close_bin(t2 - t1) * 32 + close_bin(close)], 1ull);
@@ -164,207 +180,371 @@ __device__ __forceinline__ int64_t global_find(const uint32_t *col, uint64_t lo,
     return (a < len && col[lo + a] == r) ? (int64_t)(lo + a) : -1;
 }
 
-__device__ __forceinline__ uint32_t find_pivot(const uint64_t *rowptr, uint32_t n, uint64_t k)
+// Load through the constant address space: with a wave-uniform address this
+// is a scalar load into SGPRs (the arrays are not written by the survey).
+template <class T>
+__device__ __forceinline__ T sload(const T *p)
 {
-    // the row p with rowptr[p] <= k < rowptr[p+1]
-    uint32_t a = 0, b = n;
-    while (b - a > 1) {
-        const uint32_t mid = a + (b - a) / 2;
-        if (rowptr[mid] <= k) a = mid;
-        else b = mid;
-    }
-    return a;
+    static_assert(sizeof(T) % 4 == 0, "scalar loads move whole dwords");
+    typedef const __attribute__((address_space(4))) uint32_t *cptr;
+    const cptr c = reinterpret_cast<cptr>(reinterpret_cast<uintptr_t>(p));
+    uint32_t w[sizeof(T) / 4];
+#pragma unroll
+    for (size_t i = 0; i < sizeof(T) / 4; ++i) w[i] = c[i];
+    T v;
+    __builtin_memcpy(&v, w, sizeof(T));
+    return v;
 }
+
+// One in-edge record as the wave walks it: the candidates of p -> q are the
+// `len` slots of p's row starting at `start`.
+// One in-edge as the wave walks it: the candidates of p -> q are the `len`
+// slots of p's row starting at `start`.  A block holds one in-edge per lane.
+struct RecBlock {
+    uint32_t start_lo, start_hi, len, t_pq, l_p, p;
+};
 
 // LOG_SLOTS > 0: LDS hash of Adj+(q) with 2^LOG_SLOTS slots at most.
 // LOG_SLOTS == 0: binary search of Adj+(q) in HBM.
-template <int LOG_SLOTS, bool META, bool ENUM>
-__global__ __launch_bounds__(kBlock) void survey_kernel(SurveyParams P)
+// BLOCK threads share one target's table.  The records of a tile are dealt
+// to the waves round-robin; a wave walks its records in rows of up to 64
+// consecutive candidates of one pivot's row (lane i takes candidate i), so
+// every address is a wave-uniform base plus the lane.  Hits go to a per-wave
+// ring in LDS and are reduced 64 at a time.
+template <int LOG_SLOTS, int BLOCK, bool META, bool ENUM>
+__global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
 {
+    constexpr int kW = BLOCK / kWave;  // waves per workgroup
     extern __shared__ __align__(16) unsigned char lds[];
-    constexpr uint32_t kSlots = LOG_SLOTS > 0 ? (1u << LOG_SLOTS) : 0u;
-    const LdsLayout L = lds_layout(kSlots, META, counter_words(P.table_words, P.oc_words));
+    constexpr uint32_t kSlots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
+    const LdsLayout L = lds_layout(kSlots, META || ENUM, counter_words(P.table_words, P.oc_words), kW, P.lut_shift);
     uint32_t *hkey = reinterpret_cast<uint32_t *>(lds);
     uint32_t *hts = reinterpret_cast<uint32_t *>(lds + L.off_hts);
     uint8_t *hlab = lds + L.off_hlab;
-    uint64_t *rk = reinterpret_cast<uint64_t *>(lds + L.off_rk);
-    uint32_t *rpre = reinterpret_cast<uint32_t *>(lds + L.off_rpre);
-    uint32_t *rts = reinterpret_cast<uint32_t *>(lds + L.off_rts);
-    uint8_t *rlb = lds + L.off_rlab;
     unsigned long long *cnt = reinterpret_cast<unsigned long long *>(lds + L.off_cnt);
+    uint16_t *lut = reinterpret_cast<uint16_t *>(lds + L.off_lut);
     __shared__ uint64_t mask_lds[13];
     __shared__ unsigned long long s_tile;
-    __shared__ uint32_t s_scan[kWaves];
+    __shared__ uint32_t s_stash, s_fail;
 
     const int tid = threadIdx.x;
-    const int w = tid / kWave;
+    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
     const uint32_t lane = lane_id();
+    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint4 *ring = reinterpret_cast<uint4 *>(lds + L.off_ring) + (size_t)w * kRing;
     const uint32_t nc = counter_words(P.table_words, P.oc_words);
-    for (uint32_t i = tid; i < nc; i += kBlock) cnt[i] = 0;
+    for (uint32_t i = tid; i < nc; i += BLOCK) cnt[i] = 0;
     if (tid < 13) mask_lds[tid] = P.label_mask[tid];
-
-    unsigned long long my_tri = 0, my_spread = 0, probes = 0;
-
-    for (;;) {
-        if (tid == 0) s_tile = atomicAdd(P.tile_counter, 1ull);
-        __syncthreads();
-        const unsigned long long ti = s_tile;
-        if (ti >= P.n_tiles) break;
-        const TileDesc d = P.tiles[P.n_tiles - 1 - ti];
-        const uint32_t q = d.q;
-        const uint32_t nrec = d.cnt;
-        const uint64_t kq = P.rowptr[q];
-        const uint32_t dq = (uint32_t)(P.rowptr[q + 1] - kq);
-        const uint32_t l_q = META ? P.rlab[q] : 0u;
-
-        uint32_t log_s = 0, smask = 0;
-        if (LOG_SLOTS > 0) {
-            // slots: the power of two >= 2*dq, at least 64
-            log_s = 6;
-            while ((1u << log_s) < 2u * dq) ++log_s;
-            smask = (1u << log_s) - 1;
-            for (uint32_t i = tid; i <= smask; i += kBlock) hkey[i] = kEmpty;
-        }
-        // in-edge records of this tile, and the prefix of their lengths
-        uint32_t lens[2];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const uint32_t i = tid * 2 + j;
-            lens[j] = 0;
-            if (i < nrec) {
-                const InRec r = P.inrec[d.e0 + i];
-                const uint64_t k = (uint64_t)r.k_lo | ((uint64_t)(r.k_hi_lab & 0xffffffu) << 32);
-                rk[i] = k + 1;  // first candidate slot
-                lens[j] = r.len;
-                if (META) {
-                    rts[i] = r.t_pq;
-                    rlb[i] = (uint8_t)(r.k_hi_lab >> 24);
-                }
-            }
-        }
-        uint32_t total;
-        const uint32_t pre = block_excl_scan<kBlock>(lens[0] + lens[1], s_scan, total);
-        if (tid * 2 < kTileRecords) {
-            rpre[tid * 2] = pre;
-            rpre[tid * 2 + 1] = pre + lens[0];
-        }
-        // records past the tile end: prefix = total (so that searches stop)
-        __syncthreads();
-        for (uint32_t i = nrec + tid; i < kTileRecords + 16; i += kBlock) rpre[i] = (i == nrec) ? total : 0xffffffffu;
-        if (LOG_SLOTS > 0) {
-            for (uint32_t i = tid; i < dq; i += kBlock) {
-                const uint32_t r = P.col[kq + i];
-                uint32_t h = (r * kHashMul) >> (32 - log_s);
-                for (;;) {
-                    const uint32_t prev = atomicCAS(&hkey[h], kEmpty, r);
-                    if (prev == kEmpty) break;
-                    h = (h + 1) & smask;
-                }
-                if (META) {
-                    hts[h] = P.ets[kq + i];
-                    hlab[h] = P.tlab[kq + i];
-                }
-            }
-        }
-        __syncthreads();
-        if (tid == 0) probes += total;
-
-        // ---- stream the candidates: wave w takes a contiguous range of rows
-        const uint32_t rows = (total + kWave - 1) / kWave;
-        const uint32_t row_lo = (uint32_t)((uint64_t)rows * w / kWaves);
-        const uint32_t row_hi = (uint32_t)((uint64_t)rows * (w + 1) / kWaves);
-        uint32_t seg = 0;
-        for (uint32_t row = row_lo; row < row_hi; row += kUnroll) {
-            uint64_t addr[kUnroll];
-            uint32_t segj[kUnroll];
-            bool ok[kUnroll];
-#pragma unroll
-            for (int j = 0; j < kUnroll; ++j) {
-                const uint32_t f = (row + j) * kWave + lane;
-                ok[j] = (row + j < row_hi) && f < total;
-                if (ok[j]) {
-                    while (rpre[seg + 8] <= f) seg += 8;
-                    while (rpre[seg + 1] <= f) ++seg;
-                    addr[j] = rk[seg] + (f - rpre[seg]);
-                    segj[j] = seg;
-                }
-            }
-            uint32_t cand[kUnroll], tpr[kUnroll];
-#pragma unroll
-            for (int j = 0; j < kUnroll; ++j) {
-                if (ok[j]) {
-                    cand[j] = P.col[addr[j]];
-                    if (META) tpr[j] = P.ets[addr[j]];
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < kUnroll; ++j) {
-                if (!ok[j]) continue;
-                const uint32_t r = cand[j];
-                int64_t slot = -1;
-                if (LOG_SLOTS > 0) {
-                    uint32_t h = (r * kHashMul) >> (32 - log_s);
-                    for (;;) {
-                        const uint32_t key = hkey[h];
-                        if (key == r) { slot = h; break; }
-                        if (key == kEmpty) break;
-                        h = (h + 1) & smask;
-                    }
-                } else {
-                    slot = global_find(P.col, kq, dq, r);
-                }
-                if (slot < 0) continue;
-                if (!META && !ENUM) {
-                    ++my_tri;
-                    continue;
-                }
-                Hit h;
-                h.t_pq = rts[segj[j]];
-                h.l_p = rlb[segj[j]];
-                h.l_q = l_q;
-                h.t_pr = tpr[j];
-                if (LOG_SLOTS > 0) {
-                    h.t_qr = hts[slot];
-                    h.l_r = hlab[slot];
-                } else {
-                    h.t_qr = P.ets[slot];
-                    h.l_r = P.tlab[slot];
-                }
-                if (ENUM) {
-                    const unsigned long long at = atomicAdd(P.enum_count, 1ull);
-                    if (at < P.enum_cap) {
-                        const uint64_t kpq = rk[segj[j]] - 1;
-                        const uint32_t p = find_pivot(P.rowptr, P.n, kpq);
-                        uint32_t *o = P.enum_out + at * 9;
-                        o[0] = P.perm[p];
-                        o[1] = P.perm[q];
-                        o[2] = P.perm[r];
-                        o[3] = h.t_pq;
-                        o[4] = h.t_pr;
-                        o[5] = h.t_qr;
-                        o[6] = h.l_p;
-                        o[7] = h.l_q;
-                        o[8] = h.l_r;
-                    }
-                    ++my_tri;
-                } else {
-                    my_tri += reduce_hit(P, h, cnt, mask_lds, my_spread);
-                }
-            }
-        }
-        __syncthreads();
+    if (META) {
+        const uint32_t ls = P.lut_shift, lm = (1u << ls) - 1;
+        for (uint32_t i = tid; i < (1u << (3 * ls)); i += BLOCK)
+            lut[i] = (uint16_t)multiset_index(i >> (2 * ls), (i >> ls) & lm, i & lm);
     }
 
+    unsigned long long my_tri = 0, my_spread = 0, probes = 0;
+    uint32_t qh = 0, qt = 0;  // this wave's hit ring: entries [qh, qt)
+
+    // the target whose out-list is in the LDS table, and its geometry
+    uint32_t cur_q = 0xffffffffu;
+    uint64_t kq = 0;
+    uint32_t dq = 0, l_q = 0, log_s = 0;
+    uint32_t n_stash = 0;  // keys in the stash
+    bool gmode = LOG_SLOTS == 0;  // search Adj+(q) in HBM (huge targets, or a failed table)
+
+    // reduce the hits queued in this wave's ring, one per lane
+    auto drain = [&](uint32_t count) {
+        uint32_t tri = 0, spread = 0;
+        if (lane < count) {
+            const uint4 e = ring[(qh + lane) & (kRing - 1)];
+            const uint32_t where = e.x & 0x3fffffu;
+            Hit h;
+            h.t_pq = e.z;
+            h.l_p = e.x >> 22;
+            h.l_q = l_q;
+            h.t_pr = e.y;
+            if (!gmode) {
+                h.t_qr = hts[where];
+                h.l_r = hlab[where];
+            } else {
+                h.t_qr = P.ets[kq + where];
+                h.l_r = P.tlab[kq + where];
+            }
+            if (ENUM) {
+                const uint32_t r = !gmode ? hkey[where] : P.col[kq + where];
+                const unsigned long long at = atomicAdd(P.enum_count, 1ull);
+                if (at < P.enum_cap) {
+                    uint32_t *o = P.enum_out + at * 9;
+                    o[0] = P.perm[e.w];
+                    o[1] = P.perm[cur_q];
+                    o[2] = P.perm[r];
+                    o[3] = h.t_pq;
+                    o[4] = h.t_pr;
+                    o[5] = h.t_qr;
+                    o[6] = h.l_p;
+                    o[7] = h.l_q;
+                    o[8] = h.l_r;
+                }
+                tri = 1;
+            } else {
+                tri = reduce_hit(P, h, cnt, mask_lds, lut, spread);
+            }
+        }
+        my_tri += tri;
+        my_spread += spread;
+        qh += count;
+    };
+
+    for (;;) {
+        // claim a chunk of kChunk consecutive tiles; consecutive tiles mostly
+        // share their target, whose table is then built once
+        if (tid == 0) s_tile = atomicAdd(P.tile_counter, 1ull);
+        __syncthreads();
+        const uint64_t t_begin = s_tile * kChunk;
+        __syncthreads();  // everyone has read s_tile before it is claimed again
+        if (t_begin >= P.n_tiles) break;
+        const uint64_t t_end = min(t_begin + kChunk, P.n_tiles);
+        for (uint64_t ti = t_begin; ti < t_end; ++ti) {
+            const TileDesc d = sload(P.tiles + (P.n_tiles - 1 - ti));
+            if (d.q != cur_q) {
+                // a new target: reduce the hits still queued against the old
+                // table, then rebuild it once every wave is done with it
+                if (META || ENUM) {
+                    if (qt != qh) drain(qt - qh);
+                }
+                __syncthreads();
+                cur_q = d.q;
+                kq = sload(P.rowptr + cur_q);
+                dq = (uint32_t)(sload(P.rowptr + cur_q + 1) - kq);
+                l_q = META ? __builtin_amdgcn_readfirstlane(P.rlab[cur_q]) : 0u;
+                if (LOG_SLOTS > 0) {
+                    // two tables of 2^log_s >= 1.25 dq slots each, then the stash
+                    log_s = 5;
+                    while ((1u << log_s) < dq + dq / 4) ++log_s;
+                    const uint32_t S = 1u << log_s;
+                    for (uint32_t i = tid; i < 2 * S + kStash; i += BLOCK) hkey[i] = kEmpty;
+                    if (tid == 0) {
+                        s_stash = 0;
+                        s_fail = 0;
+                    }
+                    __syncthreads();
+                    // cuckoo insertion: a key evicted from one table moves to
+                    // its slot in the other; keys still homeless after
+                    // kMaxKicks moves go to the stash
+                    for (uint32_t i = tid; i < dq; i += BLOCK) {
+                        uint32_t cur = P.col[kq + i];
+                        uint32_t t = 0;
+                        for (uint32_t it = 0; it < P.max_kicks; ++it) {
+                            const uint32_t h = t == 0 ? hash0(cur, log_s) : S + hash1(cur, log_s);
+                            cur = atomicExch(&hkey[h], cur);
+                            if (cur == kEmpty) break;
+                            t ^= 1u;
+                        }
+                        if (cur != kEmpty) {
+                            const uint32_t at = atomicAdd(&s_stash, 1u);
+                            if (at < kStash) hkey[2 * S + at] = cur;
+                            else s_fail = 1;
+                        }
+                    }
+                    __syncthreads();
+                    n_stash = __builtin_amdgcn_readfirstlane(min(s_stash, kStash));
+                    gmode = __builtin_amdgcn_readfirstlane(s_fail) != 0;
+                    // the metadata of every key goes beside its final slot
+                    if ((META || ENUM) && !gmode) {
+                        for (uint32_t i = tid; i < dq; i += BLOCK) {
+                            const uint32_t r = P.col[kq + i];
+                            uint32_t h = hash0(r, log_s);
+                            if (hkey[h] != r) {
+                                h = S + hash1(r, log_s);
+                                if (hkey[h] != r) {
+                                    h = 2 * S;
+                                    while (hkey[h] != r) ++h;
+                                }
+                            }
+                            hts[h] = P.ets[kq + i];
+                            hlab[h] = P.tlab[kq + i];
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+
+            // ---- this wave's records: tile records w, w + kW, w + 2kW, ...
+            // The wave loads them 64 at a time into VGPRs (lane i holds its
+            // i-th record) and reads the current one with readlane, so the
+            // walk itself issues no memory access.
+            const uint32_t ncnt = d.cnt;
+            const uint32_t nw = ncnt > (uint32_t)w ? (ncnt - (uint32_t)w + kW - 1) / kW : 0u;
+            if (nw == 0) continue;
+            const uint64_t kmask = (1ull << P.kbits) - 1;
+            // lane l of block b holds this wave's in-edge 64b + l (tile record w + (64b + l) kW)
+            auto load_block = [&](uint32_t blk) -> RecBlock {
+                const uint32_t i = blk * kWave + lane;
+                RecBlock r{0, 0, 0, 0, 0, 0};
+                if (i < nw) {
+                    const uint64_t e = d.e0 + ((uint64_t)(uint32_t)w + (uint64_t)i * kW) * d.stride;
+                    const uint64_t k = P.inkey[e] & kmask;
+                    const uint32_t p = P.inp[e];
+                    const uint64_t st = k + 1;
+                    r.start_lo = (uint32_t)st;
+                    r.start_hi = (uint32_t)(st >> 32);
+                    r.len = (uint32_t)(P.rowptr[p + 1] - st);
+                    r.t_pq = (META || ENUM) ? P.ets[k] : 0u;
+                    r.l_p = (META || ENUM) ? P.rlab[p] : 0u;
+                    r.p = p;
+                }
+                return r;
+            };
+            RecBlock blk_cur = load_block(0);
+            RecBlock blk_nxt = nw > kWave ? load_block(1) : RecBlock{0, 0, 0, 0, 0, 0};
+            struct WaveRec {
+                uint64_t start;
+                uint32_t len, t_pq, l_p, p;
+            };
+            auto read_rec = [&](uint32_t i) -> WaveRec {
+                const uint32_t l = i & (kWave - 1);
+                WaveRec r;
+                r.start = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(blk_cur.start_lo, l) |
+                          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(blk_cur.start_hi, l) << 32);
+                r.len = __builtin_amdgcn_readlane(blk_cur.len, l);
+                r.t_pq = (META || ENUM) ? __builtin_amdgcn_readlane(blk_cur.t_pq, l) : 0;
+                r.l_p = (META || ENUM) ? __builtin_amdgcn_readlane(blk_cur.l_p, l) : 0;
+                r.p = ENUM ? __builtin_amdgcn_readlane(blk_cur.p, l) : 0;
+                return r;
+            };
+            uint32_t i = 0;   // current record (wave-local index)
+            WaveRec rec = read_rec(0);
+            uint32_t off = 0; // next slot of the current record
+            uint32_t wave_work = 0, wave_hits = 0;
+
+            // next row: valid lanes and the record's metadata; returns the
+            // row's first slot
+            struct Row {
+                uint32_t n, t_pq, l_p, p;
+            };
+            auto next_row = [&](Row &rw) -> uint64_t {
+                uint64_t base = 0;
+                if (i < nw) {
+                    base = rec.start + off;
+                    rw.n = min(rec.len - off, (uint32_t)kWave);
+                    rw.t_pq = rec.t_pq;
+                    rw.l_p = rec.l_p;
+                    rw.p = rec.p;
+                    wave_work += rw.n;
+                    off += kWave;
+                    if (off >= rec.len) {
+                        off = 0;
+                        ++i;
+                        if (i < nw) {
+                            if ((i & (kWave - 1)) == 0) {
+                                blk_cur = blk_nxt;
+                                blk_nxt = (i + kWave < nw) ? load_block(i / kWave + 1) : RecBlock{0, 0, 0, 0, 0, 0};
+                            }
+                            rec = read_rec(i);
+                        }
+                    }
+                } else {
+                    rw.n = 0;
+                    rw.t_pq = 0;
+                    rw.l_p = 0;
+                    rw.p = 0;
+                }
+                return base;
+            };
+            // issue the loads of kUnroll rows: buffer loads whose resource
+            // covers exactly the row's valid slots (other lanes read 0)
+            auto prepare = [&](Row(&rows)[kUnroll], uint32_t(&cand)[kUnroll], uint32_t(&tpr)[kUnroll]) {
+#pragma unroll
+                for (int j = 0; j < kUnroll; ++j) {
+                    const uint64_t base = next_row(rows[j]);
+                    const uint32_t bytes = rows[j].n * 4u;
+                    cand[j] = __builtin_amdgcn_raw_buffer_load_b32(
+                        __builtin_amdgcn_make_buffer_rsrc((void *)(P.col + base), (short)0, bytes, kRsrcWord3),
+                        lane * 4u, 0, 0);
+                    if (META || ENUM)
+                        tpr[j] = __builtin_amdgcn_raw_buffer_load_b32(
+                            __builtin_amdgcn_make_buffer_rsrc((void *)(P.ets + base), (short)0, bytes, kRsrcWord3),
+                            lane * 4u, 0, 0);
+                }
+            };
+            auto process = [&](const Row(&rows)[kUnroll], const uint32_t(&cand)[kUnroll],
+                               const uint32_t(&tpr)[kUnroll]) {
+#pragma unroll
+                for (int j = 0; j < kUnroll; ++j) {
+                    if (rows[j].n == 0) continue;
+                    const uint32_t r = cand[j];
+                    bool hit = false;
+                    uint32_t slot = 0;
+                    if (lane < rows[j].n) {
+                        if (!gmode) {
+                            // two independent reads, no loop
+                            const uint32_t h0 = hash0(r, log_s), h1 = (1u << log_s) + hash1(r, log_s);
+                            const uint32_t k0 = hkey[h0], k1 = hkey[h1];
+                            hit = k0 == r || k1 == r;
+                            slot = k0 == r ? h0 : h1;
+                            if (n_stash) {
+                                const uint32_t st = 2u << log_s;
+                                for (uint32_t x = 0; x < n_stash; ++x) {
+                                    if (hkey[st + x] == r) {
+                                        hit = true;
+                                        slot = st + x;
+                                    }
+                                }
+                            }
+                        } else {
+                            const int64_t at = global_find(P.col, kq, dq, r);
+                            hit = at >= 0;
+                            slot = (uint32_t)(at - (int64_t)kq);
+                        }
+                    }
+                    const uint64_t m = __ballot(hit);
+                    if (!META && !ENUM) {
+                        wave_hits += (uint32_t)__popcll(m);
+                        continue;
+                    }
+                    if (m) {
+                        if (hit) {
+                            const uint32_t pos = qt + (uint32_t)__popcll(m & lt_mask);
+                            ring[pos & (kRing - 1)] = make_uint4(slot | (rows[j].l_p << 22), tpr[j], rows[j].t_pq,
+                                                                 rows[j].p);
+                        }
+                        qt += (uint32_t)__popcll(m);
+                        if (qt - qh >= (uint32_t)kWave) drain(kWave);
+                    }
+                }
+            };
+            // two batches in flight: the next batch's loads are issued before
+            // the current batch is probed
+            Row rA[kUnroll], rB[kUnroll];
+            uint32_t cA[kUnroll], tA[kUnroll], cB[kUnroll], tB[kUnroll];
+            prepare(rA, cA, tA);
+            for (;;) {
+                prepare(rB, cB, tB);
+                process(rA, cA, tA);
+                if (rB[0].n == 0) break;
+                prepare(rA, cA, tA);
+                process(rB, cB, tB);
+                if (rA[0].n == 0) break;
+            }
+            if (lane == 0) {
+                probes += wave_work;
+                my_tri += wave_hits;
+            }
+        }
+    }
+
+    if (META || ENUM) {
+        if (qt != qh) drain(qt - qh);
+    }
     // ---- merge this workgroup's counters into the result
     my_tri = wave_sum(my_tri);
     my_spread = wave_sum(my_spread);
     if (lane == 0) {
         if (my_tri) atomicAdd(&P.out[TP_RW_TRIANGLES], my_tri);
         if (my_spread) atomicAdd(&P.out[TP_RW_SPREAD], my_spread);
+        if (probes) atomicAdd(&P.out[TP_RW_PROBES], probes);
     }
-    if (tid == 0 && probes) atomicAdd(&P.out[TP_RW_PROBES], probes);
     __syncthreads();
-    for (uint32_t i = tid; i < nc; i += kBlock) {
+    for (uint32_t i = tid; i < nc; i += BLOCK) {
         const unsigned long long v = cnt[i];
         if (!v) continue;
         uint32_t word;
@@ -382,16 +562,17 @@ __global__ void zero_u64(unsigned long long *p, size_t n)
 
 uint32_t table_size(uint32_t L) { return (L + 2) * (L + 1) * L / 6; }
 
-template <int LOG_SLOTS, bool META, bool ENUM>
+template <int LOG_SLOTS, int BLOCK, bool META, bool ENUM>
 void launch_class(const SurveyParams &P, hipStream_t s, int device)
 {
     if (P.n_tiles == 0) return;
-    const uint32_t slots = LOG_SLOTS > 0 ? (1u << LOG_SLOTS) : 0u;
-    const LdsLayout L = lds_layout(slots, META, counter_words(P.table_words, P.oc_words));
-    auto kern = survey_kernel<LOG_SLOTS, META, ENUM>;
+    const uint32_t slots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
+    const LdsLayout L =
+        lds_layout(slots, META || ENUM, counter_words(P.table_words, P.oc_words), BLOCK / kWave, P.lut_shift);
+    auto kern = survey_kernel<LOG_SLOTS, BLOCK, META, ENUM>;
     TP_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total));
     int per_cu = 0;
-    TP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, L.total));
+    TP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, L.total));
     if (per_cu < 1) fail(TP_ERR_DEVICE, "survey kernel does not fit on a compute unit");
     int cus = 0;
     TP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
@@ -399,31 +580,27 @@ void launch_class(const SurveyParams &P, hipStream_t s, int device)
     if (grid > P.n_tiles) grid = P.n_tiles;
     zero_u64<<<1, 64, 0, s>>>(P.tile_counter, 1);
     TP_CHECK_LAUNCH();
-    kern<<<(unsigned)grid, kBlock, L.total, s>>>(P);
+    kern<<<(unsigned)grid, BLOCK, L.total, s>>>(P);
     TP_CHECK_LAUNCH();
 }
 
+// Launch the three target classes in turn.  `timers`, when given, holds one
+// EventTimer per class around its launch.
 template <bool META, bool ENUM>
-void launch_all(const tp_graph *g, SurveyParams P, uint32_t strategy, hipStream_t s)
+void launch_all(const tp_graph *g, SurveyParams P, uint32_t strategy, hipStream_t s, EventTimer *timers = nullptr)
 {
-    // one tile counter per class, so the three launches may overlap later
-    if (strategy == TP_STRAT_GLOBAL_SEARCH) {
-        for (int c = 0; c < kNumClasses; ++c) {
-            P.tiles = g->tiles[c].get();
-            P.n_tiles = g->n_tiles[c];
-            launch_class<0, META, ENUM>(P, s, g->device);
-        }
-        return;
+    for (int c = 0; c < kNumClasses; ++c) {
+        P.tiles = g->tiles[c].get();
+        P.n_tiles = g->n_tiles[c];
+        if (timers) timers[c].start();
+        if (strategy == TP_STRAT_GLOBAL_SEARCH || c == kClassHuge)
+            launch_class<0, kSmallBlock, META, ENUM>(P, s, g->device);
+        else if (c == kClassSmall)
+            launch_class<kSmallLogSlots, kSmallBlock, META, ENUM>(P, s, g->device);
+        else
+            launch_class<kLargeLogSlots, kLargeBlock, META, ENUM>(P, s, g->device);
+        if (timers) timers[c].stop();
     }
-    P.tiles = g->tiles[kClassSmall].get();
-    P.n_tiles = g->n_tiles[kClassSmall];
-    launch_class<kSmallLogSlots, META, ENUM>(P, s, g->device);
-    P.tiles = g->tiles[kClassLarge].get();
-    P.n_tiles = g->n_tiles[kClassLarge];
-    launch_class<kLargeLogSlots, META, ENUM>(P, s, g->device);
-    P.tiles = g->tiles[kClassHuge].get();
-    P.n_tiles = g->n_tiles[kClassHuge];
-    launch_class<0, META, ENUM>(P, s, g->device);
 }
 
 void validate_spec(const tp_graph *g, const tp_survey_spec *sp)
@@ -433,7 +610,7 @@ void validate_spec(const tp_graph *g, const tp_survey_spec *sp)
                            TP_OUT_OPEN_CLOSE;
     if (sp->outputs & ~known) fail(TP_ERR_INVALID, "tripoll_survey: unknown output bits");
     if (sp->filters & ~(TP_FILT_WINDOW | TP_FILT_LABEL_MASK)) fail(TP_ERR_INVALID, "tripoll_survey: unknown filter bits");
-    if (sp->strategy > TP_STRAT_GLOBAL_SEARCH) fail(TP_ERR_INVALID, "tripoll_survey: unknown strategy");
+    if (sp->strategy > TP_STRAT_TABLE_STRESS) fail(TP_ERR_INVALID, "tripoll_survey: unknown strategy");
     const bool labels = (sp->outputs & TP_OUT_LABEL_TABLE) || (sp->filters & TP_FILT_LABEL_MASK);
     if (labels) {
         if (sp->n_labels < 1 || sp->n_labels > TP_MAX_LABELS)
@@ -455,18 +632,29 @@ SurveyParams make_params(const tp_graph *g, const tp_survey_spec *sp, unsigned l
     P.ets = g->ets.get();
     P.tlab = g->tlab.get();
     P.rlab = g->rlab.get();
-    P.inrec = g->inrec.get();
+    P.inkey = g->inkey.get();
+    P.inp = g->inp.get();
+    P.kbits = g->kbits;
     P.tile_counter = counter;
     P.out = out;
     P.outputs = sp->outputs | TP_OUT_COUNT;
     P.filters = sp->filters;
     P.table_words = (sp->outputs & TP_OUT_LABEL_TABLE) ? table_size(sp->n_labels) : 0;
     P.oc_words = (sp->outputs & TP_OUT_OPEN_CLOSE) ? 1024 : 0;
-    P.spread_lt = sp->spread_lt;
-    P.t_lo = sp->t_lo;
-    P.t_hi = sp->t_hi;
-    // window bounds beyond the uint32 time range clamp to it
-    if (P.t_hi > 0xffffffffull) P.t_hi = 0xffffffffull;
+    // close < spread_lt  <=>  close <= spread_lt - 1 (close is a uint32)
+    P.spread_any = sp->spread_lt > 0;
+    P.spread_le = sp->spread_lt == 0 ? 0u : (uint32_t)std::min<uint64_t>(sp->spread_lt - 1, 0xffffffffull);
+    // window bounds beyond the uint32 time range clamp to it; an empty clamped
+    // window (t_lo > 2^32 - 1) keeps nothing
+    P.t_lo32 = (uint32_t)std::min<uint64_t>(sp->t_lo, 0xffffffffull);
+    P.t_hi32 = (uint32_t)std::min<uint64_t>(sp->t_hi, 0xffffffffull);
+    P.window_empty = sp->t_lo > 0xffffffffull;
+    // the table-stress strategy allows a single placement attempt, so that
+    // the stash and the HBM fallback are exercised
+    P.max_kicks = sp->strategy == TP_STRAT_TABLE_STRESS ? 1u : kMaxKicks;
+    P.lut_shift = 0;
+    if ((sp->outputs & TP_OUT_LABEL_TABLE) || (sp->filters & TP_FILT_LABEL_MASK))
+        while ((1u << P.lut_shift) < sp->n_labels) ++P.lut_shift;
     for (int i = 0; i < 13; ++i) P.label_mask[i] = sp->label_mask[i];
     P.perm = g->perm.get();
     P.n = g->n;
@@ -482,7 +670,7 @@ bool needs_meta(const tp_survey_spec *sp)
 // the tile counter).  Allocates nothing.
 template <bool ENUM>
 void survey_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned long long *dev_out, hipStream_t s,
-                    uint32_t *enum_out = nullptr, uint64_t enum_cap = 0)
+                    uint32_t *enum_out = nullptr, uint64_t enum_cap = 0, EventTimer *timers = nullptr)
 {
     zero_u64<<<grid_for(TP_RESULT_WORDS, 256), 256, 0, s>>>(dev_out, TP_RESULT_WORDS);
     TP_CHECK_LAUNCH();
@@ -494,9 +682,9 @@ void survey_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned long l
         P.enum_count = dev_out + TP_RW_SCRATCH + 1;
         launch_all<true, true>(g, P, TP_STRAT_AUTO, s);
     } else if (needs_meta(sp)) {
-        launch_all<true, false>(g, P, sp->strategy, s);
+        launch_all<true, false>(g, P, sp->strategy, s, timers);
     } else {
-        launch_all<false, false>(g, P, sp->strategy, s);
+        launch_all<false, false>(g, P, sp->strategy, s, timers);
     }
 }
 
@@ -523,9 +711,10 @@ extern "C" tp_status tripoll_survey(const tp_graph *g, const tp_survey_spec *spe
         hipStream_t s = (hipStream_t)stream;
         DArray<unsigned long long> res(TP_RESULT_WORDS, s);
         EventTimer all(s), kern(s);
+        EventTimer cls[kNumClasses] = {EventTimer(s), EventTimer(s), EventTimer(s)};
         all.start();
         kern.start();
-        survey_enqueue<false>(g, spec, res.get(), s);
+        survey_enqueue<false>(g, spec, res.get(), s, nullptr, 0, cls);
         kern.stop();
         std::vector<unsigned long long> h(TP_RESULT_WORDS);
         TP_HIP(hipMemcpyAsync(h.data(), res.get(), TP_RESULT_WORDS * 8, hipMemcpyDeviceToHost, s));
@@ -534,6 +723,7 @@ extern "C" tp_status tripoll_survey(const tp_graph *g, const tp_survey_spec *spe
         copy_result(h, out);
         out->kernel_ms = kern.ms();
         out->total_ms = all.ms();
+        for (int c = 0; c < kNumClasses; ++c) out->class_ms[c] = g->n_tiles[c] ? cls[c].ms() : 0.f;
     });
 }
 

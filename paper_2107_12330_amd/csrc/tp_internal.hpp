@@ -128,6 +128,8 @@ struct EventTimer {
         TP_HIP(hipEventCreate(&a));
         TP_HIP(hipEventCreate(&b));
     }
+    EventTimer(const EventTimer &) = delete;
+    EventTimer &operator=(const EventTimer &) = delete;
     ~EventTimer()
     {
         if (a) (void)hipEventDestroy(a);
@@ -208,11 +210,11 @@ void scan_u64(const uint64_t *in, uint64_t *out, size_t n, bool with_total, hipS
 // Exclusive scan of n uint32 values into uint64 offsets (out holds n+1).
 void scan_u32_to_u64(const uint32_t *in, uint64_t *out, size_t n, hipStream_t s);
 
-// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the
-// key.  Sorts keys[0..n) with vals; alt buffers are scratch of the same size.
-// Returns true when the result ended in the alt buffers.
+// Stable LSD radix sort of (key, value) pairs on key bits [begin_bit,
+// begin_bit + bits).  Sorts keys[0..n) with vals; alt buffers are scratch of
+// the same size.  Returns true when the result ended in the alt buffers.
 bool radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, size_t n,
-                      int bits, hipStream_t s);
+                      int bits, hipStream_t s, int begin_bit = 0);
 
 template <class T>
 void fill(T *p, T v, size_t n, hipStream_t s);

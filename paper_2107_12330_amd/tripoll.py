@@ -23,7 +23,7 @@ TP_MEM_HOST, TP_MEM_DEVICE = 0, 1
 TP_TIE_MIX, TP_TIE_ID = 0, 1
 TP_OUT_COUNT, TP_OUT_CLOSE_HIST, TP_OUT_LABEL_TABLE, TP_OUT_SPREAD_COUNT, TP_OUT_OPEN_CLOSE = 1, 2, 4, 8, 16
 TP_FILT_WINDOW, TP_FILT_LABEL_MASK = 1, 2
-TP_STRAT_AUTO, TP_STRAT_GLOBAL_SEARCH = 0, 1
+TP_STRAT_AUTO, TP_STRAT_GLOBAL_SEARCH, TP_STRAT_TABLE_STRESS = 0, 1, 2
 TP_MAX_LABELS = 16
 TP_TABLE_MAX = 816
 TP_RW_TRIANGLES, TP_RW_SPREAD, TP_RW_PROBES, TP_RW_HIST = 0, 1, 2, 3
@@ -48,7 +48,9 @@ class tp_graph_stats(ctypes.Structure):
                 ("dplus_max", ctypes.c_uint64), ("wedges", ctypes.c_uint64), ("probes", ctypes.c_uint64),
                 ("n_targets", ctypes.c_uint64), ("n_tiles", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
                 ("max_label", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("phase_ms", ctypes.c_float * 8), ("build_ms", ctypes.c_float)]
+                ("phase_ms", ctypes.c_float * 8), ("build_ms", ctypes.c_float), ("reserved2", ctypes.c_uint32),
+                ("class_tiles", ctypes.c_uint64 * 3), ("class_records", ctypes.c_uint64 * 3),
+                ("class_staged", ctypes.c_uint64 * 3), ("class_probes", ctypes.c_uint64 * 3)]
 
 
 class tp_survey_spec(ctypes.Structure):
@@ -61,7 +63,7 @@ class tp_survey_result(ctypes.Structure):
     _fields_ = [("triangles", ctypes.c_uint64), ("spread_count", ctypes.c_uint64), ("probes", ctypes.c_uint64),
                 ("close_hist", ctypes.c_uint64 * 32), ("label_table", ctypes.c_uint64 * TP_TABLE_MAX),
                 ("open_close", ctypes.c_uint64 * 1024), ("kernel_ms", ctypes.c_float),
-                ("total_ms", ctypes.c_float)]
+                ("total_ms", ctypes.c_float), ("class_ms", ctypes.c_float * 3), ("reserved", ctypes.c_uint32)]
 
 
 class TripollError(RuntimeError):
@@ -197,7 +199,8 @@ def result_dict(res: tp_survey_result, n_labels: int = 16) -> dict:
                 close_hist=np.frombuffer(bytes(res.close_hist), np.uint64).copy(),
                 label_table=np.frombuffer(bytes(res.label_table), np.uint64)[:table_size(n_labels)].copy(),
                 open_close=np.frombuffer(bytes(res.open_close), np.uint64).reshape(32, 32).copy(),
-                kernel_ms=float(res.kernel_ms), total_ms=float(res.total_ms))
+                kernel_ms=float(res.kernel_ms), total_ms=float(res.total_ms),
+                class_ms=[float(x) for x in res.class_ms])
 
 
 def words_dict(words: np.ndarray, n_labels: int = 16) -> dict:
@@ -210,8 +213,10 @@ def words_dict(words: np.ndarray, n_labels: int = 16) -> dict:
 
 
 def stats_dict(st: tp_graph_stats) -> dict:
-    d = {f: getattr(st, f) for f, _ in tp_graph_stats._fields_ if f not in ("phase_ms", "reserved")}
+    d = {f: getattr(st, f) for f, _ in tp_graph_stats._fields_ if not f.startswith(("phase_ms", "reserved", "class_"))}
     d["phase_ms"] = list(st.phase_ms)
+    for f in ("class_tiles", "class_records", "class_staged", "class_probes"):
+        d[f] = [int(x) for x in getattr(st, f)]
     return d
 
 

@@ -47,8 +47,9 @@ def test_struct_layout_matches_header(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu\\n", sizeof(tp_edge_list), sizeof(tp_graph_stats), sizeof(tp_survey_spec),
          sizeof(tp_survey_result));
-  printf("%zu %zu %zu\\n", offsetof(tp_graph_stats, phase_ms), offsetof(tp_survey_spec, label_mask),
-         offsetof(tp_survey_result, kernel_ms));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(tp_graph_stats, phase_ms), offsetof(tp_survey_spec, label_mask),
+         offsetof(tp_survey_result, kernel_ms), offsetof(tp_graph_stats, class_probes),
+         offsetof(tp_survey_result, class_ms));
   printf("%u %u %u %u\\n", TP_RW_TABLE, TP_RW_OPEN_CLOSE, TP_RW_SCRATCH, TP_RESULT_WORDS);
   return 0;
 }
@@ -59,7 +60,8 @@ int main(void) {
     assert list(map(int, l1.split())) == [ctypes.sizeof(tp.tp_edge_list), ctypes.sizeof(tp.tp_graph_stats),
                                           ctypes.sizeof(tp.tp_survey_spec), ctypes.sizeof(tp.tp_survey_result)]
     assert list(map(int, l2.split())) == [tp.tp_graph_stats.phase_ms.offset, tp.tp_survey_spec.label_mask.offset,
-                                          tp.tp_survey_result.kernel_ms.offset]
+                                          tp.tp_survey_result.kernel_ms.offset, tp.tp_graph_stats.class_probes.offset,
+                                          tp.tp_survey_result.class_ms.offset]
     assert list(map(int, l3.split())) == [tp.TP_RW_TABLE, tp.TP_RW_OPEN_CLOSE, tp.TP_RW_SCRATCH,
                                           tp.TP_RESULT_WORDS]
 

@@ -86,7 +86,7 @@ def test_complete_graphs(torch_cuda, n):
     ts = (np.arange(len(src)) * 7919 % 100000).astype(np.uint32)
     vlab = (np.arange(n) % 4).astype(np.uint8)
     say("K_%d" % n)
-    ref, st = check_graph(torch_cuda, n, src, dst, ts, vlab, 4, strategies=(0, 1))
+    ref, st = check_graph(torch_cuda, n, src, dst, ts, vlab, 4, strategies=(0, 1, 2))
     assert ref["triangles"] == math.comb(n, 3)
 
 
@@ -180,7 +180,7 @@ def test_random_graphs_against_oracle(torch_cuda, seed):
     vlab = rng.integers(0, L, n).astype(np.uint8)
     say("random seed", seed, n, M, L)
     check_graph(torch_cuda, n, src, dst, ts, vlab, L, spread_lt=int(rng.integers(0, 1 << 20)),
-                strategies=(0, 1), device=bool(seed % 2))
+                strategies=(0, 1, 2), device=bool(seed % 2))
 
 
 def test_filters_against_oracle(torch_cuda):
@@ -199,7 +199,7 @@ def test_workload1_scale12(torch_cuda):
     g = synth.generate(w.graph)
     say("workload 1")
     ref, st = check_graph(torch_cuda, g["n"], g["src"], g["dst"], g["ts"], g["vlab"], 4,
-                          strategies=(0, 1), tie=tp.TP_TIE_MIX)
+                          strategies=(0, 1, 2), tie=tp.TP_TIE_MIX)
     assert ref["triangles"] > 100000
 
 
