@@ -32,7 +32,9 @@ namespace {
 
 constexpr int kSmallBlock = 256;   // 4 waves share a small target's tables
 constexpr int kLargeBlock = 1024;  // 16 waves share a large target's tables
-constexpr int kUnroll = 8;         // rows of 64 candidates per batch; two batches in flight
+constexpr int kSub = 4;            // sub-rows of 64 candidates per chunk
+constexpr uint32_t kChunkCand = kSub * 64;  // candidates per chunk of a record
+constexpr int kBatch = 2;          // chunks per batch; two batches in flight
 constexpr uint32_t kRing = 128;    // per-wave ring of queued hits: slot|label(p), time(p,r), time(p,q), p
 constexpr uint64_t kChunk = 4;     // tiles claimed at a time by a workgroup
 constexpr int kRsrcWord3 = 0x00020000;  // buffer resource word 3 for raw 32-bit loads on CDNA
@@ -416,21 +418,22 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
             uint32_t off = 0; // next slot of the current record
             uint32_t wave_work = 0, wave_hits = 0;
 
-            // next row: valid lanes and the record's metadata; returns the
-            // row's first slot
-            struct Row {
+            // next chunk of up to kChunkCand candidates of the current
+            // record: its size and the record's metadata; returns the
+            // chunk's first slot
+            struct Chunk {
                 uint32_t n, t_pq, l_p, p;
             };
-            auto next_row = [&](Row &rw) -> uint64_t {
+            auto next_chunk = [&](Chunk &ch) -> uint64_t {
                 uint64_t base = 0;
                 if (i < nw) {
                     base = rec.start + off;
-                    rw.n = min(rec.len - off, (uint32_t)kWave);
-                    rw.t_pq = rec.t_pq;
-                    rw.l_p = rec.l_p;
-                    rw.p = rec.p;
-                    wave_work += rw.n;
-                    off += kWave;
+                    ch.n = min(rec.len - off, kChunkCand);
+                    ch.t_pq = rec.t_pq;
+                    ch.l_p = rec.l_p;
+                    ch.p = rec.p;
+                    wave_work += ch.n;
+                    off += kChunkCand;
                     if (off >= rec.len) {
                         off = 0;
                         ++i;
@@ -443,38 +446,47 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                         }
                     }
                 } else {
-                    rw.n = 0;
-                    rw.t_pq = 0;
-                    rw.l_p = 0;
-                    rw.p = 0;
+                    ch.n = 0;
+                    ch.t_pq = 0;
+                    ch.l_p = 0;
+                    ch.p = 0;
                 }
                 return base;
             };
-            // issue the loads of kUnroll rows: buffer loads whose resource
-            // covers exactly the row's valid slots (other lanes read 0)
-            auto prepare = [&](Row(&rows)[kUnroll], uint32_t(&cand)[kUnroll], uint32_t(&tpr)[kUnroll]) {
+            // issue the loads of kBatch chunks: lane l of sub-row s reads
+            // candidate 64 s + l; the buffer resource spans exactly the
+            // chunk, so lanes past its end read 0 without touching memory
+            auto prepare = [&](Chunk(&chs)[kBatch], uint32_t(&cand)[kBatch][kSub], uint32_t(&tpr)[kBatch][kSub]) {
 #pragma unroll
-                for (int j = 0; j < kUnroll; ++j) {
-                    const uint64_t base = next_row(rows[j]);
-                    const uint32_t bytes = rows[j].n * 4u;
-                    cand[j] = __builtin_amdgcn_raw_buffer_load_b32(
-                        __builtin_amdgcn_make_buffer_rsrc((void *)(P.col + base), (short)0, bytes, kRsrcWord3),
-                        lane * 4u, 0, 0);
-                    if (META || ENUM)
-                        tpr[j] = __builtin_amdgcn_raw_buffer_load_b32(
-                            __builtin_amdgcn_make_buffer_rsrc((void *)(P.ets + base), (short)0, bytes, kRsrcWord3),
-                            lane * 4u, 0, 0);
+                for (int c = 0; c < kBatch; ++c) {
+                    const uint64_t base = next_chunk(chs[c]);
+                    const uint32_t bytes = chs[c].n * 4u;
+                    const auto rc = __builtin_amdgcn_make_buffer_rsrc((void *)(P.col + base), (short)0, bytes, kRsrcWord3);
+#pragma unroll
+                    for (int sr = 0; sr < kSub; ++sr)
+                        cand[c][sr] = __builtin_amdgcn_raw_buffer_load_b32(rc, lane * 4u + sr * 256u, 0, 0);
+                    if (META || ENUM) {
+                        const auto rt =
+                            __builtin_amdgcn_make_buffer_rsrc((void *)(P.ets + base), (short)0, bytes, kRsrcWord3);
+#pragma unroll
+                        for (int sr = 0; sr < kSub; ++sr)
+                            tpr[c][sr] = __builtin_amdgcn_raw_buffer_load_b32(rt, lane * 4u + sr * 256u, 0, 0);
+                    }
                 }
             };
-            auto process = [&](const Row(&rows)[kUnroll], const uint32_t(&cand)[kUnroll],
-                               const uint32_t(&tpr)[kUnroll]) {
+            auto process = [&](const Chunk(&chs)[kBatch], const uint32_t(&cand)[kBatch][kSub],
+                               const uint32_t(&tpr)[kBatch][kSub]) {
 #pragma unroll
-                for (int j = 0; j < kUnroll; ++j) {
-                    if (rows[j].n == 0) continue;
-                    const uint32_t r = cand[j];
-                    bool hit = false;
-                    uint32_t slot = 0;
-                    if (lane < rows[j].n) {
+                for (int c = 0; c < kBatch; ++c) {
+#pragma unroll
+                    for (int sr = 0; sr < kSub; ++sr) {
+                        if (chs[c].n <= (uint32_t)(sr * kWave)) break;
+                        const uint32_t nsub = min(chs[c].n - sr * kWave, (uint32_t)kWave);
+                        // lanes >= nsub hold no candidate (they read 0): mask their hits
+                        const uint64_t live = nsub >= (uint32_t)kWave ? ~0ull : ((1ull << nsub) - 1);
+                        const uint32_t r = cand[c][sr];
+                        bool hit;
+                        uint32_t slot;
                         if (!gmode) {
                             // two independent reads, no loop
                             const uint32_t h0 = hash0(r, log_s), h1 = (1u << log_s) + hash1(r, log_s);
@@ -491,31 +503,35 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                                 }
                             }
                         } else {
-                            const int64_t at = global_find(P.col, kq, dq, r);
-                            hit = at >= 0;
-                            slot = (uint32_t)(at - (int64_t)kq);
+                            hit = false;
+                            slot = 0;
+                            if (lane < nsub) {
+                                const int64_t at = global_find(P.col, kq, dq, r);
+                                hit = at >= 0;
+                                slot = (uint32_t)(at - (int64_t)kq);
+                            }
                         }
-                    }
-                    const uint64_t m = __ballot(hit);
-                    if (!META && !ENUM) {
-                        wave_hits += (uint32_t)__popcll(m);
-                        continue;
-                    }
-                    if (m) {
-                        if (hit) {
-                            const uint32_t pos = qt + (uint32_t)__popcll(m & lt_mask);
-                            ring[pos & (kRing - 1)] = make_uint4(slot | (rows[j].l_p << 22), tpr[j], rows[j].t_pq,
-                                                                 rows[j].p);
+                        const uint64_t m = __ballot(hit) & live;
+                        if (!META && !ENUM) {
+                            wave_hits += (uint32_t)__popcll(m);
+                            continue;
                         }
-                        qt += (uint32_t)__popcll(m);
-                        if (qt - qh >= (uint32_t)kWave) drain(kWave);
+                        if (m) {
+                            if ((m >> lane) & 1ull) {
+                                const uint32_t pos = qt + (uint32_t)__popcll(m & lt_mask);
+                                ring[pos & (kRing - 1)] =
+                                    make_uint4(slot | (chs[c].l_p << 22), tpr[c][sr], chs[c].t_pq, chs[c].p);
+                            }
+                            qt += (uint32_t)__popcll(m);
+                            if (qt - qh >= (uint32_t)kWave) drain(kWave);
+                        }
                     }
                 }
             };
             // two batches in flight: the next batch's loads are issued before
             // the current batch is probed
-            Row rA[kUnroll], rB[kUnroll];
-            uint32_t cA[kUnroll], tA[kUnroll], cB[kUnroll], tB[kUnroll];
+            Chunk rA[kBatch], rB[kBatch];
+            uint32_t cA[kBatch][kSub], tA[kBatch][kSub], cB[kBatch][kSub], tB[kBatch][kSub];
             prepare(rA, cA, tA);
             for (;;) {
                 prepare(rB, cB, tB);
