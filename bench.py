@@ -32,8 +32,10 @@ METRIC = "triangles surveyed/s + HBM GB/s at R-MAT scale 26; p50/p99 survey late
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2107_12330_amd", "csrc", "survey.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "survey_traffic.json")
-CLASS_NAMES = ("survey_kernel<11,META> (d+(q) <= 1024, LDS hash)", "survey_kernel<13,META> (d+(q) <= 4096, LDS hash)",
-               "survey_kernel<0,META> (d+(q) > 4096, HBM binary search)")
+CLASS_NAMES = ("survey_kernel<10,256,META> (d+(q) <= 819, LDS cuckoo tables)",
+               "survey_kernel<12,1024,META> (d+(q) <= 3276, LDS cuckoo tables)",
+               "survey_kernel<0,256,META> (d+(q) > 3276, HBM binary search)")
+TRAFFIC_KEYS = ("survey_kernel<10,256,%s>", "survey_kernel<12,1024,%s>", "survey_kernel<0,256,%s>")
 
 
 def log(*a):
@@ -60,17 +62,19 @@ def algorithmic_bytes(st: dict, c: int, meta: bool) -> int:
             + 32 * st["class_tiles"][c])
 
 
-def load_traffic(meta: bool, workload_name: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source and this workload."""
+def load_traffic(meta: bool, workload_name: str, cls: int):
+    """HBM bytes per launch of class `cls`'s kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source and this
+    workload (else None)."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if rec.get("kernel_hash") != kernel_source_hash() or rec.get("workload") != workload_name:
         return None
-    key = "meta" if meta else "count"
-    return rec.get(key, {}).get("hbm_bytes_per_launch")
+    k = TRAFFIC_KEYS[cls] % ("true" if meta else "false")
+    v = rec.get("kernels", {}).get(k)
+    return None if v is None else int(v["hbm_bytes_per_launch"])
 
 
 def cpu_baseline(scale: int, threads: int) -> dict:
@@ -190,10 +194,11 @@ def main():
     c = int(np.argmax(cls_ms))
     alg = algorithmic_bytes(st, c, meta)
     achieved = alg / (cls_ms[c] * 1e-3) / 1e9
-    traffic = load_traffic(meta, w.name)
+    traffic = load_traffic(meta, w.name, c)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": CLASS_NAMES[c].replace("META", "true" if meta else "false"),
+                "traffic_per_algorithmic_byte": None if traffic is None else round(traffic / alg, 3),
                 "kernel_ms": round(cls_ms[c], 3), "algorithmic_bytes": int(alg),
                 "wedge_checks": int(st["class_probes"][c])}
 
