@@ -107,7 +107,7 @@ typedef struct {
                                   5 CSR+metadata, 6 in-edge index, 7 survey plan */
     float build_ms;            /* sum of phase_ms */
     uint32_t reserved2;
-    /* survey plan per target class (0: d+(q) <= 1024, 1: <= 4096, 2: larger) */
+    /* survey plan per target class (0: d+(q) <= 819, 1: <= 3276, 2: larger) */
     uint64_t class_tiles[3];   /* tiles */
     uint64_t class_records[3]; /* in-edge records (one per oriented edge p -> q) */
     uint64_t class_staged[3];  /* sum over tiles of d+(q): out-list entries loaded per survey */
@@ -248,6 +248,99 @@ tp_status tripoll_survey_async(const tp_graph *g, const tp_survey_spec *spec, ui
  */
 tp_status tripoll_enumerate(const tp_graph *g, uint32_t *dev_records, uint64_t capacity,
                             uint64_t *n_found, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batches of independent graphs                                             */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Many independent raw edge lists, built and surveyed together.  A batch is
+ * one disjoint union; every graph is cleaned and degree-ordered within
+ * itself (Preliminaries), and since no triangle spans two graphs the survey
+ * of the union, split per graph, is the survey of each graph (Algorithm 1 on
+ * each part).  Graph g owns raw edges [edge_offsets[g], edge_offsets[g+1])
+ * of src/dst/edge_time, whose ids are local to it, in [0, vertex_counts[g]);
+ * its labels are vertex_label[voff[g] + i] for local id i, where voff is the
+ * running sum of vertex_counts (voff[0] = 0).
+ *   n_graphs       >= 1
+ *   edge_offsets   uint64[n_graphs + 1] in host memory; edge_offsets[0] = 0,
+ *                  non-decreasing; the last entry is the total raw edge count
+ *   vertex_counts  uint32[n_graphs] in host memory; 0 allowed (a graph with
+ *                  no vertices must own no edges); the sum is < 2^32 - 1
+ *   src, dst, edge_time, vertex_label, mem_space, tie_hash: as in
+ *                  tp_edge_list, concatenated over the graphs
+ */
+typedef struct {
+    uint32_t n_graphs;
+    uint32_t mem_space;
+    const uint64_t *edge_offsets;
+    const uint32_t *vertex_counts;
+    const uint32_t *src;
+    const uint32_t *dst;
+    const uint32_t *edge_time;
+    const uint8_t *vertex_label;
+    uint32_t tie_hash;
+    uint32_t reserved;
+} tp_batch_edges;
+
+/*
+ * Build a batch as one tp_graph whose vertices are grouped by graph (graph
+ * g holds ranks [voff[g], voff[g+1]) of the degree order).  The whole batch
+ * shares one survey plan, so one persistent kernel per target class covers
+ * every graph.  Synchronous.  Graph statistics are those of the union.
+ * Errors: as tripoll_build; TP_ERR_INVALID also for decreasing offsets, an
+ * edge whose local id is >= its graph's vertex count, or a batch whose
+ * graph, degree and vertex bits exceed one 64-bit order key.
+ */
+tp_status tripoll_build_batch(const tp_batch_edges *batch, void *stream, tp_graph **out);
+
+/* Number of graphs of a batch (1 for a graph from tripoll_build). */
+tp_status tripoll_graph_count(const tp_graph *g, uint32_t *n_graphs);
+
+/*
+ * Per-graph result block of a batch survey, in uint64 words:
+ *   [TP_BW_TRIANGLES] [TP_BW_SPREAD] [TP_BW_PROBES] [TP_BW_HIST, +32)
+ *   then C(n_labels+2, 3) label-table words if LABEL_TABLE is requested,
+ *   then 32*32 open/close words if OPEN_CLOSE is requested.
+ * tripoll_batch_words(spec) returns the block length (0 for a NULL spec).
+ */
+#define TP_BW_TRIANGLES 0u
+#define TP_BW_SPREAD 1u
+#define TP_BW_PROBES 2u
+#define TP_BW_HIST 3u
+#define TP_BW_TABLE 35u
+#define TP_BATCH_SCRATCH_WORDS 4u
+uint64_t tripoll_batch_words(const tp_survey_spec *spec);
+
+/*
+ * Survey every graph of a batch (Algorithm 1 with the reductions above,
+ * reported per graph).  Enqueued on `stream`; allocates nothing; may be
+ * recorded into a HIP graph by the caller.
+ *   dev_out  device buffer of n_graphs * tripoll_batch_words(spec) +
+ *            TP_BATCH_SCRATCH_WORDS uint64, owned by the caller: block g
+ *            starts at word g * tripoll_batch_words(spec); the last
+ *            TP_BATCH_SCRATCH_WORDS words are work counters.  Overwritten
+ *            by work ordered on `stream`; one survey in flight per buffer.
+ * Errors: as tripoll_survey.
+ */
+tp_status tripoll_survey_batch(const tp_graph *g, const tp_survey_spec *spec, uint64_t *dev_out, void *stream);
+
+/*
+ * A recorded survey launch: the fills and persistent kernels of
+ * tripoll_survey_batch for one graph, spec and output buffer, captured once
+ * into an executable HIP graph and replayed with one launch call.
+ *   tripoll_survey_capture  records it (synchronous); `dev_out` as for
+ *                           tripoll_survey_batch and bound to the launch
+ *   tripoll_launch_replay   enqueues one replay on `stream`; replays on one
+ *                           launch must not overlap (they share dev_out)
+ *   tripoll_launch_free     releases it (NULL accepted); the graph must
+ *                           outlive the launch
+ */
+typedef struct tp_launch tp_launch;
+tp_status tripoll_survey_capture(const tp_graph *g, const tp_survey_spec *spec, uint64_t *dev_out,
+                                 tp_launch **out);
+tp_status tripoll_launch_replay(tp_launch *launch, void *stream);
+tp_status tripoll_launch_free(tp_launch *launch);
 
 /* Colex index of the label multiset {a, b, c} (any order). */
 uint32_t tripoll_msidx(uint32_t a, uint32_t b, uint32_t c);

@@ -17,6 +17,7 @@
 //   7 plan: split each target's list into tiles and class targets by d+(q)
 #include <algorithm>
 #include <memory>
+#include <vector>
 
 #include "graph.hpp"
 #include "plan.hpp"
@@ -34,14 +35,43 @@ __device__ __forceinline__ uint64_t pair_key(uint32_t lo, uint32_t hi, int nb)
 
 // ------------------------------------------------------------ phase 0
 
+// Graphs of a batch: graph g owns edges [eoff[g], eoff[g+1]) with local
+// vertex ids < vcnt[g], which map to global ids voff[g] + local.
+struct BatchMap {
+    uint32_t n_graphs;
+    const uint64_t *eoff;  // [n_graphs + 1]
+    const uint32_t *voff;  // [n_graphs + 1]
+};
+
+__device__ __forceinline__ uint32_t graph_of_edge(const BatchMap &bm, size_t i)
+{
+    uint32_t a = 0, b = bm.n_graphs;  // eoff[a] <= i < eoff[b]
+    while (b - a > 1) {
+        const uint32_t mid = (a + b) >> 1;
+        if (bm.eoff[mid] <= i) a = mid;
+        else b = mid;
+    }
+    return a;
+}
+
 __global__ void k_canon(const uint32_t *src, const uint32_t *dst, const uint32_t *ts, size_t M, uint32_t n,
                         int nb, uint64_t sentinel, uint64_t *keys, uint32_t *vals, unsigned long long *bad,
-                        unsigned long long *loops)
+                        unsigned long long *loops, BatchMap bm)
 {
     unsigned long long nbad = 0, nloop = 0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < M; i += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t a = src[i], b = dst[i];
-        const bool ok = a < n && b < n;
+        uint32_t a = src[i], b = dst[i];
+        bool ok;
+        if (bm.n_graphs) {
+            // local ids of graph g become global ids
+            const uint32_t g = graph_of_edge(bm, i);
+            const uint32_t base = bm.voff[g], cnt = bm.voff[g + 1] - base;
+            ok = a < cnt && b < cnt;
+            a += base;
+            b += base;
+        } else {
+            ok = a < n && b < n;
+        }
         nbad += ok ? 0 : 1;
         uint64_t k;
         if (!ok || a == b) {
@@ -161,11 +191,29 @@ __device__ __forceinline__ uint32_t tie_mix(uint32_t x, int nb)
     return (uint32_t)y;
 }
 
-__global__ void k_rank_keys(const uint32_t *deg, uint32_t n, int nb, uint32_t tie, uint64_t *rkey, uint32_t *rval)
+// graph of vertex v in a batch: voff[g] <= v < voff[g + 1]
+__device__ __forceinline__ uint32_t graph_of_vertex(const uint32_t *voff, uint32_t n_graphs, uint32_t v)
+{
+    uint32_t a = 0, b = n_graphs;
+    while (b - a > 1) {
+        const uint32_t mid = (a + b) >> 1;
+        if (voff[mid] <= v) a = mid;
+        else b = mid;
+    }
+    return a;
+}
+
+// Sort key of the degree order: (d(v), hash(v)).  In a batch the graph id
+// sits above them, so that every graph owns a contiguous range of ranks (the
+// graphs share no edge, so the order between graphs is free).
+__global__ void k_rank_keys(const uint32_t *deg, uint32_t n, int nb, int gshift, const uint32_t *voff,
+                            uint32_t n_graphs, uint32_t tie, uint64_t *rkey, uint32_t *rval)
 {
     for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
         const uint32_t h = tie == TP_TIE_ID ? (uint32_t)v : tie_mix((uint32_t)v, nb);
-        rkey[v] = ((uint64_t)deg[v] << nb) | h;
+        uint64_t key = ((uint64_t)deg[v] << nb) | h;
+        if (voff) key |= (uint64_t)graph_of_vertex(voff, n_graphs, (uint32_t)v) << gshift;
+        rkey[v] = key;
         rval[v] = (uint32_t)v;
     }
 }
@@ -177,6 +225,14 @@ __global__ void k_rank_scatter(const uint32_t *perm, uint32_t n, const uint8_t *
         rank[v] = (uint32_t)i;
         rlab[i] = vlab ? vlab[v] : 0;
     }
+}
+
+// graph id of every rank in a batch
+__global__ void k_rank_graph(const uint32_t *perm, uint32_t n, const uint32_t *voff, uint32_t n_graphs,
+                             uint32_t *rank_gid)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        rank_gid[i] = graph_of_vertex(voff, n_graphs, perm[i]);
 }
 
 // ------------------------------------------------------------ phase 4
@@ -404,7 +460,13 @@ const T *to_device(const T *p, size_t n, uint32_t space, DArray<T> &hold, hipStr
 
 // ================================================================ build
 
-static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out)
+struct HostBatch {
+    uint32_t n_graphs = 0;
+    std::vector<uint64_t> eoff;  // [n_graphs + 1]
+    std::vector<uint32_t> voff;  // [n_graphs + 1]
+};
+
+static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, const HostBatch *hb = nullptr)
 {
     if (!el || !out) fail(TP_ERR_INVALID, "tripoll_build: NULL argument");
     if (el->mem_space != TP_MEM_HOST && el->mem_space != TP_MEM_DEVICE)
@@ -450,9 +512,21 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out)
     const size_t Mcap = std::max<size_t>(M, 1);
     DArray<uint64_t> keyA(Mcap, s), keyB(Mcap, s);
     DArray<uint32_t> valA(Mcap, s), valB(Mcap, s);
+    BatchMap bm{0, nullptr, nullptr};
+    DArray<uint64_t> d_eoff;
+    DArray<uint32_t> d_voff;
+    if (hb) {
+        d_eoff.reset(hb->n_graphs + 1, s);
+        d_voff.reset(hb->n_graphs + 1, s);
+        TP_HIP(hipMemcpyAsync(d_eoff.get(), hb->eoff.data(), (hb->n_graphs + 1) * sizeof(uint64_t),
+                              hipMemcpyHostToDevice, s));
+        TP_HIP(hipMemcpyAsync(d_voff.get(), hb->voff.data(), (hb->n_graphs + 1) * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, s));
+        bm = BatchMap{hb->n_graphs, d_eoff.get(), d_voff.get()};
+    }
     if (M) {
         k_canon<<<grid_for(M, kB), kB, 0, s>>>(src, dst, ts, M, n, nb, sentinel, keyA.get(), valA.get(), c_bad,
-                                               c_loop);
+                                               c_loop, bm);
         TP_CHECK_LAUNCH();
     }
     unsigned long long hc[2];
@@ -522,14 +596,24 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out)
         // sort keys (d(v), hash(v)) with the vertex as value
         DArray<uint64_t> rkeyA(n, s), rkeyB(n, s);
         DArray<uint32_t> rvalA(n, s), rvalB(n, s);
-        k_rank_keys<<<grid_for(n, kB), kB, 0, s>>>(deg.get(), n, nb, el->tie_hash, rkeyA.get(), rvalA.get());
+        const int gshift = nb + bits_for(mx[0]);
+        const int rbits = gshift + (hb ? bits_for(hb->n_graphs - 1) : 0);
+        if (rbits > 64) fail(TP_ERR_INVALID, "tripoll_build_batch: too many graphs and vertices for one order key");
+        k_rank_keys<<<grid_for(n, kB), kB, 0, s>>>(deg.get(), n, nb, gshift, hb ? d_voff.get() : nullptr,
+                                                   hb ? hb->n_graphs : 0u, el->tie_hash, rkeyA.get(), rvalA.get());
         TP_CHECK_LAUNCH();
-        const int rbits = nb + bits_for(mx[0]);
         const bool rb = radix_sort_pairs(rkeyA.get(), rvalA.get(), rkeyB.get(), rvalB.get(), n, rbits, s);
         g->perm = rb ? std::move(rvalB) : std::move(rvalA);
         g->rlab.reset(n, s);
         k_rank_scatter<<<grid_for(n, kB), kB, 0, s>>>(g->perm.get(), n, vlab, rank.get(), g->rlab.get());
         TP_CHECK_LAUNCH();
+        if (hb) {
+            g->n_graphs = hb->n_graphs;
+            g->rank_gid.reset(n, s);
+            k_rank_graph<<<grid_for(n, kB), kB, 0, s>>>(g->perm.get(), n, d_voff.get(), hb->n_graphs,
+                                                       g->rank_gid.get());
+            TP_CHECK_LAUNCH();
+        }
     }
     h_lab.release();
     TP_HIP(hipEventRecord(ev[4], s));
@@ -679,4 +763,36 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out)
 extern "C" tp_status tripoll_build(const tp_edge_list *edges, void *stream, tp_graph **out)
 {
     return guard([&] { build_impl(edges, (hipStream_t)stream, out); });
+}
+
+extern "C" tp_status tripoll_build_batch(const tp_batch_edges *be, void *stream, tp_graph **out)
+{
+    return guard([&] {
+        if (!be || !out || !be->edge_offsets || !be->vertex_counts || be->n_graphs == 0)
+            fail(TP_ERR_INVALID, "tripoll_build_batch: NULL argument or no graphs");
+        HostBatch hb;
+        hb.n_graphs = be->n_graphs;
+        hb.eoff.assign(be->edge_offsets, be->edge_offsets + be->n_graphs + 1);
+        hb.voff.resize(be->n_graphs + 1);
+        uint64_t nv = 0;
+        hb.voff[0] = 0;
+        for (uint32_t i = 0; i < be->n_graphs; ++i) {
+            if (hb.eoff[i + 1] < hb.eoff[i]) fail(TP_ERR_INVALID, "tripoll_build_batch: edge offsets decrease");
+            nv += be->vertex_counts[i];
+            if (nv >= 0xffffffffull) fail(TP_ERR_INVALID, "tripoll_build_batch: more than 2^32-2 vertices in all");
+            hb.voff[i + 1] = (uint32_t)nv;
+        }
+        if (hb.eoff[0] != 0) fail(TP_ERR_INVALID, "tripoll_build_batch: edge_offsets[0] must be 0");
+        if (nv == 0) fail(TP_ERR_INVALID, "tripoll_build_batch: no vertices");
+        tp_edge_list el{};
+        el.n_vertices = (uint32_t)nv;
+        el.mem_space = be->mem_space;
+        el.n_edges = hb.eoff[be->n_graphs];
+        el.src = be->src;
+        el.dst = be->dst;
+        el.edge_time = be->edge_time;
+        el.vertex_label = be->vertex_label;
+        el.tie_hash = be->tie_hash;
+        build_impl(&el, (hipStream_t)stream, out, &hb);
+    });
 }

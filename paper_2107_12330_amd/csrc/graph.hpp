@@ -37,6 +37,8 @@ struct tp_graph {
     tp::DArray<uint64_t> inkey;   // [n_in] (q << kbits) | k, sorted by q
     tp::DArray<uint32_t> inp;     // [n_in] pivot p of each in-edge
     tp::DArray<TileDesc> tiles[kNumClasses];
+    uint32_t n_graphs = 0;         // > 0 for a batch of disjoint graphs
+    tp::DArray<uint32_t> rank_gid; // [n] graph of each rank (batches only)
     uint64_t n_tiles[kNumClasses] = {0, 0, 0};
     tp_graph_stats stats{};
 };

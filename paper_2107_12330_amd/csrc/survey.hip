@@ -22,6 +22,9 @@
 // split into three classes by d+(q): LDS hash of <= 2048 slots, LDS hash of
 // <= 8192 slots, and binary search of Adj+(q) in HBM for the rest.
 #include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
 
 #include "graph.hpp"
 #include "plan.hpp"
@@ -61,7 +64,10 @@ struct SurveyParams {
     const TileDesc *tiles;
     uint64_t n_tiles;
     unsigned long long *tile_counter;
-    unsigned long long *out;  // TP_RESULT_WORDS
+    unsigned long long *out;  // result words (one block per graph of a batch)
+    const uint32_t *rank_gid; // graph of each rank (batches), or null
+    uint32_t g_stride;        // words per graph block
+    uint32_t o_tri, o_spread, o_probes, o_hist, o_table, o_oc;  // word offsets in a block
     uint32_t outputs, filters;
     uint32_t table_words;     // entries of the label table in LDS (0 if unused)
     uint32_t oc_words;        // 1024 if OPEN_CLOSE else 0
@@ -246,6 +252,34 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     unsigned long long my_tri = 0, my_spread = 0, probes = 0;
     uint32_t qh = 0, qt = 0;  // this wave's hit ring: entries [qh, qt)
 
+    // merge this workgroup's counters into graph g's result block; every
+    // thread of the workgroup calls it
+    auto flush = [&](uint32_t g) {
+        unsigned long long *blk = P.out + (size_t)g * P.g_stride;
+        const unsigned long long t = wave_sum(my_tri), sp = wave_sum(my_spread);
+        if (lane == 0) {
+            if (t) atomicAdd(&blk[P.o_tri], t);
+            if (sp) atomicAdd(&blk[P.o_spread], sp);
+            if (probes) atomicAdd(&blk[P.o_probes], probes);
+        }
+        my_tri = 0;
+        my_spread = 0;
+        probes = 0;
+        __syncthreads();
+        for (uint32_t i = tid; i < nc; i += BLOCK) {
+            const unsigned long long v = cnt[i];
+            if (!v) continue;
+            uint32_t word;
+            if (i < 32) word = P.o_hist + i;
+            else if (i < 32 + P.table_words) word = P.o_table + (i - 32);
+            else word = P.o_oc + (i - 32 - P.table_words);
+            atomicAdd(&blk[word], v);
+            cnt[i] = 0;
+        }
+        __syncthreads();
+    };
+    uint32_t cur_g = 0;  // graph whose counters the workgroup holds
+
     // the target whose out-list is in the LDS table, and its geometry
     uint32_t cur_q = 0xffffffffu;
     uint64_t kq = 0;
@@ -312,6 +346,13 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 // table, then rebuild it once every wave is done with it
                 if (META || ENUM) {
                     if (qt != qh) drain(qt - qh);
+                }
+                if (P.rank_gid) {
+                    const uint32_t g = sload(P.rank_gid + d.q);
+                    if (g != cur_g) {
+                        flush(cur_g);
+                        cur_g = g;
+                    }
                 }
                 __syncthreads();
                 cur_q = d.q;
@@ -552,23 +593,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
         if (qt != qh) drain(qt - qh);
     }
     // ---- merge this workgroup's counters into the result
-    my_tri = wave_sum(my_tri);
-    my_spread = wave_sum(my_spread);
-    if (lane == 0) {
-        if (my_tri) atomicAdd(&P.out[TP_RW_TRIANGLES], my_tri);
-        if (my_spread) atomicAdd(&P.out[TP_RW_SPREAD], my_spread);
-        if (probes) atomicAdd(&P.out[TP_RW_PROBES], probes);
-    }
-    __syncthreads();
-    for (uint32_t i = tid; i < nc; i += BLOCK) {
-        const unsigned long long v = cnt[i];
-        if (!v) continue;
-        uint32_t word;
-        if (i < 32) word = TP_RW_HIST + i;
-        else if (i < 32 + P.table_words) word = TP_RW_TABLE + (i - 32);
-        else word = TP_RW_OPEN_CLOSE + (i - 32 - P.table_words);
-        atomicAdd(&P.out[word], v);
-    }
+    flush(cur_g);
 }
 
 __global__ void zero_u64(unsigned long long *p, size_t n)
@@ -586,13 +611,28 @@ void launch_class(const SurveyParams &P, hipStream_t s, int device)
     const LdsLayout L =
         lds_layout(slots, META || ENUM, counter_words(P.table_words, P.oc_words), BLOCK / kWave, P.lut_shift);
     auto kern = survey_kernel<LOG_SLOTS, BLOCK, META, ENUM>;
-    TP_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total));
-    int per_cu = 0;
-    TP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, L.total));
-    if (per_cu < 1) fail(TP_ERR_DEVICE, "survey kernel does not fit on a compute unit");
-    int cus = 0;
-    TP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
-    uint64_t grid = (uint64_t)per_cu * cus;
+    // attribute and occupancy queries run once per kernel, device and LDS
+    // size, so that a survey recorded into a HIP graph issues launches only
+    static std::mutex mu;
+    static std::map<std::pair<int, size_t>, uint64_t> resident;  // workgroups that fit on the device
+    uint64_t fit = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = resident.find({device, L.total});
+        if (it != resident.end()) fit = it->second;
+    }
+    if (!fit) {
+        TP_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total));
+        int per_cu = 0;
+        TP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, L.total));
+        if (per_cu < 1) fail(TP_ERR_DEVICE, "survey kernel does not fit on a compute unit");
+        int cus = 0;
+        TP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+        fit = (uint64_t)per_cu * cus;
+        std::lock_guard<std::mutex> lock(mu);
+        resident[{device, L.total}] = fit;
+    }
+    uint64_t grid = fit;
     if (grid > P.n_tiles) grid = P.n_tiles;
     zero_u64<<<1, 64, 0, s>>>(P.tile_counter, 1);
     TP_CHECK_LAUNCH();
@@ -653,6 +693,14 @@ SurveyParams make_params(const tp_graph *g, const tp_survey_spec *sp, unsigned l
     P.kbits = g->kbits;
     P.tile_counter = counter;
     P.out = out;
+    P.rank_gid = nullptr;
+    P.g_stride = 0;
+    P.o_tri = TP_RW_TRIANGLES;
+    P.o_spread = TP_RW_SPREAD;
+    P.o_probes = TP_RW_PROBES;
+    P.o_hist = TP_RW_HIST;
+    P.o_table = TP_RW_TABLE;
+    P.o_oc = TP_RW_OPEN_CLOSE;
     P.outputs = sp->outputs | TP_OUT_COUNT;
     P.filters = sp->filters;
     P.table_words = (sp->outputs & TP_OUT_LABEL_TABLE) ? table_size(sp->n_labels) : 0;
@@ -702,6 +750,40 @@ void survey_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned long l
     } else {
         launch_all<false, false>(g, P, sp->strategy, s, timers);
     }
+}
+
+uint32_t batch_words(const tp_survey_spec *sp)
+{
+    uint32_t w = TP_BW_TABLE;
+    if (sp->outputs & TP_OUT_LABEL_TABLE) w += table_size(sp->n_labels);
+    if (sp->outputs & TP_OUT_OPEN_CLOSE) w += 1024;
+    return w;
+}
+
+uint32_t graph_count(const tp_graph *g) { return g->n_graphs ? g->n_graphs : 1u; }
+
+// Enqueue the survey of every graph of a batch into per-graph blocks of
+// `dev_out`, followed by the tile counter.  Allocates nothing.
+void survey_batch_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned long long *dev_out, hipStream_t s)
+{
+    const uint32_t words = batch_words(sp);
+    const uint64_t total = (uint64_t)graph_count(g) * words + TP_BATCH_SCRATCH_WORDS;
+    zero_u64<<<grid_for(total, 256), 256, 0, s>>>(dev_out, total);
+    TP_CHECK_LAUNCH();
+    SurveyParams P = make_params(g, sp, dev_out, dev_out + (total - TP_BATCH_SCRATCH_WORDS));
+    P.rank_gid = g->n_graphs ? g->rank_gid.get() : nullptr;
+    P.g_stride = words;
+    P.o_tri = TP_BW_TRIANGLES;
+    P.o_spread = TP_BW_SPREAD;
+    P.o_probes = TP_BW_PROBES;
+    P.o_hist = TP_BW_HIST;
+    P.o_table = TP_BW_TABLE;
+    P.o_oc = TP_BW_TABLE + P.table_words;
+    if (g->m == 0 || g->n_in == 0) return;
+    if (needs_meta(sp))
+        launch_all<true, false>(g, P, sp->strategy, s);
+    else
+        launch_all<false, false>(g, P, sp->strategy, s);
 }
 
 void copy_result(const std::vector<unsigned long long> &h, tp_survey_result *out)
@@ -768,4 +850,84 @@ extern "C" tp_status tripoll_enumerate(const tp_graph *g, uint32_t *dev_records,
         TP_HIP(hipStreamSynchronize(s));
         *n_found = found;
     });
+}
+
+extern "C" tp_status tripoll_graph_count(const tp_graph *g, uint32_t *n_graphs)
+{
+    return guard([&] {
+        if (!g || !n_graphs) fail(TP_ERR_INVALID, "tripoll_graph_count: NULL argument");
+        *n_graphs = graph_count(g);
+    });
+}
+
+extern "C" uint64_t tripoll_batch_words(const tp_survey_spec *spec)
+{
+    return spec ? batch_words(spec) : 0;
+}
+
+extern "C" tp_status tripoll_survey_batch(const tp_graph *g, const tp_survey_spec *spec, uint64_t *dev_out,
+                                          void *stream)
+{
+    return guard([&] {
+        if (!dev_out) fail(TP_ERR_INVALID, "tripoll_survey_batch: NULL output");
+        validate_spec(g, spec);
+        survey_batch_enqueue(g, spec, reinterpret_cast<unsigned long long *>(dev_out), (hipStream_t)stream);
+    });
+}
+
+// ================================================================ recorded launches
+
+struct tp_launch {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~tp_launch()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+extern "C" tp_status tripoll_survey_capture(const tp_graph *g, const tp_survey_spec *spec, uint64_t *dev_out,
+                                            tp_launch **out)
+{
+    return guard([&] {
+        if (!dev_out || !out) fail(TP_ERR_INVALID, "tripoll_survey_capture: NULL argument");
+        validate_spec(g, spec);
+        // the kernels' attributes are set outside the capture: one eager
+        // survey on a private stream prepares every launch
+        hipStream_t cs = nullptr;
+        TP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        struct StreamGuard {
+            hipStream_t s;
+            ~StreamGuard() { (void)hipStreamDestroy(s); }
+        } sg{cs};
+        survey_batch_enqueue(g, spec, reinterpret_cast<unsigned long long *>(dev_out), cs);
+        TP_HIP(hipStreamSynchronize(cs));
+        auto L = std::make_unique<tp_launch>();
+        TP_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+            survey_batch_enqueue(g, spec, reinterpret_cast<unsigned long long *>(dev_out), cs);
+        } catch (...) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(cs, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            throw;
+        }
+        TP_HIP(hipStreamEndCapture(cs, &L->graph));
+        TP_HIP(hipGraphInstantiate(&L->exec, L->graph, nullptr, nullptr, 0));
+        *out = L.release();
+    });
+}
+
+extern "C" tp_status tripoll_launch_replay(tp_launch *launch, void *stream)
+{
+    return guard([&] {
+        if (!launch) fail(TP_ERR_INVALID, "tripoll_launch_replay: NULL launch");
+        TP_HIP(hipGraphLaunch(launch->exec, (hipStream_t)stream));
+    });
+}
+
+extern "C" tp_status tripoll_launch_free(tp_launch *launch)
+{
+    return guard([&] { delete launch; });
 }

@@ -31,6 +31,8 @@ TP_RW_TABLE = TP_RW_HIST + 32
 TP_RW_OPEN_CLOSE = TP_RW_TABLE + TP_TABLE_MAX
 TP_RW_SCRATCH = TP_RW_OPEN_CLOSE + 1024
 TP_RESULT_WORDS = TP_RW_SCRATCH + 4
+TP_BW_TRIANGLES, TP_BW_SPREAD, TP_BW_PROBES, TP_BW_HIST, TP_BW_TABLE = 0, 1, 2, 3, 35
+TP_BATCH_SCRATCH_WORDS = 4
 
 OUT_BITS = {"count": TP_OUT_COUNT, "close_hist": TP_OUT_CLOSE_HIST, "label_table": TP_OUT_LABEL_TABLE,
             "spread_count": TP_OUT_SPREAD_COUNT, "open_close": TP_OUT_OPEN_CLOSE}
@@ -40,6 +42,13 @@ class tp_edge_list(ctypes.Structure):
     _fields_ = [("n_vertices", ctypes.c_uint32), ("mem_space", ctypes.c_uint32), ("n_edges", ctypes.c_uint64),
                 ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("edge_time", ctypes.c_void_p),
                 ("vertex_label", ctypes.c_void_p), ("tie_hash", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class tp_batch_edges(ctypes.Structure):
+    _fields_ = [("n_graphs", ctypes.c_uint32), ("mem_space", ctypes.c_uint32), ("edge_offsets", ctypes.c_void_p),
+                ("vertex_counts", ctypes.c_void_p), ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
+                ("edge_time", ctypes.c_void_p), ("vertex_label", ctypes.c_void_p), ("tie_hash", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class tp_graph_stats(ctypes.Structure):
@@ -84,6 +93,13 @@ SIGNATURES = {
     "tripoll_survey": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), ctypes.POINTER(tp_survey_result), _P]),
     "tripoll_survey_async": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, _P]),
     "tripoll_enumerate": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64), _P]),
+    "tripoll_build_batch": (ctypes.c_int, [ctypes.POINTER(tp_batch_edges), _P, ctypes.POINTER(_P)]),
+    "tripoll_graph_count": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32)]),
+    "tripoll_batch_words": (ctypes.c_uint64, [ctypes.POINTER(tp_survey_spec)]),
+    "tripoll_survey_batch": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, _P]),
+    "tripoll_survey_capture": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, ctypes.POINTER(_P)]),
+    "tripoll_launch_replay": (ctypes.c_int, [_P, _P]),
+    "tripoll_launch_free": (ctypes.c_int, [_P]),
     "tripoll_msidx": (ctypes.c_uint32, [ctypes.c_uint32] * 3),
     "tripoll_trim": (ctypes.c_int, []),
     "tripoll_cached_bytes": (ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64)]),
@@ -151,6 +167,40 @@ def tripoll_enumerate(g: int, dev_records: int, capacity: int, stream=None) -> i
     n = ctypes.c_uint64(0)
     _check(load().tripoll_enumerate(g, dev_records, capacity, ctypes.byref(n), stream))
     return n.value
+
+
+def tripoll_build_batch(batch: tp_batch_edges, stream=None) -> int:
+    g = _P()
+    _check(load().tripoll_build_batch(ctypes.byref(batch), stream, ctypes.byref(g)))
+    return g.value
+
+
+def tripoll_graph_count(g: int) -> int:
+    v = ctypes.c_uint32(0)
+    _check(load().tripoll_graph_count(g, ctypes.byref(v)))
+    return v.value
+
+
+def tripoll_batch_words(spec: tp_survey_spec) -> int:
+    return int(load().tripoll_batch_words(ctypes.byref(spec)))
+
+
+def tripoll_survey_batch(g: int, spec: tp_survey_spec, dev_out: int, stream=None) -> None:
+    _check(load().tripoll_survey_batch(g, ctypes.byref(spec), dev_out, stream))
+
+
+def tripoll_survey_capture(g: int, spec: tp_survey_spec, dev_out: int) -> int:
+    h = _P()
+    _check(load().tripoll_survey_capture(g, ctypes.byref(spec), dev_out, ctypes.byref(h)))
+    return h.value
+
+
+def tripoll_launch_replay(launch: int, stream=None) -> None:
+    _check(load().tripoll_launch_replay(launch, stream))
+
+
+def tripoll_launch_free(launch: int) -> None:
+    _check(load().tripoll_launch_free(launch))
 
 
 def tripoll_msidx(a: int, b: int, c: int) -> int:
@@ -287,3 +337,75 @@ def export(graph: Graph) -> dict:
                tlabel=np.empty(m, np.uint8), rank_to_id=np.empty(n, np.uint32), rank_label=np.empty(n, np.uint8))
     tripoll_graph_export(graph.handle, **out)
     return out
+
+
+# ------------------------------------------------------------------ batches
+
+def batch_edges(edge_offsets, vertex_counts, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX,
+                device=None) -> tuple:
+    """Pack a batch into a tp_batch_edges.  Returns (struct, keep-alive host
+    arrays); the offsets and counts are always host arrays."""
+    if device is None:
+        device = not isinstance(src, np.ndarray)
+    eoff = np.ascontiguousarray(edge_offsets, np.uint64)
+    vcnt = np.ascontiguousarray(vertex_counts, np.uint32)
+    be = tp_batch_edges()
+    be.n_graphs = len(vcnt)
+    be.mem_space = TP_MEM_DEVICE if device else TP_MEM_HOST
+    be.edge_offsets, be.vertex_counts = eoff.ctypes.data, vcnt.ctypes.data
+    be.src, be.dst, be.edge_time, be.vertex_label = _addr(src), _addr(dst), _addr(ts), _addr(vlab)
+    be.tie_hash = tie
+    return be, (eoff, vcnt)
+
+
+def build_batch(edge_offsets, vertex_counts, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX, stream=None) -> Graph:
+    be, keep = batch_edges(edge_offsets, vertex_counts, src, dst, ts, vlab, tie)
+    h = tripoll_build_batch(be, stream)
+    del keep
+    return Graph(h)
+
+
+def batch_dicts(words: np.ndarray, n_graphs: int, spec: tp_survey_spec, n_labels: int) -> list:
+    """Unpack the per-graph blocks of a batch result copied to host."""
+    bw = tripoll_batch_words(spec)
+    w = np.asarray(words, np.uint64)[:n_graphs * bw].reshape(n_graphs, bw)
+    ts = table_size(n_labels) if spec.outputs & TP_OUT_LABEL_TABLE else 0
+    oc = TP_BW_TABLE + ts
+    out = []
+    for g in range(n_graphs):
+        r = w[g]
+        d = dict(triangles=int(r[TP_BW_TRIANGLES]), spread_count=int(r[TP_BW_SPREAD]), probes=int(r[TP_BW_PROBES]),
+                 close_hist=r[TP_BW_HIST:TP_BW_HIST + 32].copy())
+        if ts:
+            d["label_table"] = r[TP_BW_TABLE:TP_BW_TABLE + ts].copy()
+        if spec.outputs & TP_OUT_OPEN_CLOSE:
+            d["open_close"] = r[oc:oc + 1024].reshape(32, 32).copy()
+        out.append(d)
+    return out
+
+
+class Launch:
+    """Owning handle of a recorded survey launch."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def replay(self, stream=None):
+        tripoll_launch_replay(self.handle, stream)
+
+    def close(self):
+        if self.handle:
+            tripoll_launch_free(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -209,3 +209,36 @@ def batch_graph_spec(g: int, master: int = MASTER_SEED + 4, scale_lo: int = 6, s
                            ctypes.byref(sg), ctypes.byref(kind), ctypes.byref(sc), ctypes.byref(ef))
     return GraphSpec("er" if kind.value else "rmat", sc.value, ef.value, sg.value,
                      ("uniform", 20), ("uniform", 8))
+
+
+def batch_specs(n_graphs: int, master: int = MASTER_SEED + 4, scale_lo: int = 6, scale_hi: int = 16,
+                ef_lo: int = 4, ef_hi: int = 32) -> list:
+    """Recipes of graphs 0..n_graphs-1 of a batch (see batch_graph_spec)."""
+    return [batch_graph_spec(g, master, scale_lo, scale_hi, ef_lo, ef_hi) for g in range(n_graphs)]
+
+
+def batch_offsets(specs: list) -> tuple:
+    """(edge_offsets uint64[G+1], vertex_counts uint32[G]) of a batch."""
+    eoff = np.zeros(len(specs) + 1, np.uint64)
+    eoff[1:] = np.cumsum([s.n_edges for s in specs], dtype=np.uint64)
+    vcnt = np.array([s.n for s in specs], np.uint32)
+    return eoff, vcnt
+
+
+def generate_batch(specs: list) -> dict:
+    """Concatenated raw inputs of a batch: src, dst, ts (uint32, local ids),
+    vlab (uint8), edge_offsets, vertex_counts."""
+    eoff, vcnt = batch_offsets(specs)
+    M, N = int(eoff[-1]), int(vcnt.sum())
+    src = np.empty(M, np.uint32)
+    dst = np.empty(M, np.uint32)
+    ts = np.empty(M, np.uint32)
+    vlab = np.empty(N, np.uint8)
+    v0 = 0
+    for i, s in enumerate(specs):
+        e0, e1 = int(eoff[i]), int(eoff[i + 1])
+        fill_edges(s, src[e0:e1], dst[e0:e1])
+        fill_ts(s, ts[e0:e1])
+        fill_labels(s, vlab[v0:v0 + s.n])
+        v0 += s.n
+    return dict(src=src, dst=dst, ts=ts, vlab=vlab, edge_offsets=eoff, vertex_counts=vcnt)
