@@ -95,12 +95,167 @@ def cpu_baseline(scale: int, threads: int) -> dict:
                       % (threads, scale, r["triangles"], dt)}
 
 
+def batch_bench(args, torch, synth, tp) -> dict:
+    """Batched form: every graph of the batch built and surveyed together,
+    against the same graphs built and surveyed one launch sequence each.
+
+    A step is tripoll_build_batch + tripoll_survey_batch + readback of all
+    per-graph results.  The recorded (HIP graph) survey launch is timed
+    separately by replays on the resident batch.  The one-graph loop
+    (tripoll_build + tripoll_survey per graph, synchronous) runs on every
+    k-th graph; its total is that sample's time times k, an unbiased
+    estimate of the loop over all graphs, and the sampled graphs' results
+    must equal their blocks of the batch result."""
+    w = synth.workload(4)
+    ex = w.extra
+    G = args.graphs or ex["n_graphs"]
+    specs = synth.batch_specs(G, scale_lo=ex["scale_lo"], scale_hi=ex["scale_hi"], ef_lo=ex["ef_lo"],
+                              ef_hi=ex["ef_hi"])
+    eoff, vcnt = synth.batch_offsets(specs)
+    M, N = int(eoff[-1]), int(vcnt.sum())
+    stream = torch.cuda.current_stream()
+    sptr = stream.cuda_stream
+    log("batch of %d graphs: %d vertices, %d raw edges; generating" % (G, N, M))
+    t0 = time.perf_counter()
+    src = torch.empty(M, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    ts = torch.empty_like(src)
+    vlab = torch.empty(N, dtype=torch.uint8, device="cuda")
+    v0 = 0
+    chunk = 1000
+    for lo in range(0, G, chunk):
+        hi = min(G, lo + chunk)
+        d = synth.generate_batch(specs[lo:hi])
+        e0, e1 = int(eoff[lo]), int(eoff[hi])
+        for dev, k in ((src, "src"), (dst, "dst"), (ts, "ts")):
+            dev[e0:e1].copy_(torch.from_numpy(d[k].view(np.int32)))
+        vlab[v0:v0 + len(d["vlab"])].copy_(torch.from_numpy(d["vlab"]))
+        v0 += len(d["vlab"])
+        del d
+        log("  graphs %d..%d generated (%.1f s)" % (lo, hi, time.perf_counter() - t0))
+    torch.cuda.synchronize()
+    outputs = w.outputs
+    spec = tp.make_spec(outputs=outputs, n_labels=w.n_labels)
+    bw = tp.tripoll_batch_words(spec)
+    out = torch.zeros(G * bw + tp.TP_BATCH_SCRATCH_WORDS, dtype=torch.int64, device="cuda")
+    be, keep = tp.batch_edges(eoff, vcnt, src, dst, ts, vlab, device=True)
+
+    def step():
+        h = tp.tripoll_build_batch(be, sptr)
+        try:
+            st = tp.stats_dict(tp.tripoll_graph_stats(h))
+            tp.tripoll_survey_batch(h, spec, out.data_ptr(), sptr)
+            words = out.cpu().numpy().view(np.uint64)  # synchronises the stream
+        finally:
+            tp.tripoll_graph_free(h)
+        return st, words
+
+    for i in range(args.warmup):
+        st, words = step()
+        log("warmup %d: build %.1f ms" % (i, st["build_ms"]))
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    per = []
+    for i in range(args.steps):
+        s0 = time.perf_counter()
+        st, words = step()
+        per.append(time.perf_counter() - s0)
+        log("step %d: %.1f ms (build %.1f)" % (i, per[-1] * 1e3, st["build_ms"]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_per_step = wall * 1e3 / args.steps
+    res = tp.batch_dicts(words, G, spec, w.n_labels)
+    tri = sum(r["triangles"] for r in res)
+    probes = sum(r["probes"] for r in res)
+
+    # recorded launch on the resident batch
+    h = tp.tripoll_build_batch(be, sptr)
+    rec_ms = []
+    try:
+        st = tp.stats_dict(tp.tripoll_graph_stats(h))
+        rec = torch.zeros_like(out)
+        with tp.Launch(tp.tripoll_survey_capture(h, spec, rec.data_ptr())) as L:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            for i in range(max(3, args.steps)):
+                e0.record(stream)
+                L.replay(sptr)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                rec_ms.append(e0.elapsed_time(e1))
+        assert np.array_equal(rec.cpu().numpy().view(np.uint64), words), "recorded launch differs from eager"
+    finally:
+        tp.tripoll_graph_free(h)
+    log("recorded survey: %s ms" % ["%.2f" % x for x in rec_ms])
+
+    # one graph per launch sequence, on every k-th graph
+    k = max(1, args.loop_stride)
+    sample = list(range(0, G, k))
+    log("one-graph loop on %d sampled graphs" % len(sample))
+    loop_build = loop_survey = 0.0
+    v0s = np.concatenate([[0], np.cumsum(vcnt.astype(np.int64))])
+    torch.cuda.synchronize()
+    for g in sample:
+        e0, e1 = int(eoff[g]), int(eoff[g + 1])
+        n = int(vcnt[g])
+        if n == 0:
+            continue
+        el = tp.edge_list(n, src[e0:e1], dst[e0:e1], ts[e0:e1], vlab[int(v0s[g]):int(v0s[g + 1])], device=True)
+        t0 = time.perf_counter()
+        hg = tp.tripoll_build(el, sptr)
+        t1 = time.perf_counter()
+        try:
+            r1 = tp.result_dict(tp.tripoll_survey(hg, spec, sptr), w.n_labels)
+        finally:
+            tp.tripoll_graph_free(hg)
+        t2 = time.perf_counter()
+        loop_build += t1 - t0
+        loop_survey += t2 - t1
+        assert r1["triangles"] == res[g]["triangles"], g
+        assert np.array_equal(r1["close_hist"], res[g]["close_hist"]), g
+    loop_total_est = (loop_build + loop_survey) * k
+
+    return {
+        "metric": METRIC,
+        "value": tri / (ms_per_step * 1e-3),
+        "unit": "triangles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": w.name if G == ex["n_graphs"] else "batch-%d" % G, "graphs": G,
+                   "scale_range": [ex["scale_lo"], ex["scale_hi"]], "edge_factor_range": [ex["ef_lo"], ex["ef_hi"]],
+                   "kinds": "R-MAT or Erdos-Renyi 50/50", "raw_edges": M, "vertices": N, "edges": st["n_edges"],
+                   "outputs": list(outputs),
+                   "step": "batch build + batch survey + readback of every graph's counters"},
+        "result": {"triangles": tri, "wedge_checks": probes, "graphs_per_s": G / (ms_per_step * 1e-3)},
+        "batch": {"build_ms": round(st["build_ms"], 2), "build_phase_ms": [round(x, 2) for x in st["phase_ms"]],
+                  "recorded_survey_ms_p50": round(statistics.median(rec_ms), 3),
+                  "recorded_survey_triangles_per_s": tri / (statistics.median(rec_ms) * 1e-3),
+                  "tiles": st["class_tiles"]},
+        "one_graph_loop": {"sampled_graphs": len(sample), "stride": k,
+                           "build_s_est": round(loop_build * k, 3), "survey_s_est": round(loop_survey * k, 3),
+                           "total_s_est": round(loop_total_est, 3),
+                           "batched_speedup": round(loop_total_est / (ms_per_step * 1e-3), 2),
+                           "survey_speedup_recorded": round(loop_survey * k / (statistics.median(rec_ms) * 1e-3),
+                                                            2)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", type=int, default=3, choices=(1, 2, 3))
+    ap.add_argument("--workload", type=int, default=3, choices=(1, 2, 3, 4))
+    ap.add_argument("--graphs", type=int, default=None, help="batch size override (workload 4)")
+    ap.add_argument("--loop-stride", type=int, default=10,
+                    help="workload 4: time the one-graph-per-launch loop on every k-th graph")
     ap.add_argument("--scale", type=int, default=None, help="override the R-MAT scale (same recipe)")
     ap.add_argument("--count-only", action="store_true", help="survey the triangle count only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -123,6 +278,10 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     sptr = stream.cuda_stream
+
+    if args.workload == 4:
+        print(json.dumps(batch_bench(args, torch, synth, tp)), flush=True)
+        return
 
     w = synth.workload(args.workload, scale=args.scale)
     gs = w.graph

@@ -54,17 +54,25 @@ __device__ __forceinline__ uint32_t graph_of_edge(const BatchMap &bm, size_t i)
     return a;
 }
 
+// Each workgroup canonicalises one contiguous span of `per_block` raw edges,
+// so in a batch a thread finds the graph of its first edge by binary search
+// and then only steps forward through the edge offsets.
 __global__ void k_canon(const uint32_t *src, const uint32_t *dst, const uint32_t *ts, size_t M, uint32_t n,
                         int nb, uint64_t sentinel, uint64_t *keys, uint32_t *vals, unsigned long long *bad,
-                        unsigned long long *loops, BatchMap bm)
+                        unsigned long long *loops, BatchMap bm, size_t per_block)
 {
     unsigned long long nbad = 0, nloop = 0;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < M; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t begin = blockIdx.x * per_block;
+    const size_t end = begin + per_block < M ? begin + per_block : M;
+    size_t i = begin + threadIdx.x;
+    uint32_t g = 0;
+    if (bm.n_graphs && i < end) g = graph_of_edge(bm, i);
+    for (; i < end; i += blockDim.x) {
         uint32_t a = src[i], b = dst[i];
         bool ok;
         if (bm.n_graphs) {
             // local ids of graph g become global ids
-            const uint32_t g = graph_of_edge(bm, i);
+            while (bm.eoff[g + 1] <= i) ++g;
             const uint32_t base = bm.voff[g], cnt = bm.voff[g + 1] - base;
             ok = a < cnt && b < cnt;
             a += base;
@@ -525,8 +533,10 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
         bm = BatchMap{hb->n_graphs, d_eoff.get(), d_voff.get()};
     }
     if (M) {
-        k_canon<<<grid_for(M, kB), kB, 0, s>>>(src, dst, ts, M, n, nb, sentinel, keyA.get(), valA.get(), c_bad,
-                                               c_loop, bm);
+        const unsigned blocks = grid_for(M, kB);
+        const size_t per_block = (M + blocks - 1) / blocks;
+        k_canon<<<blocks, kB, 0, s>>>(src, dst, ts, M, n, nb, sentinel, keyA.get(), valA.get(), c_bad, c_loop, bm,
+                                      per_block);
         TP_CHECK_LAUNCH();
     }
     unsigned long long hc[2];
