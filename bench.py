@@ -32,10 +32,23 @@ METRIC = "triangles surveyed/s + HBM GB/s at R-MAT scale 26; p50/p99 survey late
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2107_12330_amd", "csrc", "survey.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "survey_traffic.json")
-CLASS_NAMES = ("survey_kernel<10,256,META> (d+(q) <= 819, LDS cuckoo tables)",
-               "survey_kernel<12,1024,META> (d+(q) <= 3276, LDS cuckoo tables)",
-               "survey_kernel<0,256,META> (d+(q) > 3276, HBM binary search)")
-TRAFFIC_KEYS = ("survey_kernel<10,256,%s>", "survey_kernel<12,1024,%s>", "survey_kernel<0,256,%s>")
+CLASS_NAMES = ("tiny (d+(q) <= 51)", "small (d+(q) <= 819)", "large (d+(q) <= 3276)", "huge (d+(q) > 3276)")
+VARIANT_NAMES = {1: "LDS cuckoo tables, one per wave", 2: "LDS cuckoo tables, one per workgroup",
+                 3: "HBM binary search, a workgroup per tile", 4: "HBM binary search, a wave per tile"}
+
+
+def resolve_variant(c: int, v: int) -> int:
+    """The variant a class runs with (the library's default when 0)."""
+    return v if v else {0: 1, 1: 2, 2: 2, 3: 3}[c]
+
+
+def kernel_key(c: int, v: int, meta: bool) -> str:
+    """Template arguments of the survey kernel that serves class c under
+    variant v, as in the rocprofv3 kernel name (spaces removed)."""
+    v = resolve_variant(c, v)
+    log_slots, block, wave = {1: (6, 256, "true"), 2: (12, 1024, "false") if c == 2 else (10, 256, "false"),
+                              3: (0, 256, "false"), 4: (0, 256, "true")}[v]
+    return "survey_kernel<%d,%d,%s,%s,false>" % (log_slots, block, wave, "true" if meta else "false")
 
 
 def log(*a):
@@ -62,8 +75,8 @@ def algorithmic_bytes(st: dict, c: int, meta: bool) -> int:
             + 32 * st["class_tiles"][c])
 
 
-def load_traffic(meta: bool, workload_name: str, cls: int):
-    """HBM bytes per launch of class `cls`'s kernel from the committed rocprofv3
+def load_traffic(key: str, workload_name: str):
+    """HBM bytes per launch of the kernel `key` from the committed rocprofv3
     counter summary, if it was taken on the current kernel source and this
     workload (else None)."""
     try:
@@ -72,8 +85,7 @@ def load_traffic(meta: bool, workload_name: str, cls: int):
         return None
     if rec.get("kernel_hash") != kernel_source_hash() or rec.get("workload") != workload_name:
         return None
-    k = TRAFFIC_KEYS[cls] % ("true" if meta else "false")
-    v = rec.get("kernels", {}).get(k)
+    v = rec.get("kernels", {}).get(key)
     return None if v is None else int(v["hbm_bytes_per_launch"])
 
 
@@ -139,10 +151,21 @@ def batch_bench(args, torch, synth, tp) -> dict:
     bw = tp.tripoll_batch_words(spec)
     out = torch.zeros(G * bw + tp.TP_BATCH_SCRATCH_WORDS, dtype=torch.int64, device="cuda")
     be, keep = tp.batch_edges(eoff, vcnt, src, dst, ts, vlab, device=True)
+    plan = tune = None
+    if args.tune:
+        h = tp.tripoll_build_batch(be, sptr)
+        try:
+            r = tp.tripoll_tune(h, spec, sptr)
+            tune, plan = tp.tune_dict(r), r.chosen
+        finally:
+            tp.tripoll_graph_free(h)
+        log("tuned plan: %s" % tune)
 
     def step():
         h = tp.tripoll_build_batch(be, sptr)
         try:
+            if plan is not None:
+                tp.tripoll_set_plan(h, plan, sptr)
             st = tp.stats_dict(tp.tripoll_graph_stats(h))
             tp.tripoll_survey_batch(h, spec, out.data_ptr(), sptr)
             words = out.cpu().numpy().view(np.uint64)  # synchronises the stream
@@ -172,6 +195,8 @@ def batch_bench(args, torch, synth, tp) -> dict:
     h = tp.tripoll_build_batch(be, sptr)
     rec_ms = []
     try:
+        if plan is not None:
+            tp.tripoll_set_plan(h, plan, sptr)
         st = tp.stats_dict(tp.tripoll_graph_stats(h))
         rec = torch.zeros_like(out)
         with tp.Launch(tp.tripoll_survey_capture(h, spec, rec.data_ptr())) as L:
@@ -237,7 +262,7 @@ def batch_bench(args, torch, synth, tp) -> dict:
         "batch": {"build_ms": round(st["build_ms"], 2), "build_phase_ms": [round(x, 2) for x in st["phase_ms"]],
                   "recorded_survey_ms_p50": round(statistics.median(rec_ms), 3),
                   "recorded_survey_triangles_per_s": tri / (statistics.median(rec_ms) * 1e-3),
-                  "tiles": st["class_tiles"]},
+                  "tiles": st["class_tiles"], "tune": tune},
         "one_graph_loop": {"sampled_graphs": len(sample), "stride": k,
                            "build_s_est": round(loop_build * k, 3), "survey_s_est": round(loop_survey * k, 3),
                            "total_s_est": round(loop_total_est, 3),
@@ -259,6 +284,9 @@ def main():
     ap.add_argument("--scale", type=int, default=None, help="override the R-MAT scale (same recipe)")
     ap.add_argument("--count-only", action="store_true", help="survey the triangle count only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the survey plan once on the first build; every step then re-cuts its tiles "
+                         "with the chosen plan (inside the timed step)")
     ap.add_argument("--cpu-scale", type=int, default=21)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter calibration)")
@@ -308,13 +336,29 @@ def main():
         log("copy calibration: %d bytes read, %d bytes written per copy" % (a.numel() * 4, b.numel() * 4))
         del a, b
 
+    plan = None
+    tune = None
+    if args.tune:
+        h = tp.tripoll_build(el, sptr)
+        try:
+            r = tp.tripoll_tune(h, spec, sptr)
+            tune = tp.tune_dict(r)
+            plan = r.chosen
+        finally:
+            tp.tripoll_graph_free(h)
+        log("tuned plan: %s" % tune)
+
     def step():
         h = tp.tripoll_build(el, sptr)
         try:
+            if plan is not None:
+                tp.tripoll_set_plan(h, plan, sptr)
             st = tp.stats_dict(tp.tripoll_graph_stats(h))
+            pl = tp.plan_dict(tp.tripoll_get_plan(h))
             res = tp.tripoll_survey(h, spec, sptr)
         finally:
             tp.tripoll_graph_free(h)
+        st["plan"] = pl
         return st, tp.result_dict(res, w.n_labels)
 
     for i in range(args.warmup):
@@ -349,14 +393,16 @@ def main():
     build_ms = [s["build_ms"] for _, s, _ in per]
 
     # dominant survey kernel
-    cls_ms = [statistics.mean(rr["class_ms"][c] for _, _, rr in per) for c in range(3)]
+    cls_ms = [statistics.mean(rr["class_ms"][c] for _, _, rr in per) for c in range(4)]
     c = int(np.argmax(cls_ms))
     alg = algorithmic_bytes(st, c, meta)
     achieved = alg / (cls_ms[c] * 1e-3) / 1e9
-    traffic = load_traffic(meta, w.name, c)
+    var = st["plan"]["variant"][c]
+    key = kernel_key(c, var, meta)
+    traffic = load_traffic(key, w.name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": CLASS_NAMES[c].replace("META", "true" if meta else "false"),
+                "kernel": "%s: class %s, %s" % (key, CLASS_NAMES[c], VARIANT_NAMES[resolve_variant(c, var)]),
                 "traffic_per_algorithmic_byte": None if traffic is None else round(traffic / alg, 3),
                 "kernel_ms": round(cls_ms[c], 3), "algorithmic_bytes": int(alg),
                 "wedge_checks": int(st["class_probes"][c])}
@@ -391,6 +437,8 @@ def main():
             "build_ms_p50": statistics.median(build_ms),
             "build_phase_ms": [round(x, 2) for x in st["phase_ms"]],
             "gpu_ms_per_step": round(gpu_ms / args.steps, 3),
+            "plan": st["plan"],
+            "tune": tune,
         },
         "roofline": roofline,
     }

@@ -84,6 +84,12 @@ typedef struct {
 
 typedef struct tp_graph tp_graph;
 
+/* Target classes of the survey plan, by d+(q) (the out-degree of the middle
+ * vertex of a wedge): 0 tiny d+ <= 51, 1 small <= 819, 2 large <= 3276,
+ * 3 huge.  The class decides where Adj+(q) is kept while the wedges through
+ * q are checked. */
+#define TP_NUM_CLASSES 4
+
 /* Graph statistics.  Degrees are of the cleaned simple graph; d+ is the
  * out-degree in the degree-ordered directed graph; wedges = |W+| = sum over
  * v of C(d+(v), 2), the wedge checks of the survey (Preliminaries). */
@@ -107,11 +113,12 @@ typedef struct {
                                   5 CSR+metadata, 6 in-edge index, 7 survey plan */
     float build_ms;            /* sum of phase_ms */
     uint32_t reserved2;
-    /* survey plan per target class (0: d+(q) <= 819, 1: <= 3276, 2: larger) */
-    uint64_t class_tiles[3];   /* tiles */
-    uint64_t class_records[3]; /* in-edge records (one per oriented edge p -> q) */
-    uint64_t class_staged[3];  /* sum over tiles of d+(q): out-list entries loaded per survey */
-    uint64_t class_probes[3];  /* wedge checks */
+    /* survey plan per target class (TP_NUM_CLASSES) */
+    uint64_t class_tiles[TP_NUM_CLASSES];   /* tiles */
+    uint64_t class_records[TP_NUM_CLASSES]; /* in-edge records (one per oriented edge p -> q) */
+    uint64_t class_staged[TP_NUM_CLASSES];  /* sum over tiles of d+(q): out-list entries loaded
+                                               per survey */
+    uint64_t class_probes[TP_NUM_CLASSES];  /* wedge checks */
 } tp_graph_stats;
 
 /*
@@ -181,6 +188,19 @@ tp_status tripoll_graph_export(const tp_graph *g, uint64_t *rowptr, uint32_t *co
 #define TP_STRAT_TABLE_STRESS 2u  /* LDS tables with one placement attempt per key: exercises
                                      the stash and the HBM fallback (slow; for tests) */
 
+/* How a target class searches Adj+(q) (survey plan variants):
+ *   TP_VAR_DEFAULT      the class's own choice: per-wave LDS tables (tiny),
+ *                       per-workgroup LDS tables (small, large), HBM (huge)
+ *   TP_VAR_WAVE_TABLE   LDS cuckoo tables, one per wave (tiny class only)
+ *   TP_VAR_GROUP_TABLE  LDS cuckoo tables, one per workgroup (not huge)
+ *   TP_VAR_SEARCH       binary search of Adj+(q) in HBM, a workgroup per tile
+ *   TP_VAR_WAVE_SEARCH  binary search of Adj+(q) in HBM, a wave per tile */
+#define TP_VAR_DEFAULT 0u
+#define TP_VAR_WAVE_TABLE 1u
+#define TP_VAR_GROUP_TABLE 2u
+#define TP_VAR_SEARCH 3u
+#define TP_VAR_WAVE_SEARCH 4u
+
 typedef struct {
     uint32_t outputs;        /* TP_OUT_* bitmask */
     uint32_t filters;        /* TP_FILT_* bitmask */
@@ -202,8 +222,7 @@ typedef struct {
     uint64_t open_close[32 * 32];
     float kernel_ms;         /* device time of the intersection kernels */
     float total_ms;          /* device time of the whole survey call */
-    float class_ms[3];       /* device time of the kernel of each target class */
-    uint32_t reserved;
+    float class_ms[TP_NUM_CLASSES]; /* device time of the kernel of each target class */
 } tp_survey_result;
 
 /* Word layout of a device result buffer (uint64[TP_RESULT_WORDS]).  The
@@ -341,6 +360,54 @@ tp_status tripoll_survey_capture(const tp_graph *g, const tp_survey_spec *spec, 
                                  tp_launch **out);
 tp_status tripoll_launch_replay(tp_launch *launch, void *stream);
 tp_status tripoll_launch_free(tp_launch *launch);
+
+/* ------------------------------------------------------------------------ */
+/* Survey plan and autotuning                                                */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The survey plan of a graph: per target class, the search variant
+ * (TP_VAR_*) and the cap on in-edge records per tile (a tile is the unit of
+ * work one workgroup or wave claims; a target with more records, or more
+ * than 256 wedge checks per record of cap, is cut into several interleaved
+ * tiles).  Results never depend on the plan, only the time does.
+ *   tile_records  power of two in [16, 65536]
+ */
+typedef struct {
+    uint32_t variant[TP_NUM_CLASSES];
+    uint32_t tile_records[TP_NUM_CLASSES];
+} tp_plan;
+
+/* Read the plan of a graph (host struct). */
+tp_status tripoll_get_plan(const tp_graph *g, tp_plan *out);
+
+/*
+ * Replace the plan of a graph (re-cuts the tiles on `stream`; synchronous).
+ * Not to be called while surveys of the graph are in flight.
+ * Errors: TP_ERR_INVALID for an unknown variant, a variant the class cannot
+ * use (tables for the huge class, per-wave tables outside the tiny class) or
+ * a tile cap that is not a power of two in [16, 65536].
+ */
+tp_status tripoll_set_plan(tp_graph *g, const tp_plan *plan, void *stream);
+
+/* Outcome of tripoll_tune. */
+typedef struct {
+    tp_plan chosen;                    /* the plan now set on the graph */
+    float default_ms[TP_NUM_CLASSES];  /* kernel time of each class under the default plan */
+    float tuned_ms[TP_NUM_CLASSES];    /* kernel time of each class under the chosen plan */
+    uint32_t trials;                   /* timed (class, variant, tile cap) launches */
+    uint32_t reserved;
+} tp_tune_result;
+
+/*
+ * Autotune the plan for one survey kind: for every class, time each usable
+ * variant at tile caps 256, 1024 and 4096 with the survey `spec` on this
+ * graph, and keep the fastest per class (the default stays unless another
+ * beats it by more than 3%).  Runs real surveys (cost: a few times one
+ * survey).  Synchronous; sets the plan on the graph.  Not to be called while
+ * surveys of the graph are in flight.
+ */
+tp_status tripoll_tune(tp_graph *g, const tp_survey_spec *spec, void *stream, tp_tune_result *out);
 
 /* Colex index of the label multiset {a, b, c} (any order). */
 uint32_t tripoll_msidx(uint32_t a, uint32_t b, uint32_t c);

@@ -356,26 +356,42 @@ __global__ void k_in_work(const uint64_t *key, const uint32_t *piv, uint64_t n_i
 
 __device__ __forceinline__ int class_of(uint64_t dq)
 {
-    return dq <= kSmallMaxDeg ? kClassSmall : (dq <= kLargeMaxDeg ? kClassLarge : kClassHuge);
+    return dq <= kTinyMaxDeg ? kClassTiny
+                             : (dq <= kSmallMaxDeg ? kClassSmall : (dq <= kLargeMaxDeg ? kClassLarge : kClassHuge));
 }
 
-__device__ __forceinline__ uint32_t tiles_of(uint64_t cnt, uint64_t work)
+// Tile caps of each class: records per tile and wedge checks per tile.
+struct TileCaps {
+    uint32_t rec[kNumClasses];
+    uint64_t work[kNumClasses];
+};
+
+__device__ __forceinline__ uint32_t tiles_of(uint64_t cnt, uint64_t work, uint32_t rec_cap, uint64_t work_cap)
 {
     if (cnt == 0) return 0;
-    const uint64_t a = (cnt + kTileRecords - 1) / kTileRecords;
-    const uint64_t b = (work + kTileWork - 1) / kTileWork;
+    const uint64_t a = (cnt + rec_cap - 1) / rec_cap;
+    const uint64_t b = (work + work_cap - 1) / work_cap;
     uint64_t t = a > b ? a : b;
     if (t > cnt) t = cnt;
     return (uint32_t)t;
 }
 
 __global__ void k_plan_count(const uint64_t *cptr, const unsigned long long *work, const uint64_t *rowptr,
-                             uint32_t n, uint32_t *tcnt /* [3][n] */)
+                             uint32_t n, TileCaps caps, uint32_t *tcnt /* [classes][n] */)
 {
     for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
         const uint64_t cnt = cptr[q + 1] - cptr[q];
         const int c = class_of(rowptr[q + 1] - rowptr[q]);
-        const uint32_t t = tiles_of(cnt, work[q]);
+        uint32_t rc = caps.rec[0];
+        uint64_t wc = caps.work[0];
+#pragma unroll
+        for (int i = 1; i < kNumClasses; ++i) {
+            if (i == c) {
+                rc = caps.rec[i];
+                wc = caps.work[i];
+            }
+        }
+        const uint32_t t = tiles_of(cnt, work[q], rc, wc);
         for (int i = 0; i < kNumClasses; ++i) tcnt[(size_t)i * n + q] = (i == c) ? t : 0u;
     }
 }
@@ -418,9 +434,9 @@ __global__ void k_work_stats(const unsigned long long *work, uint32_t n, unsigne
 
 // Per-class totals of the plan: records, staged out-list entries, probes.
 __global__ void k_plan_stats(const uint64_t *cptr, const unsigned long long *work, const uint64_t *rowptr,
-                             const uint32_t *tcnt, uint32_t n, unsigned long long *out /* [3][3] */)
+                             const uint32_t *tcnt, uint32_t n, unsigned long long *out /* [3][classes] */)
 {
-    unsigned long long rec[kNumClasses] = {0, 0, 0}, stg[kNumClasses] = {0, 0, 0}, prb[kNumClasses] = {0, 0, 0};
+    unsigned long long rec[kNumClasses] = {}, stg[kNumClasses] = {}, prb[kNumClasses] = {};
     for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
         const uint64_t dq = rowptr[q + 1] - rowptr[q];
         const int c = class_of(dq);
@@ -465,6 +481,79 @@ const T *to_device(const T *p, size_t n, uint32_t space, DArray<T> &hold, hipStr
 }
 
 }  // namespace
+
+// ================================================================ plan
+
+uint64_t graph_bytes(const tp_graph *g)
+{
+    uint64_t b = g->rowptr.bytes() + g->col.bytes() + g->ets.bytes() + g->tlab.bytes() + g->rlab.bytes() +
+                 g->perm.bytes() + g->inkey.bytes() + g->inp.bytes() + g->rank_gid.bytes();
+    for (int c = 0; c < kNumClasses; ++c) b += g->tiles[c].bytes();
+    return b;
+}
+
+// Cut the tiles of every class with the caps of `cfg` and record the plan's
+// statistics.  The work of each target (in-edges and wedge checks) is
+// recomputed from the in-edge index.
+void plan_graph(tp_graph *g, const PlanCfg &cfg, hipStream_t s)
+{
+    const uint32_t n = g->n;
+    DArray<unsigned long long> work(n, s);
+    DArray<uint64_t> cptr((size_t)n + 1, s);
+    {
+        DArray<uint32_t> incnt(n, s);
+        TP_HIP(hipMemsetAsync(incnt.get(), 0, n * sizeof(uint32_t), s));
+        TP_HIP(hipMemsetAsync(work.get(), 0, n * sizeof(unsigned long long), s));
+        if (g->n_in) {
+            k_in_work<<<grid_for(g->n_in, kB), kB, 0, s>>>(g->inkey.get(), g->inp.get(), g->n_in, (int)g->kbits,
+                                                           g->rowptr.get(), work.get(), incnt.get());
+            TP_CHECK_LAUNCH();
+        }
+        scan_u32_to_u64(incnt.get(), cptr.get(), n, s);
+    }
+    TileCaps caps;
+    for (int c = 0; c < kNumClasses; ++c) {
+        caps.rec[c] = cfg.tile_records[c];
+        caps.work[c] = kTileWorkPerRecord * cfg.tile_records[c];
+    }
+    DArray<uint32_t> tcnt((size_t)kNumClasses * n, s);
+    k_plan_count<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), work.get(), g->rowptr.get(), n, caps, tcnt.get());
+    TP_CHECK_LAUNCH();
+    for (int c = 0; c < kNumClasses; ++c) {
+        DArray<uint64_t> toff((size_t)n + 1, s);
+        scan_u32_to_u64(tcnt.get() + (size_t)c * n, toff.get(), n, s);
+        const uint64_t nt = read_scalar(toff.get() + n, s);
+        g->n_tiles[c] = nt;
+        g->tiles[c].reset(std::max<uint64_t>(nt, 1), s);
+        if (nt) {
+            k_plan_write<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), toff.get(), tcnt.get() + (size_t)c * n, n,
+                                                        g->tiles[c].get());
+            TP_CHECK_LAUNCH();
+        }
+    }
+    // per class: records, staged entries, probes; then all probes and active targets
+    constexpr int kStat = 3 * kNumClasses;
+    DArray<unsigned long long> pst(kStat + 2, s);
+    TP_HIP(hipMemsetAsync(pst.get(), 0, (kStat + 2) * sizeof(unsigned long long), s));
+    k_plan_stats<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), work.get(), g->rowptr.get(), tcnt.get(), n, pst.get());
+    TP_CHECK_LAUNCH();
+    k_work_stats<<<grid_for(n, kB), kB, 0, s>>>(work.get(), n, pst.get() + kStat, pst.get() + kStat + 1);
+    TP_CHECK_LAUNCH();
+    unsigned long long h[kStat + 2];
+    TP_HIP(hipMemcpyAsync(h, pst.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    g->stats.n_tiles = 0;
+    for (int c = 0; c < kNumClasses; ++c) {
+        g->stats.class_tiles[c] = g->n_tiles[c];
+        g->stats.class_records[c] = h[c];
+        g->stats.class_staged[c] = h[kNumClasses + c];
+        g->stats.class_probes[c] = h[2 * kNumClasses + c];
+        g->stats.n_tiles += g->n_tiles[c];
+    }
+    g->stats.probes = h[kStat];
+    g->stats.n_targets = h[kStat + 1];
+    g->plan = cfg;
+}
 
 // ================================================================ build
 
@@ -664,8 +753,6 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
     TP_HIP(hipEventRecord(ev[6], s));
 
     // ---- phase 6: in-edge index, a sort of the oriented edges by target
-    DArray<unsigned long long> work(n, s);
-    DArray<uint64_t> cptr((size_t)n + 1, s);
     {
         int kbits = std::max(1, bits_for(m));
         if (kbits + nb + 1 > 64) fail(TP_ERR_UNSUPPORTED, "tripoll_build: graph too large for the in-edge keys");
@@ -690,15 +777,6 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
         DArray<uint32_t> &vv = (ival == valA.get()) ? valA : valB;
         g->inkey = std::move(kk);
         g->inp = std::move(vv);
-        DArray<uint32_t> incnt(n, s);
-        TP_HIP(hipMemsetAsync(incnt.get(), 0, n * sizeof(uint32_t), s));
-        TP_HIP(hipMemsetAsync(work.get(), 0, n * sizeof(unsigned long long), s));
-        if (g->n_in) {
-            k_in_work<<<grid_for(g->n_in, kB), kB, 0, s>>>(g->inkey.get(), g->inp.get(), g->n_in, kbits,
-                                                           g->rowptr.get(), work.get(), incnt.get());
-            TP_CHECK_LAUNCH();
-        }
-        scan_u32_to_u64(incnt.get(), cptr.get(), n, s);
     }
     keyA.release();
     keyB.release();
@@ -706,41 +784,10 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
     valB.release();
     TP_HIP(hipEventRecord(ev[7], s));
 
-    // ---- phase 7: tile plan per class
-    {
-        DArray<uint32_t> tcnt((size_t)kNumClasses * n, s);
-        k_plan_count<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), work.get(), g->rowptr.get(), n, tcnt.get());
-        TP_CHECK_LAUNCH();
-        for (int c = 0; c < kNumClasses; ++c) {
-            DArray<uint64_t> toff((size_t)n + 1, s);
-            scan_u32_to_u64(tcnt.get() + (size_t)c * n, toff.get(), n, s);
-            const uint64_t nt = read_scalar(toff.get() + n, s);
-            g->n_tiles[c] = nt;
-            g->tiles[c].reset(std::max<uint64_t>(nt, 1), s);
-            if (nt) {
-                k_plan_write<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), toff.get(), tcnt.get() + (size_t)c * n, n,
-                                                            g->tiles[c].get());
-                TP_CHECK_LAUNCH();
-            }
-        }
-        DArray<unsigned long long> pst(3 * kNumClasses, s);
-        TP_HIP(hipMemsetAsync(pst.get(), 0, 3 * kNumClasses * sizeof(unsigned long long), s));
-        k_plan_stats<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), work.get(), g->rowptr.get(), tcnt.get(), n,
-                                                    pst.get());
-        TP_CHECK_LAUNCH();
-        unsigned long long h[3 * kNumClasses];
-        TP_HIP(hipMemcpyAsync(h, pst.get(), sizeof(h), hipMemcpyDeviceToHost, s));
-        TP_HIP(hipStreamSynchronize(s));
-        for (int c = 0; c < kNumClasses; ++c) {
-            g->stats.class_tiles[c] = g->n_tiles[c];
-            g->stats.class_records[c] = h[c];
-            g->stats.class_staged[c] = h[kNumClasses + c];
-            g->stats.class_probes[c] = h[2 * kNumClasses + c];
-        }
-    }
-    // probes = sum of the work of all targets; active targets = targets with work
-    k_work_stats<<<grid_for(n, kB), kB, 0, s>>>(work.get(), n, c_bad + 6, c_bad + 7);
-    TP_CHECK_LAUNCH();
+    // ---- phase 7: work per target and the tile plan per class
+    PlanCfg cfg{};
+    for (int c = 0; c < kNumClasses; ++c) cfg.tile_records[c] = kTileRecords;
+    plan_graph(g.get(), cfg, s);
     TP_HIP(hipEventRecord(ev[8], s));
     TP_HIP(hipStreamSynchronize(s));
 
@@ -752,9 +799,7 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
     // the survey packs a position in Adj+(q) into 22 bits; d+ <= sqrt(2m) keeps
     // this far away for any graph that fits in memory
     if (hs[5] >= (1ull << 22)) fail(TP_ERR_UNSUPPORTED, "tripoll_build: out-degree above 2^22 in the oriented graph");
-    g->stats.probes = hs[6];
-    g->stats.n_targets = hs[7];
-    g->stats.n_tiles = g->n_tiles[0] + g->n_tiles[1] + g->n_tiles[2];
+
     float total = 0.f;
     for (int i = 0; i < 8; ++i) {
         float t = 0.f;
@@ -763,10 +808,7 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
         total += t;
     }
     g->stats.build_ms = total;
-    g->stats.device_bytes = g->rowptr.bytes() + g->col.bytes() + g->ets.bytes() + g->tlab.bytes() +
-                            g->rlab.bytes() + g->perm.bytes() + g->inkey.bytes() + g->inp.bytes() +
-                            g->tiles[0].bytes() +
-                            g->tiles[1].bytes() + g->tiles[2].bytes();
+    g->stats.device_bytes = graph_bytes(g.get());
     *out = g.release();
 }
 

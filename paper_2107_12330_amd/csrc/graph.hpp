@@ -19,7 +19,14 @@ struct TileDesc {
 // slot k of the edge in p's row below it; the wedges (p, q, r) to check are
 // the slots after k in p's row.  A second array holds p.
 // Target classes of the survey plan, by d+(q).
-enum { kClassSmall = 0, kClassLarge = 1, kClassHuge = 2, kNumClasses = 3 };
+enum { kClassTiny = 0, kClassSmall = 1, kClassLarge = 2, kClassHuge = 3, kNumClasses = TP_NUM_CLASSES };
+
+// Survey plan choices per class: how Adj+(q) is searched (TP_VAR_*) and the
+// records-per-tile cap the tiles were cut with.
+struct PlanCfg {
+    uint32_t variant[kNumClasses];
+    uint32_t tile_records[kNumClasses];
+};
 
 struct tp_graph {
     int device = 0;
@@ -39,6 +46,14 @@ struct tp_graph {
     tp::DArray<TileDesc> tiles[kNumClasses];
     uint32_t n_graphs = 0;         // > 0 for a batch of disjoint graphs
     tp::DArray<uint32_t> rank_gid; // [n] graph of each rank (batches only)
-    uint64_t n_tiles[kNumClasses] = {0, 0, 0};
+    uint64_t n_tiles[kNumClasses] = {};
+    PlanCfg plan{};
     tp_graph_stats stats{};
 };
+
+// Cut the survey tiles of every class with the caps of `cfg`, store `cfg` as
+// the graph's plan and refresh the plan statistics (build.hip).
+void plan_graph(tp_graph *g, const PlanCfg &cfg, hipStream_t s);
+
+// Device bytes held by a graph.
+uint64_t graph_bytes(const tp_graph *g);

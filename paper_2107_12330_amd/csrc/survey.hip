@@ -17,10 +17,13 @@
 // workgroup) that are merged into the result with global atomics when the
 // workgroup retires.
 //
-// Work is a list of tiles (at most kTileRecords in-edge records of one q);
-// persistent workgroups take tiles from an atomic counter.  Targets are
-// split into three classes by d+(q): LDS hash of <= 2048 slots, LDS hash of
-// <= 8192 slots, and binary search of Adj+(q) in HBM for the rest.
+// Work is a list of tiles (a capped number of in-edge records of one q);
+// persistent workgroups, or in the per-wave form single waves, take tiles
+// from an atomic counter.  Targets are split into four classes by d+(q), and
+// each class runs one variant of the kernel (the survey plan): LDS tables
+// per wave for tiny targets, LDS tables per workgroup of <= 2 x 1024 or
+// <= 2 x 4096 slots for small and large ones, binary search of Adj+(q) in
+// HBM for huge ones; any class may be switched to HBM search.
 #include <algorithm>
 #include <map>
 #include <memory>
@@ -214,40 +217,65 @@ struct RecBlock {
 
 // LOG_SLOTS > 0: LDS hash of Adj+(q) with 2^LOG_SLOTS slots at most.
 // LOG_SLOTS == 0: binary search of Adj+(q) in HBM.
-// BLOCK threads share one target's table.  The records of a tile are dealt
-// to the waves round-robin; a wave walks its records in rows of up to 64
-// consecutive candidates of one pivot's row (lane i takes candidate i), so
-// every address is a wave-uniform base plus the lane.  Hits go to a per-wave
-// ring in LDS and are reduced 64 at a time.
-template <int LOG_SLOTS, int BLOCK, bool META, bool ENUM>
+// WAVE == false: the BLOCK threads of a workgroup share one target's table
+// and the records of a tile are dealt to its waves round-robin.
+// WAVE == true: every wave is its own group, with its own table, tiles and
+// counters, and never waits for the other waves (for small targets, whose
+// tiles are too short to keep a whole workgroup busy between barriers).
+// A wave walks its records in rows of up to 64 consecutive candidates of one
+// pivot's row (lane i takes candidate i), so every address is a wave-uniform
+// base plus the lane.  Hits go to a per-wave ring in LDS and are reduced 64
+// at a time.
+template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM>
 __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
 {
-    constexpr int kW = BLOCK / kWave;  // waves per workgroup
+    constexpr int kWaves = BLOCK / kWave;       // waves per workgroup
+    constexpr int kW = WAVE ? 1 : kWaves;       // waves sharing one table
+    constexpr int kGroup = WAVE ? kWave : BLOCK;  // threads sharing one table
+    constexpr int kGroups = WAVE ? kWaves : 1;  // tables per workgroup
+    constexpr uint64_t kClaim = WAVE ? 8 : kChunk;  // tiles claimed at a time
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr uint32_t kSlots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
-    const LdsLayout L = lds_layout(kSlots, META || ENUM, counter_words(P.table_words, P.oc_words), kW, P.lut_shift);
-    uint32_t *hkey = reinterpret_cast<uint32_t *>(lds);
-    uint32_t *hts = reinterpret_cast<uint32_t *>(lds + L.off_hts);
-    uint8_t *hlab = lds + L.off_hlab;
-    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(lds + L.off_cnt);
+    const uint32_t nc = counter_words(P.table_words, P.oc_words);
+    const LdsLayout L = lds_layout(kSlots * kGroups, META || ENUM, nc * kGroups, kWaves, P.lut_shift);
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
+    const int grp = WAVE ? w : 0;     // this thread's group
+    const int gtid = WAVE ? (int)lane_id() : tid;  // rank in the group
+    const int wl = WAVE ? 0 : w;      // rank of this wave in the group
+    uint32_t *hkey = reinterpret_cast<uint32_t *>(lds) + (size_t)grp * kSlots;
+    uint32_t *hts = reinterpret_cast<uint32_t *>(lds + L.off_hts) + (size_t)grp * kSlots;
+    uint8_t *hlab = lds + L.off_hlab + (size_t)grp * kSlots;
+    unsigned long long *cnt_all = reinterpret_cast<unsigned long long *>(lds + L.off_cnt);
+    unsigned long long *cnt = cnt_all + (size_t)grp * nc;
     uint16_t *lut = reinterpret_cast<uint16_t *>(lds + L.off_lut);
     __shared__ uint64_t mask_lds[13];
     __shared__ unsigned long long s_tile;
-    __shared__ uint32_t s_stash, s_fail;
+    __shared__ uint32_t s_stash_g[kGroups], s_fail_g[kGroups];
+    uint32_t &s_stash = s_stash_g[grp];
+    uint32_t &s_fail = s_fail_g[grp];
+    // barrier of the threads that share a table
+    auto gsync = [&]() {
+        if (WAVE) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
+    };
 
-    const int tid = threadIdx.x;
-    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
     const uint32_t lane = lane_id();
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     uint4 *ring = reinterpret_cast<uint4 *>(lds + L.off_ring) + (size_t)w * kRing;
-    const uint32_t nc = counter_words(P.table_words, P.oc_words);
-    for (uint32_t i = tid; i < nc; i += BLOCK) cnt[i] = 0;
+    for (uint32_t i = tid; i < nc * kGroups; i += BLOCK) cnt_all[i] = 0;
     if (tid < 13) mask_lds[tid] = P.label_mask[tid];
     if (META) {
         const uint32_t ls = P.lut_shift, lm = (1u << ls) - 1;
         for (uint32_t i = tid; i < (1u << (3 * ls)); i += BLOCK)
             lut[i] = (uint16_t)multiset_index(i >> (2 * ls), (i >> ls) & lm, i & lm);
     }
+    __syncthreads();
 
     unsigned long long my_tri = 0, my_spread = 0, probes = 0;
     uint32_t qh = 0, qt = 0;  // this wave's hit ring: entries [qh, qt)
@@ -265,8 +293,8 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
         my_tri = 0;
         my_spread = 0;
         probes = 0;
-        __syncthreads();
-        for (uint32_t i = tid; i < nc; i += BLOCK) {
+        gsync();
+        for (uint32_t i = gtid; i < nc; i += kGroup) {
             const unsigned long long v = cnt[i];
             if (!v) continue;
             uint32_t word;
@@ -276,7 +304,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
             atomicAdd(&blk[word], v);
             cnt[i] = 0;
         }
-        __syncthreads();
+        gsync();
     };
     uint32_t cur_g = 0;  // graph whose counters the workgroup holds
 
@@ -333,12 +361,21 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     for (;;) {
         // claim a chunk of kChunk consecutive tiles; consecutive tiles mostly
         // share their target, whose table is then built once
-        if (tid == 0) s_tile = atomicAdd(P.tile_counter, 1ull);
-        __syncthreads();
-        const uint64_t t_begin = s_tile * kChunk;
-        __syncthreads();  // everyone has read s_tile before it is claimed again
+        uint64_t t_begin;
+        if (WAVE) {
+            unsigned long long c = 0;
+            if (lane == 0) c = atomicAdd(P.tile_counter, 1ull);
+            const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)c);
+            const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(c >> 32));
+            t_begin = (((uint64_t)hi << 32) | lo) * kClaim;
+        } else {
+            if (tid == 0) s_tile = atomicAdd(P.tile_counter, 1ull);
+            __syncthreads();
+            t_begin = s_tile * kClaim;
+            __syncthreads();  // everyone has read s_tile before it is claimed again
+        }
         if (t_begin >= P.n_tiles) break;
-        const uint64_t t_end = min(t_begin + kChunk, P.n_tiles);
+        const uint64_t t_end = min(t_begin + kClaim, P.n_tiles);
         for (uint64_t ti = t_begin; ti < t_end; ++ti) {
             const TileDesc d = sload(P.tiles + (P.n_tiles - 1 - ti));
             if (d.q != cur_q) {
@@ -354,26 +391,29 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                         cur_g = g;
                     }
                 }
-                __syncthreads();
+                gsync();
                 cur_q = d.q;
                 kq = sload(P.rowptr + cur_q);
                 dq = (uint32_t)(sload(P.rowptr + cur_q + 1) - kq);
                 l_q = META ? __builtin_amdgcn_readfirstlane(P.rlab[cur_q]) : 0u;
-                if (LOG_SLOTS > 0) {
+                log_s = 5;
+                while ((1u << log_s) < dq + dq / 4) ++log_s;
+                // a target too large for this kernel's tables (the planner's
+                // classes never send one) is searched in HBM
+                if (LOG_SLOTS > 0) gmode = log_s > (uint32_t)LOG_SLOTS;
+                if (LOG_SLOTS > 0 && !gmode) {
                     // two tables of 2^log_s >= 1.25 dq slots each, then the stash
-                    log_s = 5;
-                    while ((1u << log_s) < dq + dq / 4) ++log_s;
                     const uint32_t S = 1u << log_s;
-                    for (uint32_t i = tid; i < 2 * S + kStash; i += BLOCK) hkey[i] = kEmpty;
-                    if (tid == 0) {
+                    for (uint32_t i = gtid; i < 2 * S + kStash; i += kGroup) hkey[i] = kEmpty;
+                    if (gtid == 0) {
                         s_stash = 0;
                         s_fail = 0;
                     }
-                    __syncthreads();
+                    gsync();
                     // cuckoo insertion: a key evicted from one table moves to
                     // its slot in the other; keys still homeless after
                     // kMaxKicks moves go to the stash
-                    for (uint32_t i = tid; i < dq; i += BLOCK) {
+                    for (uint32_t i = gtid; i < dq; i += kGroup) {
                         uint32_t cur = P.col[kq + i];
                         uint32_t t = 0;
                         for (uint32_t it = 0; it < P.max_kicks; ++it) {
@@ -388,12 +428,12 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                             else s_fail = 1;
                         }
                     }
-                    __syncthreads();
+                    gsync();
                     n_stash = __builtin_amdgcn_readfirstlane(min(s_stash, kStash));
                     gmode = __builtin_amdgcn_readfirstlane(s_fail) != 0;
                     // the metadata of every key goes beside its final slot
                     if ((META || ENUM) && !gmode) {
-                        for (uint32_t i = tid; i < dq; i += BLOCK) {
+                        for (uint32_t i = gtid; i < dq; i += kGroup) {
                             const uint32_t r = P.col[kq + i];
                             uint32_t h = hash0(r, log_s);
                             if (hkey[h] != r) {
@@ -408,7 +448,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                         }
                     }
                 }
-                __syncthreads();
+                gsync();
             }
 
             // ---- this wave's records: tile records w, w + kW, w + 2kW, ...
@@ -416,7 +456,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
             // i-th record) and reads the current one with readlane, so the
             // walk itself issues no memory access.
             const uint32_t ncnt = d.cnt;
-            const uint32_t nw = ncnt > (uint32_t)w ? (ncnt - (uint32_t)w + kW - 1) / kW : 0u;
+            const uint32_t nw = ncnt > (uint32_t)wl ? (ncnt - (uint32_t)wl + kW - 1) / kW : 0u;
             if (nw == 0) continue;
             const uint64_t kmask = (1ull << P.kbits) - 1;
             // lane l of block b holds this wave's in-edge 64b + l (tile record w + (64b + l) kW)
@@ -424,7 +464,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 const uint32_t i = blk * kWave + lane;
                 RecBlock r{0, 0, 0, 0, 0, 0};
                 if (i < nw) {
-                    const uint64_t e = d.e0 + ((uint64_t)(uint32_t)w + (uint64_t)i * kW) * d.stride;
+                    const uint64_t e = d.e0 + ((uint64_t)(uint32_t)wl + (uint64_t)i * kW) * d.stride;
                     const uint64_t k = P.inkey[e] & kmask;
                     const uint32_t p = P.inp[e];
                     const uint64_t st = k + 1;
@@ -603,14 +643,15 @@ __global__ void zero_u64(unsigned long long *p, size_t n)
 
 uint32_t table_size(uint32_t L) { return (L + 2) * (L + 1) * L / 6; }
 
-template <int LOG_SLOTS, int BLOCK, bool META, bool ENUM>
+template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM>
 void launch_class(const SurveyParams &P, hipStream_t s, int device)
 {
     if (P.n_tiles == 0) return;
+    constexpr uint32_t groups = WAVE ? BLOCK / kWave : 1;
     const uint32_t slots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
-    const LdsLayout L =
-        lds_layout(slots, META || ENUM, counter_words(P.table_words, P.oc_words), BLOCK / kWave, P.lut_shift);
-    auto kern = survey_kernel<LOG_SLOTS, BLOCK, META, ENUM>;
+    const LdsLayout L = lds_layout(slots * groups, META || ENUM, counter_words(P.table_words, P.oc_words) * groups,
+                                   BLOCK / kWave, P.lut_shift);
+    auto kern = survey_kernel<LOG_SLOTS, BLOCK, WAVE, META, ENUM>;
     // attribute and occupancy queries run once per kernel, device and LDS
     // size, so that a survey recorded into a HIP graph issues launches only
     static std::mutex mu;
@@ -632,15 +673,50 @@ void launch_class(const SurveyParams &P, hipStream_t s, int device)
         std::lock_guard<std::mutex> lock(mu);
         resident[{device, L.total}] = fit;
     }
+    // each workgroup claims kChunk tiles at a time, or 8 per wave
+    const uint64_t claims = WAVE ? (P.n_tiles + 8 * groups - 1) / (8 * groups) : (P.n_tiles + kChunk - 1) / kChunk;
     uint64_t grid = fit;
-    if (grid > P.n_tiles) grid = P.n_tiles;
+    if (grid > claims) grid = claims;
     zero_u64<<<1, 64, 0, s>>>(P.tile_counter, 1);
     TP_CHECK_LAUNCH();
     kern<<<(unsigned)grid, BLOCK, L.total, s>>>(P);
     TP_CHECK_LAUNCH();
 }
 
-// Launch the three target classes in turn.  `timers`, when given, holds one
+// The search variant class c runs with under `strategy`.
+uint32_t resolve_variant(const tp_graph *g, int c, uint32_t strategy)
+{
+    if (strategy == TP_STRAT_GLOBAL_SEARCH) return TP_VAR_SEARCH;
+    const uint32_t v = g->plan.variant[c];
+    if (v != TP_VAR_DEFAULT) return v;
+    if (c == kClassTiny) return TP_VAR_WAVE_TABLE;
+    if (c == kClassHuge) return TP_VAR_SEARCH;
+    return TP_VAR_GROUP_TABLE;
+}
+
+template <bool META, bool ENUM>
+void launch_variant(int c, uint32_t v, const SurveyParams &P, hipStream_t s, int device)
+{
+    switch (v) {
+    case TP_VAR_WAVE_TABLE:
+        launch_class<kTinyLogSlots, kSmallBlock, true, META, ENUM>(P, s, device);
+        break;
+    case TP_VAR_GROUP_TABLE:
+        if (c == kClassLarge)
+            launch_class<kLargeLogSlots, kLargeBlock, false, META, ENUM>(P, s, device);
+        else
+            launch_class<kSmallLogSlots, kSmallBlock, false, META, ENUM>(P, s, device);
+        break;
+    case TP_VAR_WAVE_SEARCH:
+        launch_class<0, kSmallBlock, true, META, ENUM>(P, s, device);
+        break;
+    default:
+        launch_class<0, kSmallBlock, false, META, ENUM>(P, s, device);
+        break;
+    }
+}
+
+// Launch the target classes in turn.  `timers`, when given, holds one
 // EventTimer per class around its launch.
 template <bool META, bool ENUM>
 void launch_all(const tp_graph *g, SurveyParams P, uint32_t strategy, hipStream_t s, EventTimer *timers = nullptr)
@@ -649,12 +725,7 @@ void launch_all(const tp_graph *g, SurveyParams P, uint32_t strategy, hipStream_
         P.tiles = g->tiles[c].get();
         P.n_tiles = g->n_tiles[c];
         if (timers) timers[c].start();
-        if (strategy == TP_STRAT_GLOBAL_SEARCH || c == kClassHuge)
-            launch_class<0, kSmallBlock, META, ENUM>(P, s, g->device);
-        else if (c == kClassSmall)
-            launch_class<kSmallLogSlots, kSmallBlock, META, ENUM>(P, s, g->device);
-        else
-            launch_class<kLargeLogSlots, kLargeBlock, META, ENUM>(P, s, g->device);
+        launch_variant<META, ENUM>(c, resolve_variant(g, c, strategy), P, s, g->device);
         if (timers) timers[c].stop();
     }
 }
@@ -809,7 +880,7 @@ extern "C" tp_status tripoll_survey(const tp_graph *g, const tp_survey_spec *spe
         hipStream_t s = (hipStream_t)stream;
         DArray<unsigned long long> res(TP_RESULT_WORDS, s);
         EventTimer all(s), kern(s);
-        EventTimer cls[kNumClasses] = {EventTimer(s), EventTimer(s), EventTimer(s)};
+        EventTimer cls[kNumClasses] = {EventTimer(s), EventTimer(s), EventTimer(s), EventTimer(s)};
         all.start();
         kern.start();
         survey_enqueue<false>(g, spec, res.get(), s, nullptr, 0, cls);
@@ -930,4 +1001,161 @@ extern "C" tp_status tripoll_launch_replay(tp_launch *launch, void *stream)
 extern "C" tp_status tripoll_launch_free(tp_launch *launch)
 {
     return guard([&] { delete launch; });
+}
+
+// ================================================================ plan and tuning
+
+namespace {
+
+bool variant_allowed(int c, uint32_t v)
+{
+    switch (v) {
+    case TP_VAR_DEFAULT:
+    case TP_VAR_SEARCH:
+    case TP_VAR_WAVE_SEARCH:
+        return true;
+    case TP_VAR_WAVE_TABLE:
+        return c == kClassTiny;
+    case TP_VAR_GROUP_TABLE:
+        return c != kClassHuge;
+    default:
+        return false;
+    }
+}
+
+void check_plan(const tp_plan *p)
+{
+    for (int c = 0; c < kNumClasses; ++c) {
+        if (!variant_allowed(c, p->variant[c]))
+            fail(TP_ERR_INVALID, "tripoll_set_plan: variant " + std::to_string(p->variant[c]) +
+                                     " cannot serve class " + std::to_string(c));
+        const uint32_t r = p->tile_records[c];
+        if (r < 16 || r > 65536 || (r & (r - 1)))
+            fail(TP_ERR_INVALID, "tripoll_set_plan: tile_records must be a power of two in [16, 65536]");
+    }
+}
+
+PlanCfg to_cfg(const tp_plan *p)
+{
+    PlanCfg c{};
+    for (int i = 0; i < kNumClasses; ++i) {
+        c.variant[i] = p->variant[i];
+        c.tile_records[i] = p->tile_records[i];
+    }
+    return c;
+}
+
+// Device time of class c's launch under variant v, on the graph's current
+// tiles.  `reps` launches; the fastest counts.
+float time_class(const tp_graph *g, const tp_survey_spec *sp, unsigned long long *buf, int c, uint32_t v, int reps,
+                 hipStream_t s)
+{
+    SurveyParams P = make_params(g, sp, buf, buf + TP_RW_SCRATCH);
+    P.tiles = g->tiles[c].get();
+    P.n_tiles = g->n_tiles[c];
+    float best = 0.f;
+    for (int r = 0; r < reps; ++r) {
+        EventTimer t(s);
+        t.start();
+        if (needs_meta(sp))
+            launch_variant<true, false>(c, v, P, s, g->device);
+        else
+            launch_variant<false, false>(c, v, P, s, g->device);
+        t.stop();
+        const float ms = t.ms();
+        if (r == 0 || ms < best) best = ms;
+    }
+    return best;
+}
+
+}  // namespace
+
+extern "C" tp_status tripoll_get_plan(const tp_graph *g, tp_plan *out)
+{
+    return guard([&] {
+        if (!g || !out) fail(TP_ERR_INVALID, "tripoll_get_plan: NULL argument");
+        for (int c = 0; c < kNumClasses; ++c) {
+            out->variant[c] = g->plan.variant[c];
+            out->tile_records[c] = g->plan.tile_records[c];
+        }
+    });
+}
+
+extern "C" tp_status tripoll_set_plan(tp_graph *g, const tp_plan *plan, void *stream)
+{
+    return guard([&] {
+        if (!g || !plan) fail(TP_ERR_INVALID, "tripoll_set_plan: NULL argument");
+        check_plan(plan);
+        plan_graph(g, to_cfg(plan), (hipStream_t)stream);
+        g->stats.device_bytes = graph_bytes(g);
+    });
+}
+
+extern "C" tp_status tripoll_tune(tp_graph *g, const tp_survey_spec *spec, void *stream, tp_tune_result *out)
+{
+    return guard([&] {
+        if (!out) fail(TP_ERR_INVALID, "tripoll_tune: NULL result");
+        validate_spec(g, spec);
+        hipStream_t s = (hipStream_t)stream;
+        tp_survey_spec sp = *spec;
+        sp.strategy = TP_STRAT_AUTO;
+        DArray<unsigned long long> buf(TP_RESULT_WORDS, s);
+        zero_u64<<<grid_for(TP_RESULT_WORDS, 256), 256, 0, s>>>(buf.get(), TP_RESULT_WORDS);
+        TP_CHECK_LAUNCH();
+        static const uint32_t kCaps[] = {256, 1024, 4096};
+        static const std::vector<uint32_t> kCands[kNumClasses] = {
+            {TP_VAR_WAVE_TABLE, TP_VAR_GROUP_TABLE, TP_VAR_WAVE_SEARCH},
+            {TP_VAR_GROUP_TABLE, TP_VAR_SEARCH, TP_VAR_WAVE_SEARCH},
+            {TP_VAR_GROUP_TABLE, TP_VAR_SEARCH},
+            {TP_VAR_SEARCH, TP_VAR_WAVE_SEARCH}};
+        tp_tune_result r{};
+        float best[kNumClasses];
+        uint32_t best_v[kNumClasses], best_cap[kNumClasses];
+        for (int c = 0; c < kNumClasses; ++c) {
+            best[c] = -1.f;
+            best_v[c] = TP_VAR_DEFAULT;
+            best_cap[c] = kTileRecords;
+        }
+        for (uint32_t cap : kCaps) {
+            PlanCfg cfg{};
+            for (int c = 0; c < kNumClasses; ++c) cfg.tile_records[c] = cap;
+            plan_graph(g, cfg, s);
+            for (int c = 0; c < kNumClasses; ++c) {
+                if (g->n_tiles[c] == 0) continue;
+                const uint32_t dflt = resolve_variant(g, c, TP_STRAT_AUTO);
+                for (uint32_t v : kCands[c]) {
+                    // a warm-up launch, then the faster of two timed ones
+                    (void)time_class(g, &sp, buf.get(), c, v, 1, s);
+                    const float ms = time_class(g, &sp, buf.get(), c, v, 2, s);
+                    ++r.trials;
+                    if (cap == kTileRecords && v == dflt) r.default_ms[c] = ms;
+                    if (best[c] < 0.f || ms < best[c]) {
+                        best[c] = ms;
+                        best_v[c] = v;
+                        best_cap[c] = cap;
+                    }
+                }
+            }
+        }
+        // keep the default unless the best is clearly faster
+        PlanCfg fin{};
+        for (int c = 0; c < kNumClasses; ++c) {
+            fin.variant[c] = TP_VAR_DEFAULT;
+            fin.tile_records[c] = kTileRecords;
+            if (best[c] >= 0.f && best[c] < 0.97f * r.default_ms[c]) {
+                fin.variant[c] = best_v[c];
+                fin.tile_records[c] = best_cap[c];
+            }
+        }
+        plan_graph(g, fin, s);
+        g->stats.device_bytes = graph_bytes(g);
+        for (int c = 0; c < kNumClasses; ++c) {
+            r.chosen.variant[c] = fin.variant[c];
+            r.chosen.tile_records[c] = fin.tile_records[c];
+            r.tuned_ms[c] = g->n_tiles[c] ? time_class(g, &sp, buf.get(), c, resolve_variant(g, c, TP_STRAT_AUTO), 2, s)
+                                          : 0.f;
+        }
+        TP_HIP(hipStreamSynchronize(s));
+        *out = r;
+    });
 }

@@ -24,6 +24,8 @@ TP_TIE_MIX, TP_TIE_ID = 0, 1
 TP_OUT_COUNT, TP_OUT_CLOSE_HIST, TP_OUT_LABEL_TABLE, TP_OUT_SPREAD_COUNT, TP_OUT_OPEN_CLOSE = 1, 2, 4, 8, 16
 TP_FILT_WINDOW, TP_FILT_LABEL_MASK = 1, 2
 TP_STRAT_AUTO, TP_STRAT_GLOBAL_SEARCH, TP_STRAT_TABLE_STRESS = 0, 1, 2
+TP_VAR_DEFAULT, TP_VAR_WAVE_TABLE, TP_VAR_GROUP_TABLE, TP_VAR_SEARCH, TP_VAR_WAVE_SEARCH = 0, 1, 2, 3, 4
+TP_NUM_CLASSES = 4
 TP_MAX_LABELS = 16
 TP_TABLE_MAX = 816
 TP_RW_TRIANGLES, TP_RW_SPREAD, TP_RW_PROBES, TP_RW_HIST = 0, 1, 2, 3
@@ -58,8 +60,8 @@ class tp_graph_stats(ctypes.Structure):
                 ("n_targets", ctypes.c_uint64), ("n_tiles", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
                 ("max_label", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("phase_ms", ctypes.c_float * 8), ("build_ms", ctypes.c_float), ("reserved2", ctypes.c_uint32),
-                ("class_tiles", ctypes.c_uint64 * 3), ("class_records", ctypes.c_uint64 * 3),
-                ("class_staged", ctypes.c_uint64 * 3), ("class_probes", ctypes.c_uint64 * 3)]
+                ("class_tiles", ctypes.c_uint64 * TP_NUM_CLASSES), ("class_records", ctypes.c_uint64 * TP_NUM_CLASSES),
+                ("class_staged", ctypes.c_uint64 * TP_NUM_CLASSES), ("class_probes", ctypes.c_uint64 * TP_NUM_CLASSES)]
 
 
 class tp_survey_spec(ctypes.Structure):
@@ -72,7 +74,17 @@ class tp_survey_result(ctypes.Structure):
     _fields_ = [("triangles", ctypes.c_uint64), ("spread_count", ctypes.c_uint64), ("probes", ctypes.c_uint64),
                 ("close_hist", ctypes.c_uint64 * 32), ("label_table", ctypes.c_uint64 * TP_TABLE_MAX),
                 ("open_close", ctypes.c_uint64 * 1024), ("kernel_ms", ctypes.c_float),
-                ("total_ms", ctypes.c_float), ("class_ms", ctypes.c_float * 3), ("reserved", ctypes.c_uint32)]
+                ("total_ms", ctypes.c_float), ("class_ms", ctypes.c_float * TP_NUM_CLASSES)]
+
+
+class tp_plan(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_uint32 * TP_NUM_CLASSES), ("tile_records", ctypes.c_uint32 * TP_NUM_CLASSES)]
+
+
+class tp_tune_result(ctypes.Structure):
+    _fields_ = [("chosen", tp_plan), ("default_ms", ctypes.c_float * TP_NUM_CLASSES),
+                ("tuned_ms", ctypes.c_float * TP_NUM_CLASSES), ("trials", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class TripollError(RuntimeError):
@@ -100,6 +112,9 @@ SIGNATURES = {
     "tripoll_survey_capture": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, ctypes.POINTER(_P)]),
     "tripoll_launch_replay": (ctypes.c_int, [_P, _P]),
     "tripoll_launch_free": (ctypes.c_int, [_P]),
+    "tripoll_get_plan": (ctypes.c_int, [_P, ctypes.POINTER(tp_plan)]),
+    "tripoll_set_plan": (ctypes.c_int, [_P, ctypes.POINTER(tp_plan), _P]),
+    "tripoll_tune": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, ctypes.POINTER(tp_tune_result)]),
     "tripoll_msidx": (ctypes.c_uint32, [ctypes.c_uint32] * 3),
     "tripoll_trim": (ctypes.c_int, []),
     "tripoll_cached_bytes": (ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64)]),
@@ -201,6 +216,22 @@ def tripoll_launch_replay(launch: int, stream=None) -> None:
 
 def tripoll_launch_free(launch: int) -> None:
     _check(load().tripoll_launch_free(launch))
+
+
+def tripoll_get_plan(g: int) -> tp_plan:
+    p = tp_plan()
+    _check(load().tripoll_get_plan(g, ctypes.byref(p)))
+    return p
+
+
+def tripoll_set_plan(g: int, plan: tp_plan, stream=None) -> None:
+    _check(load().tripoll_set_plan(g, ctypes.byref(plan), stream))
+
+
+def tripoll_tune(g: int, spec: tp_survey_spec, stream=None) -> tp_tune_result:
+    r = tp_tune_result()
+    _check(load().tripoll_tune(g, ctypes.byref(spec), stream, ctypes.byref(r)))
+    return r
 
 
 def tripoll_msidx(a: int, b: int, c: int) -> int:
@@ -409,3 +440,22 @@ class Launch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ plans
+
+def make_plan(variants=(TP_VAR_DEFAULT,) * TP_NUM_CLASSES, tile_records=(1024,) * TP_NUM_CLASSES) -> tp_plan:
+    p = tp_plan()
+    for i in range(TP_NUM_CLASSES):
+        p.variant[i] = variants[i]
+        p.tile_records[i] = tile_records[i]
+    return p
+
+
+def plan_dict(p: tp_plan) -> dict:
+    return dict(variant=[int(x) for x in p.variant], tile_records=[int(x) for x in p.tile_records])
+
+
+def tune_dict(r: tp_tune_result) -> dict:
+    return dict(chosen=plan_dict(r.chosen), default_ms=[round(float(x), 3) for x in r.default_ms],
+                tuned_ms=[round(float(x), 3) for x in r.tuned_ms], trials=int(r.trials))

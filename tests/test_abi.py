@@ -51,12 +51,14 @@ int main(void) {
          offsetof(tp_survey_result, kernel_ms), offsetof(tp_graph_stats, class_probes),
          offsetof(tp_survey_result, class_ms));
   printf("%u %u %u %u\\n", TP_RW_TABLE, TP_RW_OPEN_CLOSE, TP_RW_SCRATCH, TP_RESULT_WORDS);
+  printf("%zu %zu %zu %zu %u %u %u\\n", sizeof(tp_batch_edges), sizeof(tp_plan), sizeof(tp_tune_result),
+         offsetof(tp_tune_result, trials), TP_BW_TABLE, TP_BATCH_SCRATCH_WORDS, TP_NUM_CLASSES);
   return 0;
 }
 """)
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-std=c11", "-I", INCLUDE, str(src), "-o", str(exe)])
-    l1, l2, l3 = subprocess.check_output([str(exe)]).decode().split("\n")[:3]
+    l1, l2, l3, l4 = subprocess.check_output([str(exe)]).decode().split("\n")[:4]
     assert list(map(int, l1.split())) == [ctypes.sizeof(tp.tp_edge_list), ctypes.sizeof(tp.tp_graph_stats),
                                           ctypes.sizeof(tp.tp_survey_spec), ctypes.sizeof(tp.tp_survey_result)]
     assert list(map(int, l2.split())) == [tp.tp_graph_stats.phase_ms.offset, tp.tp_survey_spec.label_mask.offset,
@@ -64,6 +66,9 @@ int main(void) {
                                           tp.tp_survey_result.class_ms.offset]
     assert list(map(int, l3.split())) == [tp.TP_RW_TABLE, tp.TP_RW_OPEN_CLOSE, tp.TP_RW_SCRATCH,
                                           tp.TP_RESULT_WORDS]
+    assert list(map(int, l4.split())) == [ctypes.sizeof(tp.tp_batch_edges), ctypes.sizeof(tp.tp_plan),
+                                          ctypes.sizeof(tp.tp_tune_result), tp.tp_tune_result.trials.offset,
+                                          tp.TP_BW_TABLE, tp.TP_BATCH_SCRATCH_WORDS, tp.TP_NUM_CLASSES]
 
 
 def test_msidx_is_colex_rank():
