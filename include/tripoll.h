@@ -409,6 +409,113 @@ typedef struct {
  */
 tp_status tripoll_tune(tp_graph *g, const tp_survey_spec *spec, void *stream, tp_tune_result *out);
 
+/* ------------------------------------------------------------------------ */
+/* Served mode                                                               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * A survey server keeps graphs resident on the device and answers survey
+ * requests against them as they arrive (Algorithm 1 with the reductions
+ * above, one request per survey).  Requests on one graph share passes over
+ * its work (continuous batching): the pass is cut into segments, every step
+ * surveys one segment for all requests that hold one of the graph's slots,
+ * and each triangle is reduced into the counters of each such request with
+ * that request's own filters.  A request that arrives while a pass is on the
+ * device takes a free slot at the next step and is complete once it has
+ * seen every segment once (wrapping round the end of the pass); its result
+ * equals that of tripoll_survey on the same graph and spec.  Graphs with
+ * little work (one segment) run on a second stream and overlap the steps of
+ * large ones.  Device memory -- resident graphs and per-request buffers --
+ * is admitted against the server's budget.  A worker thread owned by the
+ * server drives the device; all functions are thread-safe.
+ *
+ * Served survey kinds: outputs COUNT, CLOSE_HIST, LABEL_TABLE, SPREAD_COUNT
+ * (OPEN_CLOSE is TP_ERR_UNSUPPORTED); filters WINDOW and LABEL_MASK.
+ */
+typedef struct tp_server tp_server;
+
+#define TP_SERVER_TAGS 8u /* latency statistics are kept per tag 0..7 */
+
+typedef struct {
+    uint32_t max_slots;   /* request slots per resident graph, 1..16 (0: 8) */
+    uint32_t n_labels;    /* label range of every label output or filter, 1..16
+                             (0: 8); graphs used with them need labels < n_labels */
+    uint64_t hbm_budget;  /* device bytes the server may hold: resident graphs plus
+                             request buffers (0: 90% of the free device memory) */
+    uint64_t step_wedges; /* wedge checks per step, the admission granularity
+                             (0: 2^34) */
+    uint32_t max_queue;   /* waiting requests before submit says TP_ERR_BUSY (0: 4096) */
+    uint32_t reserved;
+} tp_server_config;
+
+/* Per-request timing.  Times are microseconds on the server's clock. */
+typedef struct {
+    uint32_t tag;
+    uint32_t steps;         /* steps the request took part in */
+    double arrival_us;      /* tripoll_server_submit returned */
+    double admit_us;        /* it took a slot */
+    double done_us;         /* its result reached host memory */
+} tp_request_info;
+
+typedef struct {
+    uint64_t submitted, completed, rejected;   /* rejected: submit said BUSY */
+    uint64_t waiting, running;                 /* now */
+    uint64_t steps;                            /* device steps issued */
+    uint64_t triangles;                        /* sum over completed requests */
+    uint64_t hbm_used, hbm_budget;
+    double elapsed_s;                          /* first arrival to last completion */
+    uint64_t count[TP_SERVER_TAGS];            /* completed requests per tag */
+    double p50_ms[TP_SERVER_TAGS];             /* arrival -> result latency per tag */
+    double p99_ms[TP_SERVER_TAGS];
+} tp_server_stats;
+
+/* Create a server on the current device (synchronous).
+ * Errors: TP_ERR_INVALID for out-of-range fields; TP_ERR_DEVICE. */
+tp_status tripoll_server_create(const tp_server_config *cfg, tp_server **out);
+
+/* Stop the worker and release every graph and buffer.  Requests not yet
+ * complete are dropped.  NULL accepted. */
+tp_status tripoll_server_destroy(tp_server *srv);
+
+/*
+ * Build a graph from `edges` (as tripoll_build) and keep it resident.  Its
+ * bytes are taken from the budget: TP_ERR_OOM (and nothing kept) if they do
+ * not fit.  Synchronous.  *graph_id receives its handle.
+ */
+tp_status tripoll_server_add_graph(tp_server *srv, const tp_edge_list *edges, uint32_t *graph_id);
+
+/* Release a resident graph; TP_ERR_BUSY while requests on it wait or run,
+ * TP_ERR_NOT_FOUND for an unknown id. */
+tp_status tripoll_server_remove_graph(tp_server *srv, uint32_t graph_id);
+
+/* Statistics of a resident graph. */
+tp_status tripoll_server_graph_stats(tp_server *srv, uint32_t graph_id, tp_graph_stats *out);
+
+/*
+ * Queue a survey of graph `graph_id`.  Returns at once with a ticket.
+ * `tag` (0..7) groups requests for the latency statistics.
+ * Errors: TP_ERR_NOT_FOUND (graph), TP_ERR_INVALID (spec as tripoll_survey;
+ * labels used with n_labels other than the server's), TP_ERR_UNSUPPORTED
+ * (OPEN_CLOSE), TP_ERR_BUSY (queue full; the request is not kept).
+ */
+tp_status tripoll_server_submit(tp_server *srv, uint32_t graph_id, const tp_survey_spec *spec, uint32_t tag,
+                                uint64_t *ticket);
+
+/*
+ * Wait up to `timeout_us` (negative: no limit) for a request and take its
+ * result: the counters of tripoll_survey (probes = the graph's wedge checks;
+ * kernel_ms, class_ms 0; total_ms = admission to completion) and, if `info`
+ * is not NULL, its timing.  A ticket can be taken once.
+ * Errors: TP_ERR_BUSY when not complete in time (ticket kept),
+ * TP_ERR_NOT_FOUND for an unknown or taken ticket, TP_ERR_DEVICE if the
+ * device failed while it ran.
+ */
+tp_status tripoll_server_wait(tp_server *srv, uint64_t ticket, int64_t timeout_us, tp_survey_result *out,
+                              tp_request_info *info);
+
+/* Counters and latency percentiles (nearest rank over completed requests). */
+tp_status tripoll_server_stats(tp_server *srv, tp_server_stats *out);
+
 /* Colex index of the label multiset {a, b, c} (any order). */
 uint32_t tripoll_msidx(uint32_t a, uint32_t b, uint32_t c);
 

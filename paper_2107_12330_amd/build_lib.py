@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtripoll.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["prim.hip", "build.hip", "survey.hip", "capi.hip"]
+SOURCES = ["prim.hip", "build.hip", "survey.hip", "capi.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", INCLUDE, "-I", CSRC,

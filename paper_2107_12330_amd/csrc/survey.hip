@@ -30,6 +30,7 @@
 #include <mutex>
 
 #include "graph.hpp"
+#include "multi.hpp"
 #include "plan.hpp"
 
 using namespace tp;
@@ -87,6 +88,11 @@ struct SurveyParams {
     unsigned long long *enum_count;
     const uint32_t *perm;
     uint32_t n;
+    // multi-request passes: per slot a result block of slot_words words
+    // (layout of a batch block) at out + slot * g_stride
+    const SlotSpec *slots;
+    uint32_t n_slots, slot_words, slot_labels;
+    uint32_t grid_eighths;    // share of the device the persistent grid may fill (0 or 8: all)
 };
 
 // LDS layout (dynamic): [hash keys][hash times][hash labels][hit rings]
@@ -178,6 +184,40 @@ __device__ __forceinline__ uint32_t reduce_hit(const SurveyParams &P, const Hit 
     return 1;
 }
 
+// Reduce one hit per lane (lanes with valid == false hold none) into the
+// counters of every request slot of a multi-request pass.  Counts and spread
+// counts are added once per wave; histogram and table bins per lane.
+__device__ __forceinline__ void reduce_multi(const Hit &h, bool valid, unsigned long long *cnt, const SlotSpec *slots,
+                                             uint32_t n_slots, uint32_t words, const uint16_t *lut, uint32_t lut_shift,
+                                             bool labels)
+{
+    const uint32_t t1 = min(min(h.t_pq, h.t_pr), h.t_qr);
+    const uint32_t t3 = max(max(h.t_pq, h.t_pr), h.t_qr);
+    const uint32_t close = t3 - t1;
+    const uint32_t bin = close_bin(close);
+    const uint32_t idx = (labels && valid) ? lut[(((h.l_p << lut_shift) | h.l_q) << lut_shift) | h.l_r] : 0u;
+    const bool lane0 = lane_id() == 0;
+    for (uint32_t s = 0; s < n_slots; ++s) {
+        const SlotSpec &S = slots[s];
+        if (S.off) continue;
+        unsigned long long *c = cnt + (size_t)s * words;
+        bool pass = valid;
+        if (S.filters & TP_FILT_WINDOW)
+            pass = pass && !S.window_empty && h.t_pq >= S.t_lo && h.t_pq <= S.t_hi && h.t_pr >= S.t_lo &&
+                   h.t_pr <= S.t_hi && h.t_qr >= S.t_lo && h.t_qr <= S.t_hi;
+        if (S.filters & TP_FILT_LABEL_MASK) pass = pass && ((S.label_mask[idx >> 6] >> (idx & 63)) & 1ull);
+        const uint64_t m = __ballot(pass);
+        if (!m) continue;
+        if (lane0) atomicAdd(&c[TP_BW_TRIANGLES], (unsigned long long)__popcll(m));
+        if (S.outputs & TP_OUT_SPREAD_COUNT) {
+            const uint64_t m2 = __ballot(pass && S.spread_any && close <= S.spread_le);
+            if (lane0 && m2) atomicAdd(&c[TP_BW_SPREAD], (unsigned long long)__popcll(m2));
+        }
+        if ((S.outputs & TP_OUT_CLOSE_HIST) && pass) atomicAdd(&c[TP_BW_HIST + bin], 1ull);
+        if ((S.outputs & TP_OUT_LABEL_TABLE) && pass) atomicAdd(&c[TP_BW_TABLE + idx], 1ull);
+    }
+}
+
 // Binary search of r in col[lo, lo+len); returns the index or -1.
 __device__ __forceinline__ int64_t global_find(const uint32_t *col, uint64_t lo, uint32_t len, uint32_t r)
 {
@@ -226,7 +266,7 @@ struct RecBlock {
 // pivot's row (lane i takes candidate i), so every address is a wave-uniform
 // base plus the lane.  Hits go to a per-wave ring in LDS and are reduced 64
 // at a time.
-template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM>
+template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI>
 __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
 {
     constexpr int kWaves = BLOCK / kWave;       // waves per workgroup
@@ -236,7 +276,8 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     constexpr uint64_t kClaim = WAVE ? 8 : kChunk;  // tiles claimed at a time
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr uint32_t kSlots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
-    const uint32_t nc = counter_words(P.table_words, P.oc_words);
+    static_assert(!MULTI || (META && !ENUM), "multi-request passes reduce metadata");
+    const uint32_t nc = MULTI ? P.n_slots * P.slot_words : counter_words(P.table_words, P.oc_words);
     const LdsLayout L = lds_layout(kSlots * kGroups, META || ENUM, nc * kGroups, kWaves, P.lut_shift);
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
@@ -250,6 +291,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     unsigned long long *cnt = cnt_all + (size_t)grp * nc;
     uint16_t *lut = reinterpret_cast<uint16_t *>(lds + L.off_lut);
     __shared__ uint64_t mask_lds[13];
+    __shared__ SlotSpec slot_lds[MULTI ? kMaxSlots : 1];
     __shared__ unsigned long long s_tile;
     __shared__ uint32_t s_stash_g[kGroups], s_fail_g[kGroups];
     uint32_t &s_stash = s_stash_g[grp];
@@ -270,6 +312,11 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     uint4 *ring = reinterpret_cast<uint4 *>(lds + L.off_ring) + (size_t)w * kRing;
     for (uint32_t i = tid; i < nc * kGroups; i += BLOCK) cnt_all[i] = 0;
     if (tid < 13) mask_lds[tid] = P.label_mask[tid];
+    if (MULTI) {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(P.slots);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(slot_lds);
+        for (uint32_t i = tid; i < P.n_slots * (sizeof(SlotSpec) / 4); i += BLOCK) dst[i] = src[i];
+    }
     if (META) {
         const uint32_t ls = P.lut_shift, lm = (1u << ls) - 1;
         for (uint32_t i = tid; i < (1u << (3 * ls)); i += BLOCK)
@@ -285,7 +332,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     auto flush = [&](uint32_t g) {
         unsigned long long *blk = P.out + (size_t)g * P.g_stride;
         const unsigned long long t = wave_sum(my_tri), sp = wave_sum(my_spread);
-        if (lane == 0) {
+        if (lane == 0 && !MULTI) {
             if (t) atomicAdd(&blk[P.o_tri], t);
             if (sp) atomicAdd(&blk[P.o_spread], sp);
             if (probes) atomicAdd(&blk[P.o_probes], probes);
@@ -298,6 +345,13 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
             const unsigned long long v = cnt[i];
             if (!v) continue;
             uint32_t word;
+            if (MULTI) {
+                // slot i / slot_words, at the same word of its block
+                const uint32_t sl = i / P.slot_words;
+                atomicAdd(&P.out[(size_t)sl * P.g_stride + (i - sl * P.slot_words)], v);
+                cnt[i] = 0;
+                continue;
+            }
             if (i < 32) word = P.o_hist + i;
             else if (i < 32 + P.table_words) word = P.o_table + (i - 32);
             else word = P.o_oc + (i - 32 - P.table_words);
@@ -318,10 +372,11 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     // reduce the hits queued in this wave's ring, one per lane
     auto drain = [&](uint32_t count) {
         uint32_t tri = 0, spread = 0;
-        if (lane < count) {
+        Hit h{0, 0, 0, 0, 0, 0};
+        const bool valid = lane < count;
+        if (valid) {
             const uint4 e = ring[(qh + lane) & (kRing - 1)];
             const uint32_t where = e.x & 0x3fffffu;
-            Hit h;
             h.t_pq = e.z;
             h.l_p = e.x >> 22;
             h.l_q = l_q;
@@ -349,10 +404,11 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                     o[8] = h.l_r;
                 }
                 tri = 1;
-            } else {
+            } else if (!MULTI) {
                 tri = reduce_hit(P, h, cnt, mask_lds, lut, spread);
             }
         }
+        if (MULTI) reduce_multi(h, valid, cnt, slot_lds, P.n_slots, P.slot_words, lut, P.lut_shift, P.slot_labels);
         my_tri += tri;
         my_spread += spread;
         qh += count;
@@ -643,15 +699,15 @@ __global__ void zero_u64(unsigned long long *p, size_t n)
 
 uint32_t table_size(uint32_t L) { return (L + 2) * (L + 1) * L / 6; }
 
-template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM>
+template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI = false>
 void launch_class(const SurveyParams &P, hipStream_t s, int device)
 {
     if (P.n_tiles == 0) return;
     constexpr uint32_t groups = WAVE ? BLOCK / kWave : 1;
     const uint32_t slots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
-    const LdsLayout L = lds_layout(slots * groups, META || ENUM, counter_words(P.table_words, P.oc_words) * groups,
-                                   BLOCK / kWave, P.lut_shift);
-    auto kern = survey_kernel<LOG_SLOTS, BLOCK, WAVE, META, ENUM>;
+    const uint32_t nc = MULTI ? P.n_slots * P.slot_words : counter_words(P.table_words, P.oc_words);
+    const LdsLayout L = lds_layout(slots * groups, META || ENUM, nc * groups, BLOCK / kWave, P.lut_shift);
+    auto kern = survey_kernel<LOG_SLOTS, BLOCK, WAVE, META, ENUM, MULTI>;
     // attribute and occupancy queries run once per kernel, device and LDS
     // size, so that a survey recorded into a HIP graph issues launches only
     static std::mutex mu;
@@ -676,6 +732,7 @@ void launch_class(const SurveyParams &P, hipStream_t s, int device)
     // each workgroup claims kChunk tiles at a time, or 8 per wave
     const uint64_t claims = WAVE ? (P.n_tiles + 8 * groups - 1) / (8 * groups) : (P.n_tiles + kChunk - 1) / kChunk;
     uint64_t grid = fit;
+    if (P.grid_eighths > 0 && P.grid_eighths < 8) grid = std::max<uint64_t>(1, fit * P.grid_eighths / 8);
     if (grid > claims) grid = claims;
     zero_u64<<<1, 64, 0, s>>>(P.tile_counter, 1);
     TP_CHECK_LAUNCH();
@@ -694,24 +751,24 @@ uint32_t resolve_variant(const tp_graph *g, int c, uint32_t strategy)
     return TP_VAR_GROUP_TABLE;
 }
 
-template <bool META, bool ENUM>
+template <bool META, bool ENUM, bool MULTI = false>
 void launch_variant(int c, uint32_t v, const SurveyParams &P, hipStream_t s, int device)
 {
     switch (v) {
     case TP_VAR_WAVE_TABLE:
-        launch_class<kTinyLogSlots, kSmallBlock, true, META, ENUM>(P, s, device);
+        launch_class<kTinyLogSlots, kSmallBlock, true, META, ENUM, MULTI>(P, s, device);
         break;
     case TP_VAR_GROUP_TABLE:
         if (c == kClassLarge)
-            launch_class<kLargeLogSlots, kLargeBlock, false, META, ENUM>(P, s, device);
+            launch_class<kLargeLogSlots, kLargeBlock, false, META, ENUM, MULTI>(P, s, device);
         else
-            launch_class<kSmallLogSlots, kSmallBlock, false, META, ENUM>(P, s, device);
+            launch_class<kSmallLogSlots, kSmallBlock, false, META, ENUM, MULTI>(P, s, device);
         break;
     case TP_VAR_WAVE_SEARCH:
-        launch_class<0, kSmallBlock, true, META, ENUM>(P, s, device);
+        launch_class<0, kSmallBlock, true, META, ENUM, MULTI>(P, s, device);
         break;
     default:
-        launch_class<0, kSmallBlock, false, META, ENUM>(P, s, device);
+        launch_class<0, kSmallBlock, false, META, ENUM, MULTI>(P, s, device);
         break;
     }
 }
@@ -1001,6 +1058,63 @@ extern "C" tp_status tripoll_launch_replay(tp_launch *launch, void *stream)
 extern "C" tp_status tripoll_launch_free(tp_launch *launch)
 {
     return guard([&] { delete launch; });
+}
+
+// ================================================================ multi-request passes
+
+SlotSpec tp::make_slot(const tp_survey_spec &sp)
+{
+    SlotSpec S{};
+    S.outputs = sp.outputs | TP_OUT_COUNT;
+    S.filters = sp.filters;
+    S.t_lo = (uint32_t)std::min<uint64_t>(sp.t_lo, 0xffffffffull);
+    S.t_hi = (uint32_t)std::min<uint64_t>(sp.t_hi, 0xffffffffull);
+    S.window_empty = sp.t_lo > 0xffffffffull;
+    S.spread_any = sp.spread_lt > 0;
+    S.spread_le = sp.spread_lt == 0 ? 0u : (uint32_t)std::min<uint64_t>(sp.spread_lt - 1, 0xffffffffull);
+    S.off = 0;
+    for (int i = 0; i < 13; ++i) S.label_mask[i] = sp.label_mask[i];
+    return S;
+}
+
+uint32_t tp::slot_words(uint32_t n_labels) { return TP_BW_TABLE + table_size(n_labels); }
+
+void tp::zero_words(unsigned long long *p, size_t n, hipStream_t s)
+{
+    if (!n) return;
+    zero_u64<<<grid_for(n, 256), 256, 0, s>>>(p, n);
+    TP_CHECK_LAUNCH();
+}
+
+void tp::multi_segment_enqueue(const tp_graph *g, const SlotSpec *dev_slots, uint32_t n_slots, uint32_t n_labels,
+                               bool labels, unsigned long long *dev_out, unsigned long long *dev_counter, uint32_t seg,
+                               uint32_t n_seg, uint32_t grid_eighths, hipStream_t s)
+{
+    if (n_slots == 0 || n_slots > kMaxSlots) fail(TP_ERR_INVALID, "multi-request pass: 1..16 slots");
+    if (n_seg == 0 || seg >= n_seg) fail(TP_ERR_INVALID, "multi-request pass: bad segment");
+    if (g->m == 0 || g->n_in == 0) return;
+    tp_survey_spec sp{};
+    sp.outputs = TP_OUT_COUNT | TP_OUT_CLOSE_HIST;
+    sp.n_labels = n_labels;
+    SurveyParams P = make_params(g, &sp, dev_out, dev_counter);
+    P.slots = dev_slots;
+    P.n_slots = n_slots;
+    P.slot_words = slot_words(n_labels);
+    P.g_stride = P.slot_words;
+    P.slot_labels = labels ? 1u : 0u;
+    P.lut_shift = 0;
+    if (labels)
+        while ((1u << P.lut_shift) < n_labels) ++P.lut_shift;
+    P.grid_eighths = grid_eighths;
+    for (int c = 0; c < kNumClasses; ++c) {
+        const uint64_t nt = g->n_tiles[c];
+        const uint64_t a = nt * seg / n_seg, b = nt * (seg + 1) / n_seg;
+        if (a == b) continue;
+        // the kernel walks its tile list from the end
+        P.tiles = g->tiles[c].get() + a;
+        P.n_tiles = b - a;
+        launch_variant<true, false, true>(c, resolve_variant(g, c, TP_STRAT_AUTO), P, s, g->device);
+    }
 }
 
 // ================================================================ plan and tuning

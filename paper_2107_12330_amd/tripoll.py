@@ -87,6 +87,27 @@ class tp_tune_result(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+TP_SERVER_TAGS = 8
+
+
+class tp_server_config(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_uint32), ("n_labels", ctypes.c_uint32), ("hbm_budget", ctypes.c_uint64),
+                ("step_wedges", ctypes.c_uint64), ("max_queue", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class tp_request_info(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint32), ("steps", ctypes.c_uint32), ("arrival_us", ctypes.c_double),
+                ("admit_us", ctypes.c_double), ("done_us", ctypes.c_double)]
+
+
+class tp_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("waiting", ctypes.c_uint64), ("running", ctypes.c_uint64), ("steps", ctypes.c_uint64),
+                ("triangles", ctypes.c_uint64), ("hbm_used", ctypes.c_uint64), ("hbm_budget", ctypes.c_uint64),
+                ("elapsed_s", ctypes.c_double), ("count", ctypes.c_uint64 * TP_SERVER_TAGS),
+                ("p50_ms", ctypes.c_double * TP_SERVER_TAGS), ("p99_ms", ctypes.c_double * TP_SERVER_TAGS)]
+
+
 class TripollError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
@@ -115,6 +136,16 @@ SIGNATURES = {
     "tripoll_get_plan": (ctypes.c_int, [_P, ctypes.POINTER(tp_plan)]),
     "tripoll_set_plan": (ctypes.c_int, [_P, ctypes.POINTER(tp_plan), _P]),
     "tripoll_tune": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, ctypes.POINTER(tp_tune_result)]),
+    "tripoll_server_create": (ctypes.c_int, [ctypes.POINTER(tp_server_config), ctypes.POINTER(_P)]),
+    "tripoll_server_destroy": (ctypes.c_int, [_P]),
+    "tripoll_server_add_graph": (ctypes.c_int, [_P, ctypes.POINTER(tp_edge_list), ctypes.POINTER(ctypes.c_uint32)]),
+    "tripoll_server_remove_graph": (ctypes.c_int, [_P, ctypes.c_uint32]),
+    "tripoll_server_graph_stats": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.POINTER(tp_graph_stats)]),
+    "tripoll_server_submit": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.POINTER(tp_survey_spec), ctypes.c_uint32,
+                                             ctypes.POINTER(ctypes.c_uint64)]),
+    "tripoll_server_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(tp_survey_result),
+                                           ctypes.POINTER(tp_request_info)]),
+    "tripoll_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(tp_server_stats)]),
     "tripoll_msidx": (ctypes.c_uint32, [ctypes.c_uint32] * 3),
     "tripoll_trim": (ctypes.c_int, []),
     "tripoll_cached_bytes": (ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64)]),
@@ -232,6 +263,51 @@ def tripoll_tune(g: int, spec: tp_survey_spec, stream=None) -> tp_tune_result:
     r = tp_tune_result()
     _check(load().tripoll_tune(g, ctypes.byref(spec), stream, ctypes.byref(r)))
     return r
+
+
+def tripoll_server_create(cfg: tp_server_config) -> int:
+    h = _P()
+    _check(load().tripoll_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h.value
+
+
+def tripoll_server_destroy(srv: int) -> None:
+    _check(load().tripoll_server_destroy(srv))
+
+
+def tripoll_server_add_graph(srv: int, edges: tp_edge_list) -> int:
+    gid = ctypes.c_uint32(0)
+    _check(load().tripoll_server_add_graph(srv, ctypes.byref(edges), ctypes.byref(gid)))
+    return gid.value
+
+
+def tripoll_server_remove_graph(srv: int, graph_id: int) -> None:
+    _check(load().tripoll_server_remove_graph(srv, graph_id))
+
+
+def tripoll_server_graph_stats(srv: int, graph_id: int) -> tp_graph_stats:
+    st = tp_graph_stats()
+    _check(load().tripoll_server_graph_stats(srv, graph_id, ctypes.byref(st)))
+    return st
+
+
+def tripoll_server_submit(srv: int, graph_id: int, spec: tp_survey_spec, tag: int = 0) -> int:
+    t = ctypes.c_uint64(0)
+    _check(load().tripoll_server_submit(srv, graph_id, ctypes.byref(spec), tag, ctypes.byref(t)))
+    return t.value
+
+
+def tripoll_server_wait(srv: int, ticket: int, timeout_us: int = -1):
+    res = tp_survey_result()
+    info = tp_request_info()
+    _check(load().tripoll_server_wait(srv, ticket, timeout_us, ctypes.byref(res), ctypes.byref(info)))
+    return res, info
+
+
+def tripoll_server_stats(srv: int) -> tp_server_stats:
+    st = tp_server_stats()
+    _check(load().tripoll_server_stats(srv, ctypes.byref(st)))
+    return st
 
 
 def tripoll_msidx(a: int, b: int, c: int) -> int:
@@ -459,3 +535,59 @@ def plan_dict(p: tp_plan) -> dict:
 def tune_dict(r: tp_tune_result) -> dict:
     return dict(chosen=plan_dict(r.chosen), default_ms=[round(float(x), 3) for x in r.default_ms],
                 tuned_ms=[round(float(x), 3) for x in r.tuned_ms], trials=int(r.trials))
+
+
+# ------------------------------------------------------------------ served mode
+
+class Server:
+    """Owning handle of a survey server (tripoll_server_*)."""
+
+    def __init__(self, max_slots=8, n_labels=8, hbm_budget=0, step_wedges=0, max_queue=0):
+        cfg = tp_server_config()
+        cfg.max_slots, cfg.n_labels, cfg.hbm_budget = max_slots, n_labels, hbm_budget
+        cfg.step_wedges, cfg.max_queue = step_wedges, max_queue
+        self.n_labels = n_labels
+        self.handle = tripoll_server_create(cfg)
+
+    def add_graph(self, n, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX) -> int:
+        return tripoll_server_add_graph(self.handle, edge_list(n, src, dst, ts, vlab, tie))
+
+    def remove_graph(self, graph_id: int):
+        tripoll_server_remove_graph(self.handle, graph_id)
+
+    def graph_stats(self, graph_id: int) -> dict:
+        return stats_dict(tripoll_server_graph_stats(self.handle, graph_id))
+
+    def submit(self, graph_id: int, tag: int = 0, **spec_kw) -> int:
+        spec_kw.setdefault("n_labels", self.n_labels)
+        return tripoll_server_submit(self.handle, graph_id, make_spec(**spec_kw), tag)
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> tuple:
+        res, info = tripoll_server_wait(self.handle, ticket, timeout_us)
+        d = result_dict(res, self.n_labels)
+        return d, dict(tag=int(info.tag), steps=int(info.steps), arrival_us=info.arrival_us,
+                       admit_us=info.admit_us, done_us=info.done_us)
+
+    def stats(self) -> dict:
+        st = tripoll_server_stats(self.handle)
+        d = {f: getattr(st, f) for f, _ in tp_server_stats._fields_ if f not in ("count", "p50_ms", "p99_ms")}
+        for f in ("count", "p50_ms", "p99_ms"):
+            d[f] = list(getattr(st, f))
+        return d
+
+    def close(self):
+        if self.handle:
+            tripoll_server_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

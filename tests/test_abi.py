@@ -53,12 +53,14 @@ int main(void) {
   printf("%u %u %u %u\\n", TP_RW_TABLE, TP_RW_OPEN_CLOSE, TP_RW_SCRATCH, TP_RESULT_WORDS);
   printf("%zu %zu %zu %zu %u %u %u\\n", sizeof(tp_batch_edges), sizeof(tp_plan), sizeof(tp_tune_result),
          offsetof(tp_tune_result, trials), TP_BW_TABLE, TP_BATCH_SCRATCH_WORDS, TP_NUM_CLASSES);
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(tp_server_config), sizeof(tp_request_info), sizeof(tp_server_stats),
+         offsetof(tp_server_stats, p50_ms), offsetof(tp_server_stats, elapsed_s));
   return 0;
 }
 """)
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-std=c11", "-I", INCLUDE, str(src), "-o", str(exe)])
-    l1, l2, l3, l4 = subprocess.check_output([str(exe)]).decode().split("\n")[:4]
+    l1, l2, l3, l4, l5 = subprocess.check_output([str(exe)]).decode().split("\n")[:5]
     assert list(map(int, l1.split())) == [ctypes.sizeof(tp.tp_edge_list), ctypes.sizeof(tp.tp_graph_stats),
                                           ctypes.sizeof(tp.tp_survey_spec), ctypes.sizeof(tp.tp_survey_result)]
     assert list(map(int, l2.split())) == [tp.tp_graph_stats.phase_ms.offset, tp.tp_survey_spec.label_mask.offset,
@@ -69,6 +71,9 @@ int main(void) {
     assert list(map(int, l4.split())) == [ctypes.sizeof(tp.tp_batch_edges), ctypes.sizeof(tp.tp_plan),
                                           ctypes.sizeof(tp.tp_tune_result), tp.tp_tune_result.trials.offset,
                                           tp.TP_BW_TABLE, tp.TP_BATCH_SCRATCH_WORDS, tp.TP_NUM_CLASSES]
+    assert list(map(int, l5.split())) == [ctypes.sizeof(tp.tp_server_config), ctypes.sizeof(tp.tp_request_info),
+                                          ctypes.sizeof(tp.tp_server_stats), tp.tp_server_stats.p50_ms.offset,
+                                          tp.tp_server_stats.elapsed_s.offset]
 
 
 def test_msidx_is_colex_rank():

@@ -1,0 +1,238 @@
+"""GPU tests of served mode: requests on resident graphs answered in shared
+multi-request passes must equal the same surveys run alone, bit for bit,
+whenever they arrive; errors and limits are reported as documented."""
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2107_12330_amd import tripoll as tp
+
+pytestmark = pytest.mark.gpu
+
+L = 8
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    return torch
+
+
+def graph_arrays(scale, seed, ef=16):
+    g = synth.generate(synth.GraphSpec("rmat", scale, ef, seed, ("uniform", 20), ("uniform", L)))
+    return g["n"], g["src"], g["dst"], g["ts"], g["vlab"]
+
+
+def random_specs(rng, k):
+    """A mix of the served request kinds: full closure histograms, time
+    windows of log-uniform width, label-predicate counts, label tables and
+    spread counts."""
+    out = []
+    for i in range(k):
+        kind = i % 4
+        if kind == 0:
+            out.append(dict(outputs=("count", "close_hist")))
+        elif kind == 1:
+            w = int(2 ** rng.uniform(8, 20))
+            t0 = int(rng.integers(0, 1 << 20))
+            out.append(dict(outputs=("count", "close_hist"), window=(t0, t0 + w)))
+        elif kind == 2:
+            mask = [int(x) for x in rng.choice(tp.table_size(L), size=40, replace=False)]
+            out.append(dict(outputs=("count",), label_mask=mask))
+        else:
+            out.append(dict(outputs=("count", "label_table", "spread_count"), spread_lt=int(rng.integers(1, 1 << 18))))
+    return out
+
+
+def upload(torch, arrays):
+    n, s, d, t, v = arrays
+    return n, [torch.from_numpy(x).cuda() for x in (s, d, t, v)]
+
+
+def alone(torch, arrays, spec):
+    n, dev = upload(torch, arrays)
+    with tp.build_graph(n, *dev, stream=torch.cuda.current_stream().cuda_stream) as G:
+        return tp.survey(G, stream=torch.cuda.current_stream().cuda_stream, n_labels=L, **spec)
+
+
+def same(a, b, spec):
+    assert a["triangles"] == b["triangles"]
+    assert np.array_equal(a["close_hist"], b["close_hist"])
+    assert a["spread_count"] == b["spread_count"]
+    if "label_table" in spec.get("outputs", ()):
+        assert np.array_equal(a["label_table"], b["label_table"])
+
+
+def test_mix_equals_alone(torch_cuda):
+    """Requests that join a running pass at different segments, on a large
+    graph (many segments) and two small ones (one segment, second stream),
+    each return what the survey alone returns."""
+    torch = torch_cuda
+    big = graph_arrays(15, synth.MASTER_SEED + 501)
+    smalls = [graph_arrays(10, synth.MASTER_SEED + 502), graph_arrays(11, synth.MASTER_SEED + 503, ef=8)]
+    rng = np.random.default_rng(11)
+    with tp.Server(max_slots=4, n_labels=L, step_wedges=1 << 18) as srv:
+        n, dev = upload(torch, big)
+        gid_big = srv.add_graph(n, *dev)
+        st = srv.graph_stats(gid_big)
+        say("big graph: probes", st["probes"], "segments ~", -(-st["probes"] // (1 << 18)))
+        assert st["probes"] > 4 * (1 << 18)
+        gid_small = []
+        for a in smalls:
+            n, dev = upload(torch, a)
+            gid_small.append(srv.add_graph(n, *dev))
+        torch.cuda.synchronize()
+        jobs = []  # (ticket, arrays, spec)
+        specs = random_specs(rng, 24)
+        for i, spec in enumerate(specs):
+            which = i % 3
+            gid = gid_big if which == 0 else gid_small[which - 1]
+            arrays = big if which == 0 else smalls[which - 1]
+            jobs.append((srv.submit(gid, tag=which, **spec), arrays, spec))
+            time.sleep(float(rng.uniform(0, 0.004)))  # stagger arrivals across steps
+        results = [srv.wait(t, timeout_us=60_000_000) for t, _, _ in jobs]
+        stats = srv.stats()
+        say("server stats", stats)
+        assert stats["completed"] == len(jobs) and stats["waiting"] == 0 and stats["running"] == 0
+        assert stats["count"][0] == 8 and stats["count"][1] == 8 and stats["count"][2] == 8
+        assert stats["p99_ms"][0] >= stats["p50_ms"][0] > 0
+        # big-graph requests took part in as many steps as there are segments
+        steps_big = {info["steps"] for (res, info), (t, a, s) in zip(results, jobs) if a is big}
+        assert len(steps_big) == 1 and steps_big.pop() > 4
+        for (res, info), (t, arrays, spec) in zip(results, jobs):
+            same(res, alone(torch, arrays, spec), spec)
+            assert info["arrival_us"] <= info["admit_us"] <= info["done_us"]
+        assert stats["triangles"] == sum(r["triangles"] for r, _ in results)
+
+
+def test_served_results_against_oracle(torch_cuda):
+    """Closure histogram and windowed count of a served graph against the
+    oracle directly."""
+    torch = torch_cuda
+    arrays = graph_arrays(12, synth.MASTER_SEED + 504)
+    n, s, d, t, v = arrays
+    with tp.Server(max_slots=2, n_labels=L, step_wedges=1 << 14) as srv:
+        n, dev = upload(torch, arrays)
+        gid = srv.add_graph(n, *dev)
+        t1 = srv.submit(gid, outputs=("count", "close_hist", "label_table"))
+        t2 = srv.submit(gid, outputs=("count", "close_hist"), window=(1000, 700000))
+        r1, _ = srv.wait(t1)
+        r2, _ = srv.wait(t2)
+    ref1 = oracle.survey(n, s, d, t, v, outputs=("count", "close_hist", "label_table"), n_labels=L)
+    ref2 = oracle.survey(n, s, d, t, v, outputs=("count", "close_hist"), n_labels=L, window=(1000, 700000))
+    assert r1["triangles"] == ref1["triangles"] and np.array_equal(r1["close_hist"], ref1["close_hist"])
+    assert np.array_equal(r1["label_table"], ref1["label_table"])
+    assert r2["triangles"] == ref2["triangles"] and np.array_equal(r2["close_hist"], ref2["close_hist"])
+
+
+def test_concurrent_submitters(torch_cuda):
+    """Several host threads submit and wait at once."""
+    torch = torch_cuda
+    arrays = graph_arrays(12, synth.MASTER_SEED + 505)
+    want = alone(torch, arrays, dict(outputs=("count", "close_hist")))
+    errors = []
+    with tp.Server(max_slots=3, n_labels=L, step_wedges=1 << 13) as srv:
+        n, dev = upload(torch, arrays)
+        gid = srv.add_graph(n, *dev)
+
+        def client(k):
+            try:
+                for _ in range(4):
+                    r, _ = srv.wait(srv.submit(gid, tag=k, outputs=("count", "close_hist")), timeout_us=60_000_000)
+                    same(r, want, dict(outputs=("count", "close_hist")))
+            except Exception as e:  # reported below
+                errors.append(repr(e))
+
+        th = [threading.Thread(target=client, args=(k,)) for k in range(4)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        assert srv.stats()["completed"] == 16
+    assert not errors, errors
+
+
+def test_server_errors(torch_cuda):
+    torch = torch_cuda
+    arrays = graph_arrays(10, synth.MASTER_SEED + 506)
+    n, dev = upload(torch, arrays)
+    with tp.Server(max_slots=2, n_labels=L) as srv:
+        gid = srv.add_graph(n, *dev)
+        with pytest.raises(tp.TripollError) as e:
+            srv.submit(gid + 100, outputs=("count",))
+        assert e.value.status == tp.TP_ERR_NOT_FOUND
+        with pytest.raises(tp.TripollError) as e:
+            srv.submit(gid, outputs=("count", "open_close"))
+        assert e.value.status == tp.TP_ERR_UNSUPPORTED
+        with pytest.raises(tp.TripollError) as e:
+            srv.submit(gid, outputs=("label_table",), n_labels=4)
+        assert e.value.status == tp.TP_ERR_INVALID
+        with pytest.raises(tp.TripollError) as e:
+            srv.submit(gid, outputs=("count",), window=(10, 5))
+        assert e.value.status == tp.TP_ERR_INVALID
+        with pytest.raises(tp.TripollError) as e:
+            srv.submit(gid, tag=8, outputs=("count",))
+        assert e.value.status == tp.TP_ERR_INVALID
+        with pytest.raises(tp.TripollError) as e:
+            srv.wait(12345, timeout_us=0)
+        assert e.value.status == tp.TP_ERR_NOT_FOUND
+        t = srv.submit(gid, outputs=("count",))
+        r, _ = srv.wait(t)
+        with pytest.raises(tp.TripollError) as e:
+            srv.wait(t, timeout_us=0)  # a ticket is taken once
+        assert e.value.status == tp.TP_ERR_NOT_FOUND
+        srv.remove_graph(gid)
+        with pytest.raises(tp.TripollError) as e:
+            srv.remove_graph(gid)
+        assert e.value.status == tp.TP_ERR_NOT_FOUND
+    # a budget too small for the graph keeps nothing
+    with tp.Server(max_slots=2, n_labels=L, hbm_budget=1 << 16) as srv:
+        with pytest.raises(tp.TripollError) as e:
+            srv.add_graph(n, *dev)
+        assert e.value.status == tp.TP_ERR_OOM
+        assert srv.stats()["hbm_used"] == 0
+
+
+def test_memory_admission_and_queue_limit(torch_cuda):
+    """With room for the graph and one request buffer only, requests are
+    admitted one at a time; the queue refuses past its capacity."""
+    torch = torch_cuda
+    arrays = graph_arrays(13, synth.MASTER_SEED + 507)
+    n, dev = upload(torch, arrays)
+    words = 35 + tp.table_size(L)
+    per_req = words * 8 + 136
+    with tp.build_graph(n, *dev, stream=torch.cuda.current_stream().cuda_stream) as G:
+        gbytes = G.stats()["device_bytes"]
+    graph_bytes = gbytes + 16 * 136 + (4 * words + 1) * 8
+    with tp.Server(max_slots=4, n_labels=L, hbm_budget=graph_bytes + per_req + 64, step_wedges=1 << 10,
+                   max_queue=3) as srv:
+        gid = srv.add_graph(n, *dev)
+        assert srv.stats()["hbm_used"] == graph_bytes
+        tickets = [srv.submit(gid, outputs=("count",)) for _ in range(3)]
+        # one running, two waiting; a fourth waiting request does not fit the queue
+        busy = 0
+        for _ in range(3):
+            try:
+                tickets.append(srv.submit(gid, outputs=("count",)))
+            except tp.TripollError as e:
+                assert e.status == tp.TP_ERR_BUSY
+                busy += 1
+        st = srv.stats()
+        say("admission", st)
+        assert busy >= 1 and st["rejected"] == busy
+        assert st["running"] <= 1
+        res = [srv.wait(t, timeout_us=60_000_000)[0]["triangles"] for t in tickets]
+        assert len(set(res)) == 1
+        assert srv.stats()["hbm_used"] == graph_bytes

@@ -1,0 +1,18 @@
+"""Host-only tests of the survey server's scheduling policy (sched.hpp):
+every request sees each segment of a pass exactly once whenever it joins,
+slot limits, memory admission, queue order and capacity, percentiles."""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(os.path.dirname(HERE), "paper_2107_12330_amd", "csrc")
+
+
+def test_scheduler_policy(tmp_path):
+    exe = tmp_path / "sched_driver"
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-Wall", "-I", CSRC,
+                           os.path.join(HERE, "native", "sched_driver.cpp"), "-o", str(exe)])
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout
+    assert "FAIL" not in r.stdout and r.stdout.strip().endswith("PASSED")
