@@ -272,12 +272,183 @@ def batch_bench(args, torch, synth, tp) -> dict:
     }
 
 
+def fifo_latencies(arrivals, service):
+    """Latencies of a single server taking requests one at a time in arrival
+    order, with the given service times (seconds)."""
+    free_at = 0.0
+    lat = []
+    for a, sv in zip(arrivals, service):
+        start = max(a, free_at)
+        free_at = start + sv
+        lat.append(free_at - a)
+    return lat
+
+
+def served_bench(args, torch, synth, tp) -> dict:
+    """Served form: a resident R-MAT graph (scale 28 by default) and a pool
+    of resident small graphs (scales 16..20) answer Poisson request streams
+    through the survey server (continuous batching).  Request kinds on the
+    large graph: full closure histograms (tag 0), time windows [t0, t0 + w]
+    with w log-uniform in [2^12, 2^31] (tag 1), label-predicate counts
+    (tag 2); on the pool graphs (tag 3): the same kinds at random.  Latency
+    is arrival to result in host memory, measured by the server.
+
+    Baseline: the same arrivals served one request at a time.  The time
+    alone of one request of every (graph, kind) class is measured with
+    tripoll_survey on the same resident graph, and a first-come-first-served
+    single queue over the same arrival times, with those service times,
+    gives the serial latencies."""
+    w = synth.workload(5, scale=args.scale)
+    ex = w.extra
+    gs = w.graph
+    rng = np.random.default_rng(synth.MASTER_SEED + 5)
+    L = w.n_labels
+    sptr = torch.cuda.current_stream().cuda_stream
+    srv = tp.Server(max_slots=args.slots, n_labels=L)
+    try:
+        log("generating %s: n=%d raw edges=%d" % (w.name, gs.n, gs.n_edges))
+        t0 = time.perf_counter()
+        g = synth.generate(gs)
+        dev = [torch.from_numpy(g[k].view(np.int32) if g[k].dtype == np.uint32 else g[k]).to("cuda")
+               for k in ("src", "dst", "ts", "vlab")]
+        del g
+        torch.cuda.synchronize()
+        log("generated and uploaded in %.1f s; building the resident graph" % (time.perf_counter() - t0))
+        t0 = time.perf_counter()
+        big = srv.add_graph(gs.n, *dev)
+        build_s = time.perf_counter() - t0
+        del dev
+        torch.cuda.empty_cache()
+        bst = srv.graph_stats(big)
+        log("resident: m=%d, wedge checks %d, %.1f GB, built in %.1f s" % (
+            bst["n_edges"], bst["probes"], bst["device_bytes"] / 1e9, build_s))
+        pool = []
+        for k, sc in enumerate(range(ex["pool_scale_lo"], ex["pool_scale_hi"] + 1)):
+            ps = synth.GraphSpec("rmat", sc, 16, synth.MASTER_SEED + 50 + k, ("uniform", 31), ("uniform", L))
+            pg = synth.generate(ps)
+            pdev = [torch.from_numpy(pg[x].view(np.int32) if pg[x].dtype == np.uint32 else pg[x]).to("cuda")
+                    for x in ("src", "dst", "ts", "vlab")]
+            pool.append(srv.add_graph(ps.n, *pdev))
+            del pdev
+        torch.cuda.synchronize()
+        log("pool of %d graphs resident; hbm %.1f of %.1f GB" % (len(pool), srv.stats()["hbm_used"] / 1e9,
+                                                                 srv.stats()["hbm_budget"] / 1e9))
+
+        # the request stream
+        n_tab = tp.table_size(L)
+
+        def make_request(kind):
+            if kind == 0:
+                return dict(outputs=("count", "close_hist"))
+            if kind == 1:
+                width = int(2 ** (12 + 19 * rng.random()))
+                lo = int(rng.integers(0, 1 << 31))
+                return dict(outputs=("count", "close_hist"), window=(lo, min(lo + width, (1 << 32) - 1)))
+            mask = [int(i) for i in np.nonzero(rng.random(n_tab) < 0.5)[0]]
+            return dict(outputs=("count",), label_mask=mask)
+
+        reqs = []  # (arrival s, graph, tag, spec)
+        for rate, is_big in ((args.rate_big, True), (args.rate_small, False)):
+            t = 0.0
+            while rate > 0:
+                t += rng.exponential(1.0 / rate)
+                if t >= args.duration:
+                    break
+                kind = int(rng.integers(0, 3))
+                gid = big if is_big else pool[int(rng.integers(0, len(pool)))]
+                reqs.append((t, gid, kind if is_big else 3, make_request(kind)))
+        reqs.sort(key=lambda r: r[0])
+        log("%d requests over %.0f s (%d on the large graph)" % (len(reqs), args.duration,
+                                                               sum(1 for r in reqs if r[1] == big)))
+        tickets = []
+        start = time.perf_counter()
+        for at, gid, tag, spec in reqs:
+            delay = at - (time.perf_counter() - start)
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(srv.submit(gid, tag=tag, **spec))
+        log("all submitted after %.1f s; draining" % (time.perf_counter() - start))
+        results = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - start
+        st = srv.stats()
+        log("served: %s" % {k: st[k] for k in ("completed", "steps", "elapsed_s")})
+
+        # serial baseline: the time alone of the first request of every
+        # (graph, kind) class, measured on the same resident graph, stands
+        # for the service time of every request of that class
+        log("timing one request of each class alone")
+        alone = {}
+        for at, gid, tag, spec in reqs:
+            key = (gid, tag if gid == big else ("w" if "window" in spec else "m" if "label_mask" in spec else "h"))
+            if key in alone:
+                continue
+            h = srv.graph(gid)
+            t1 = time.perf_counter()
+            tp.tripoll_survey(h, tp.make_spec(n_labels=L, **spec), sptr)
+            alone[key] = time.perf_counter() - t1
+        service = [alone[(gid, tag if gid == big else ("w" if "window" in spec else "m" if "label_mask" in spec
+                                                        else "h"))] for at, gid, tag, spec in reqs]
+        lat_serial = fifo_latencies([r[0] for r in reqs], service)
+        tags = {0: "large: closure histogram", 1: "large: time window", 2: "large: label predicate",
+                3: "pool (scale %d-%d)" % (ex["pool_scale_lo"], ex["pool_scale_hi"])}
+        per = {}
+        for tg, name in tags.items():
+            ser = [l for l, r in zip(lat_serial, reqs) if r[2] == tg]
+            per[name] = {"requests": int(st["count"][tg]), "p50_ms": round(st["p50_ms"][tg], 2),
+                         "p99_ms": round(st["p99_ms"][tg], 2),
+                         "serial_p50_ms": round(float(np.percentile(ser, 50)) * 1e3, 2) if ser else None,
+                         "serial_p99_ms": round(float(np.percentile(ser, 99)) * 1e3, 2) if ser else None}
+        tri = st["triangles"]
+        serial_span = max(lat_serial[i] + reqs[i][0] for i in range(len(reqs))) if reqs else 0.0
+        out = {
+            "metric": METRIC,
+            "value": tri / st["elapsed_s"],
+            "unit": "triangles/s",
+            "n_gpus": 1,
+            "steps": len(reqs),
+            "warmup": 0,
+            "ms_per_step": round(st["elapsed_s"] * 1e3 / max(1, len(reqs)), 3),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "u32",
+            "data": "synthetic",
+            "config": {"workload": w.name, "kind": gs.kind, "scale": gs.scale, "edge_factor": gs.edge_factor,
+                       "timestamps": list(gs.ts), "labels": list(gs.labels), "edges": bst["n_edges"],
+                       "pool_scales": [ex["pool_scale_lo"], ex["pool_scale_hi"]], "duration_s": args.duration,
+                       "rate_big_per_s": args.rate_big, "rate_small_per_s": args.rate_small,
+                       "slots": args.slots,
+                       "step": "one served request (value: triangles surveyed per second of serving)"},
+            "served": {"requests": len(reqs), "completed": int(st["completed"]), "device_steps": int(st["steps"]),
+                       "elapsed_s": round(st["elapsed_s"], 3), "wall_s": round(wall, 3),
+                       "requests_per_s": round(st["completed"] / st["elapsed_s"], 3),
+                       "triangles": int(tri), "latency": per,
+                       "hbm_used_gb": round(st["hbm_used"] / 1e9, 2)},
+            "serial_baseline": {"kind": "same arrivals, one request at a time (FIFO) with each request's "
+                                        "measured time alone",
+                                "span_s": round(serial_span, 3),
+                                "requests_per_s": round(len(reqs) / serial_span, 3) if serial_span else None,
+                                "service_s_large": round(float(np.mean([sv for sv, r in zip(service, reqs)
+                                                                       if r[1] == big] or [0])), 3),
+                                "service_s_pool": round(float(np.mean([sv for sv, r in zip(service, reqs)
+                                                                      if r[1] != big] or [0])), 4)},
+            "graph_build_s": round(build_s, 2),
+        }
+        return out
+    finally:
+        srv.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", type=int, default=3, choices=(1, 2, 3, 4))
+    ap.add_argument("--workload", type=int, default=3, choices=(1, 2, 3, 4, 5))
+    ap.add_argument("--duration", type=float, default=60.0, help="workload 5: seconds of request arrivals")
+    ap.add_argument("--rate-big", type=float, default=0.5, help="workload 5: requests/s on the large graph")
+    ap.add_argument("--rate-small", type=float, default=20.0, help="workload 5: requests/s on the pool graphs")
+    ap.add_argument("--slots", type=int, default=8, help="workload 5: request slots per resident graph")
     ap.add_argument("--graphs", type=int, default=None, help="batch size override (workload 4)")
     ap.add_argument("--loop-stride", type=int, default=10,
                     help="workload 4: time the one-graph-per-launch loop on every k-th graph")
@@ -309,6 +480,9 @@ def main():
 
     if args.workload == 4:
         print(json.dumps(batch_bench(args, torch, synth, tp)), flush=True)
+        return
+    if args.workload == 5:
+        print(json.dumps(served_bench(args, torch, synth, tp)), flush=True)
         return
 
     w = synth.workload(args.workload, scale=args.scale)

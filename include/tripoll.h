@@ -491,6 +491,11 @@ tp_status tripoll_server_remove_graph(tp_server *srv, uint32_t graph_id);
 /* Statistics of a resident graph. */
 tp_status tripoll_server_graph_stats(tp_server *srv, uint32_t graph_id, tp_graph_stats *out);
 
+/* The resident graph itself, borrowed (valid until it is removed), for
+ * direct calls such as tripoll_survey; such calls may run beside the
+ * server's own work. */
+tp_status tripoll_server_graph(tp_server *srv, uint32_t graph_id, const tp_graph **out);
+
 /*
  * Queue a survey of graph `graph_id`.  Returns at once with a ticket.
  * `tag` (0..7) groups requests for the latency statistics.

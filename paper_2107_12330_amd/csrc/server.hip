@@ -414,6 +414,17 @@ extern "C" tp_status tripoll_server_graph_stats(tp_server *srv, uint32_t graph_i
     });
 }
 
+extern "C" tp_status tripoll_server_graph(tp_server *srv, uint32_t graph_id, const tp_graph **out)
+{
+    return guard([&] {
+        if (!srv || !out) fail(TP_ERR_INVALID, "tripoll_server_graph: NULL argument");
+        std::lock_guard<std::mutex> lk(srv->mu);
+        auto it = srv->graphs.find(graph_id);
+        if (it == srv->graphs.end()) fail(TP_ERR_NOT_FOUND, "tripoll_server_graph: unknown graph");
+        *out = it->second->g;
+    });
+}
+
 extern "C" tp_status tripoll_server_submit(tp_server *srv, uint32_t graph_id, const tp_survey_spec *spec,
                                            uint32_t tag, uint64_t *ticket)
 {

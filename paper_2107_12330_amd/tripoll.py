@@ -141,6 +141,7 @@ SIGNATURES = {
     "tripoll_server_add_graph": (ctypes.c_int, [_P, ctypes.POINTER(tp_edge_list), ctypes.POINTER(ctypes.c_uint32)]),
     "tripoll_server_remove_graph": (ctypes.c_int, [_P, ctypes.c_uint32]),
     "tripoll_server_graph_stats": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.POINTER(tp_graph_stats)]),
+    "tripoll_server_graph": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.POINTER(_P)]),
     "tripoll_server_submit": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.POINTER(tp_survey_spec), ctypes.c_uint32,
                                              ctypes.POINTER(ctypes.c_uint64)]),
     "tripoll_server_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(tp_survey_result),
@@ -289,6 +290,12 @@ def tripoll_server_graph_stats(srv: int, graph_id: int) -> tp_graph_stats:
     st = tp_graph_stats()
     _check(load().tripoll_server_graph_stats(srv, graph_id, ctypes.byref(st)))
     return st
+
+
+def tripoll_server_graph(srv: int, graph_id: int) -> int:
+    h = _P()
+    _check(load().tripoll_server_graph(srv, graph_id, ctypes.byref(h)))
+    return h.value
 
 
 def tripoll_server_submit(srv: int, graph_id: int, spec: tp_survey_spec, tag: int = 0) -> int:
@@ -557,6 +564,10 @@ class Server:
 
     def graph_stats(self, graph_id: int) -> dict:
         return stats_dict(tripoll_server_graph_stats(self.handle, graph_id))
+
+    def graph(self, graph_id: int) -> int:
+        """Borrowed tp_graph handle of a resident graph."""
+        return tripoll_server_graph(self.handle, graph_id)
 
     def submit(self, graph_id: int, tag: int = 0, **spec_kw) -> int:
         spec_kw.setdefault("n_labels", self.n_labels)
