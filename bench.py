@@ -48,7 +48,7 @@ def kernel_key(c: int, v: int, meta: bool) -> str:
     v = resolve_variant(c, v)
     log_slots, block, wave = {1: (6, 256, "true"), 2: (12, 1024, "false") if c == 2 else (10, 256, "false"),
                               3: (0, 256, "false"), 4: (0, 256, "true")}[v]
-    return "survey_kernel<%d,%d,%s,%s,false>" % (log_slots, block, wave, "true" if meta else "false")
+    return "survey_kernel<%d,%d,%s,%s,false,false>" % (log_slots, block, wave, "true" if meta else "false")
 
 
 def log(*a):
@@ -57,7 +57,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("survey.hip", "graph.hpp", "plan.hpp", "tp_internal.hpp"):
+    for f in ("survey.hip", "graph.hpp", "plan.hpp", "multi.hpp", "tp_internal.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2107_12330_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
