@@ -28,6 +28,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <type_traits>
 
 #include "graph.hpp"
 #include "multi.hpp"
@@ -251,8 +252,12 @@ __device__ __forceinline__ T sload(const T *p)
 // `len` slots of p's row starting at `start`.
 // One in-edge as the wave walks it: the candidates of p -> q are the `len`
 // slots of p's row starting at `start`.  A block holds one in-edge per lane.
+// Loaded values are kept as loaded (no arithmetic on them until they are
+// read), so that no instruction waits for a load right after issuing it.
 struct RecBlock {
-    uint32_t start_lo, start_hi, len, t_pq, l_p, p;
+    uint32_t start_lo, start_hi;  // first candidate slot
+    uint64_t rend;                // end of the pivot's row
+    uint32_t t_pq, l_p, p;
 };
 
 // LOG_SLOTS > 0: LDS hash of Adj+(q) with 2^LOG_SLOTS slots at most.
@@ -369,8 +374,11 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     uint32_t n_stash = 0;  // keys in the stash
     bool gmode = LOG_SLOTS == 0;  // search Adj+(q) in HBM (huge targets, or a failed table)
 
-    // reduce the hits queued in this wave's ring, one per lane
-    auto drain = [&](uint32_t count) {
+    // reduce the hits queued in this wave's ring, one per lane; `gm` says
+    // where Adj+^m(q) is (true: HBM) at compile time, so that the table path
+    // holds no global load
+    auto drain = [&](uint32_t count, auto gm) {
+        constexpr bool G = decltype(gm)::value;
         uint32_t tri = 0, spread = 0;
         Hit h{0, 0, 0, 0, 0, 0};
         const bool valid = lane < count;
@@ -381,7 +389,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
             h.l_p = e.x >> 22;
             h.l_q = l_q;
             h.t_pr = e.y;
-            if (!gmode) {
+            if constexpr (!G) {
                 h.t_qr = hts[where];
                 h.l_r = hlab[where];
             } else {
@@ -389,7 +397,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 h.l_r = P.tlab[kq + where];
             }
             if (ENUM) {
-                const uint32_t r = !gmode ? hkey[where] : P.col[kq + where];
+                const uint32_t r = !G ? hkey[where] : P.col[kq + where];
                 const unsigned long long at = atomicAdd(P.enum_count, 1ull);
                 if (at < P.enum_cap) {
                     uint32_t *o = P.enum_out + at * 9;
@@ -412,6 +420,11 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
         my_tri += tri;
         my_spread += spread;
         qh += count;
+    };
+    auto drain_queued = [&]() {
+        if (qt == qh) return;
+        if (gmode) drain(qt - qh, std::true_type{});
+        else drain(qt - qh, std::false_type{});
     };
 
     for (;;) {
@@ -437,9 +450,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
             if (d.q != cur_q) {
                 // a new target: reduce the hits still queued against the old
                 // table, then rebuild it once every wave is done with it
-                if (META || ENUM) {
-                    if (qt != qh) drain(qt - qh);
-                }
+                if (META || ENUM) drain_queued();
                 if (P.rank_gid) {
                     const uint32_t g = sload(P.rank_gid + d.q);
                     if (g != cur_g) {
@@ -507,187 +518,207 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 gsync();
             }
 
-            // ---- this wave's records: tile records w, w + kW, w + 2kW, ...
+            // ---- this wave's records: tile records w, w + kW, w + 2kW, ...,
+            // walked with the search mode fixed at compile time (see drain).
             // The wave loads them 64 at a time into VGPRs (lane i holds its
             // i-th record) and reads the current one with readlane, so the
             // walk itself issues no memory access.
-            const uint32_t ncnt = d.cnt;
-            const uint32_t nw = ncnt > (uint32_t)wl ? (ncnt - (uint32_t)wl + kW - 1) / kW : 0u;
-            if (nw == 0) continue;
-            const uint64_t kmask = (1ull << P.kbits) - 1;
-            // lane l of block b holds this wave's in-edge 64b + l (tile record w + (64b + l) kW)
-            auto load_block = [&](uint32_t blk) -> RecBlock {
-                const uint32_t i = blk * kWave + lane;
-                RecBlock r{0, 0, 0, 0, 0, 0};
-                if (i < nw) {
+            auto walk = [&](auto gm) {
+                constexpr bool G = decltype(gm)::value;
+                const uint32_t ncnt = d.cnt;
+                const uint32_t nw = ncnt > (uint32_t)wl ? (ncnt - (uint32_t)wl + kW - 1) / kW : 0u;
+                if (nw == 0) return;
+                const uint64_t kmask = (1ull << P.kbits) - 1;
+                // lane l of block b holds this wave's in-edge 64b + l (tile record w + (64b + l) kW)
+                // A block is loaded in two stages a block apart, so that no
+                // load waits on a load issued just before it (loads retire in
+                // order: such a wait would drain the candidate loads in
+                // flight): the in-edge keys of block b + 2, then the gathers
+                // (row end, time(p, q), label(p)) of block b + 1 from keys
+                // that arrived long ago.  Lanes past the wave's last record
+                // load the tile's first record; they are never read.
+                struct KeyBlock {
+                    uint64_t key;
+                    uint32_t p;
+                };
+                auto load_keys = [&](uint32_t blk) -> KeyBlock {
+                    const uint32_t i = min(blk * kWave + lane, nw - 1);
                     const uint64_t e = d.e0 + ((uint64_t)(uint32_t)wl + (uint64_t)i * kW) * d.stride;
-                    const uint64_t k = P.inkey[e] & kmask;
-                    const uint32_t p = P.inp[e];
+                    return KeyBlock{P.inkey[e], P.inp[e]};
+                };
+                auto gather = [&](const KeyBlock &kb) -> RecBlock {
+                    const uint64_t k = kb.key & kmask;
                     const uint64_t st = k + 1;
+                    RecBlock r;
                     r.start_lo = (uint32_t)st;
                     r.start_hi = (uint32_t)(st >> 32);
-                    r.len = (uint32_t)(P.rowptr[p + 1] - st);
+                    r.rend = P.rowptr[kb.p + 1];
                     r.t_pq = (META || ENUM) ? P.ets[k] : 0u;
-                    r.l_p = (META || ENUM) ? P.rlab[p] : 0u;
-                    r.p = p;
-                }
-                return r;
-            };
-            RecBlock blk_cur = load_block(0);
-            RecBlock blk_nxt = nw > kWave ? load_block(1) : RecBlock{0, 0, 0, 0, 0, 0};
-            struct WaveRec {
-                uint64_t start;
-                uint32_t len, t_pq, l_p, p;
-            };
-            auto read_rec = [&](uint32_t i) -> WaveRec {
-                const uint32_t l = i & (kWave - 1);
-                WaveRec r;
-                r.start = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(blk_cur.start_lo, l) |
-                          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(blk_cur.start_hi, l) << 32);
-                r.len = __builtin_amdgcn_readlane(blk_cur.len, l);
-                r.t_pq = (META || ENUM) ? __builtin_amdgcn_readlane(blk_cur.t_pq, l) : 0;
-                r.l_p = (META || ENUM) ? __builtin_amdgcn_readlane(blk_cur.l_p, l) : 0;
-                r.p = ENUM ? __builtin_amdgcn_readlane(blk_cur.p, l) : 0;
-                return r;
-            };
-            uint32_t i = 0;   // current record (wave-local index)
-            WaveRec rec = read_rec(0);
-            uint32_t off = 0; // next slot of the current record
-            uint32_t wave_work = 0, wave_hits = 0;
+                    r.l_p = (META || ENUM) ? (uint32_t)P.rlab[kb.p] : 0u;
+                    r.p = kb.p;
+                    return r;
+                };
+                RecBlock blk_cur = gather(load_keys(0));
+                RecBlock blk_nxt = gather(load_keys(1));
+                KeyBlock key_nxt = load_keys(2);
+                struct WaveRec {
+                    uint64_t start;
+                    uint32_t len, t_pq, l_p, p;
+                };
+                auto read_rec = [&](uint32_t i) -> WaveRec {
+                    const uint32_t l = i & (kWave - 1);
+                    WaveRec r;
+                    r.start = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(blk_cur.start_lo, l) |
+                              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(blk_cur.start_hi, l) << 32);
+                    const uint64_t rend = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)blk_cur.rend, l) |
+                                          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(blk_cur.rend >> 32), l)
+                                           << 32);
+                    r.len = (uint32_t)(rend - r.start);
+                    r.t_pq = (META || ENUM) ? __builtin_amdgcn_readlane(blk_cur.t_pq, l) : 0;
+                    r.l_p = (META || ENUM) ? __builtin_amdgcn_readlane(blk_cur.l_p, l) : 0;
+                    r.p = ENUM ? __builtin_amdgcn_readlane(blk_cur.p, l) : 0;
+                    return r;
+                };
+                uint32_t i = 0;   // current record (wave-local index)
+                WaveRec rec = read_rec(0);
+                uint32_t off = 0; // next slot of the current record
+                uint32_t wave_work = 0, wave_hits = 0;
 
-            // next chunk of up to kChunkCand candidates of the current
-            // record: its size and the record's metadata; returns the
-            // chunk's first slot
-            struct Chunk {
-                uint32_t n, t_pq, l_p, p;
-            };
-            auto next_chunk = [&](Chunk &ch) -> uint64_t {
-                uint64_t base = 0;
-                if (i < nw) {
-                    base = rec.start + off;
-                    ch.n = min(rec.len - off, kChunkCand);
-                    ch.t_pq = rec.t_pq;
-                    ch.l_p = rec.l_p;
-                    ch.p = rec.p;
-                    wave_work += ch.n;
-                    off += kChunkCand;
-                    if (off >= rec.len) {
-                        off = 0;
-                        ++i;
-                        if (i < nw) {
-                            if ((i & (kWave - 1)) == 0) {
-                                blk_cur = blk_nxt;
-                                blk_nxt = (i + kWave < nw) ? load_block(i / kWave + 1) : RecBlock{0, 0, 0, 0, 0, 0};
+                // next chunk of up to kChunkCand candidates of the current
+                // record: its size and the record's metadata; returns the
+                // chunk's first slot
+                struct Chunk {
+                    uint32_t n, t_pq, l_p, p;
+                };
+                auto next_chunk = [&](Chunk &ch) -> uint64_t {
+                    uint64_t base = 0;
+                    if (i < nw) {
+                        base = rec.start + off;
+                        ch.n = min(rec.len - off, kChunkCand);
+                        ch.t_pq = rec.t_pq;
+                        ch.l_p = rec.l_p;
+                        ch.p = rec.p;
+                        wave_work += ch.n;
+                        off += kChunkCand;
+                        if (off >= rec.len) {
+                            off = 0;
+                            ++i;
+                            if (i < nw) {
+                                if ((i & (kWave - 1)) == 0) {
+                                    blk_cur = blk_nxt;
+                                    blk_nxt = gather(key_nxt);
+                                    key_nxt = load_keys(i / kWave + 2);
+                                }
+                                rec = read_rec(i);
                             }
-                            rec = read_rec(i);
+                        }
+                    } else {
+                        ch.n = 0;
+                        ch.t_pq = 0;
+                        ch.l_p = 0;
+                        ch.p = 0;
+                    }
+                    return base;
+                };
+                // issue the loads of kBatch chunks: lane l of sub-row s reads
+                // candidate 64 s + l; the buffer resource spans exactly the
+                // chunk, so lanes past its end read 0 without touching memory
+                auto prepare = [&](Chunk(&chs)[kBatch], uint32_t(&cand)[kBatch][kSub], uint32_t(&tpr)[kBatch][kSub]) {
+    #pragma unroll
+                    for (int c = 0; c < kBatch; ++c) {
+                        const uint64_t base = next_chunk(chs[c]);
+                        const uint32_t bytes = chs[c].n * 4u;
+                        const auto rc = __builtin_amdgcn_make_buffer_rsrc((void *)(P.col + base), (short)0, bytes, kRsrcWord3);
+    #pragma unroll
+                        for (int sr = 0; sr < kSub; ++sr)
+                            cand[c][sr] = __builtin_amdgcn_raw_buffer_load_b32(rc, lane * 4u + sr * 256u, 0, 0);
+                        if (META || ENUM) {
+                            const auto rt =
+                                __builtin_amdgcn_make_buffer_rsrc((void *)(P.ets + base), (short)0, bytes, kRsrcWord3);
+    #pragma unroll
+                            for (int sr = 0; sr < kSub; ++sr)
+                                tpr[c][sr] = __builtin_amdgcn_raw_buffer_load_b32(rt, lane * 4u + sr * 256u, 0, 0);
                         }
                     }
-                } else {
-                    ch.n = 0;
-                    ch.t_pq = 0;
-                    ch.l_p = 0;
-                    ch.p = 0;
-                }
-                return base;
-            };
-            // issue the loads of kBatch chunks: lane l of sub-row s reads
-            // candidate 64 s + l; the buffer resource spans exactly the
-            // chunk, so lanes past its end read 0 without touching memory
-            auto prepare = [&](Chunk(&chs)[kBatch], uint32_t(&cand)[kBatch][kSub], uint32_t(&tpr)[kBatch][kSub]) {
-#pragma unroll
-                for (int c = 0; c < kBatch; ++c) {
-                    const uint64_t base = next_chunk(chs[c]);
-                    const uint32_t bytes = chs[c].n * 4u;
-                    const auto rc = __builtin_amdgcn_make_buffer_rsrc((void *)(P.col + base), (short)0, bytes, kRsrcWord3);
-#pragma unroll
-                    for (int sr = 0; sr < kSub; ++sr)
-                        cand[c][sr] = __builtin_amdgcn_raw_buffer_load_b32(rc, lane * 4u + sr * 256u, 0, 0);
-                    if (META || ENUM) {
-                        const auto rt =
-                            __builtin_amdgcn_make_buffer_rsrc((void *)(P.ets + base), (short)0, bytes, kRsrcWord3);
-#pragma unroll
-                        for (int sr = 0; sr < kSub; ++sr)
-                            tpr[c][sr] = __builtin_amdgcn_raw_buffer_load_b32(rt, lane * 4u + sr * 256u, 0, 0);
-                    }
-                }
-            };
-            auto process = [&](const Chunk(&chs)[kBatch], const uint32_t(&cand)[kBatch][kSub],
-                               const uint32_t(&tpr)[kBatch][kSub]) {
-#pragma unroll
-                for (int c = 0; c < kBatch; ++c) {
-#pragma unroll
-                    for (int sr = 0; sr < kSub; ++sr) {
-                        if (chs[c].n <= (uint32_t)(sr * kWave)) break;
-                        const uint32_t nsub = min(chs[c].n - sr * kWave, (uint32_t)kWave);
-                        // lanes >= nsub hold no candidate (they read 0): mask their hits
-                        const uint64_t live = nsub >= (uint32_t)kWave ? ~0ull : ((1ull << nsub) - 1);
-                        const uint32_t r = cand[c][sr];
-                        bool hit;
-                        uint32_t slot;
-                        if (!gmode) {
-                            // two independent reads, no loop
-                            const uint32_t h0 = hash0(r, log_s), h1 = (1u << log_s) + hash1(r, log_s);
-                            const uint32_t k0 = hkey[h0], k1 = hkey[h1];
-                            hit = k0 == r || k1 == r;
-                            slot = k0 == r ? h0 : h1;
-                            if (n_stash) {
-                                const uint32_t st = 2u << log_s;
-                                for (uint32_t x = 0; x < n_stash; ++x) {
-                                    if (hkey[st + x] == r) {
-                                        hit = true;
-                                        slot = st + x;
+                };
+                auto process = [&](const Chunk(&chs)[kBatch], const uint32_t(&cand)[kBatch][kSub],
+                                   const uint32_t(&tpr)[kBatch][kSub]) {
+    #pragma unroll
+                    for (int c = 0; c < kBatch; ++c) {
+    #pragma unroll
+                        for (int sr = 0; sr < kSub; ++sr) {
+                            if (chs[c].n <= (uint32_t)(sr * kWave)) break;
+                            const uint32_t nsub = min(chs[c].n - sr * kWave, (uint32_t)kWave);
+                            // lanes >= nsub hold no candidate (they read 0): mask their hits
+                            const uint64_t live = nsub >= (uint32_t)kWave ? ~0ull : ((1ull << nsub) - 1);
+                            const uint32_t r = cand[c][sr];
+                            bool hit;
+                            uint32_t slot;
+                            if constexpr (!G) {
+                                // two independent reads, no loop
+                                const uint32_t h0 = hash0(r, log_s), h1 = (1u << log_s) + hash1(r, log_s);
+                                const uint32_t k0 = hkey[h0], k1 = hkey[h1];
+                                hit = k0 == r || k1 == r;
+                                slot = k0 == r ? h0 : h1;
+                                if (n_stash) {
+                                    const uint32_t st = 2u << log_s;
+                                    for (uint32_t x = 0; x < n_stash; ++x) {
+                                        if (hkey[st + x] == r) {
+                                            hit = true;
+                                            slot = st + x;
+                                        }
                                     }
                                 }
+                            } else {
+                                hit = false;
+                                slot = 0;
+                                if (lane < nsub) {
+                                    const int64_t at = global_find(P.col, kq, dq, r);
+                                    hit = at >= 0;
+                                    slot = (uint32_t)(at - (int64_t)kq);
+                                }
                             }
-                        } else {
-                            hit = false;
-                            slot = 0;
-                            if (lane < nsub) {
-                                const int64_t at = global_find(P.col, kq, dq, r);
-                                hit = at >= 0;
-                                slot = (uint32_t)(at - (int64_t)kq);
+                            const uint64_t m = __ballot(hit) & live;
+                            if (!META && !ENUM) {
+                                wave_hits += (uint32_t)__popcll(m);
+                                continue;
                             }
-                        }
-                        const uint64_t m = __ballot(hit) & live;
-                        if (!META && !ENUM) {
-                            wave_hits += (uint32_t)__popcll(m);
-                            continue;
-                        }
-                        if (m) {
-                            if ((m >> lane) & 1ull) {
-                                const uint32_t pos = qt + (uint32_t)__popcll(m & lt_mask);
-                                ring[pos & (kRing - 1)] =
-                                    make_uint4(slot | (chs[c].l_p << 22), tpr[c][sr], chs[c].t_pq, chs[c].p);
+                            if (m) {
+                                if ((m >> lane) & 1ull) {
+                                    const uint32_t pos = qt + (uint32_t)__popcll(m & lt_mask);
+                                    ring[pos & (kRing - 1)] =
+                                        make_uint4(slot | (chs[c].l_p << 22), tpr[c][sr], chs[c].t_pq, chs[c].p);
+                                }
+                                qt += (uint32_t)__popcll(m);
+                                if (qt - qh >= (uint32_t)kWave) drain(kWave, gm);
                             }
-                            qt += (uint32_t)__popcll(m);
-                            if (qt - qh >= (uint32_t)kWave) drain(kWave);
                         }
                     }
+                };
+                // two batches in flight: the next batch's loads are issued before
+                // the current batch is probed
+                Chunk rA[kBatch], rB[kBatch];
+                uint32_t cA[kBatch][kSub], tA[kBatch][kSub], cB[kBatch][kSub], tB[kBatch][kSub];
+                prepare(rA, cA, tA);
+                for (;;) {
+                    prepare(rB, cB, tB);
+                    process(rA, cA, tA);
+                    if (rB[0].n == 0) break;
+                    prepare(rA, cA, tA);
+                    process(rB, cB, tB);
+                    if (rA[0].n == 0) break;
+                }
+                if (lane == 0) {
+                    probes += wave_work;
+                    my_tri += wave_hits;
                 }
             };
-            // two batches in flight: the next batch's loads are issued before
-            // the current batch is probed
-            Chunk rA[kBatch], rB[kBatch];
-            uint32_t cA[kBatch][kSub], tA[kBatch][kSub], cB[kBatch][kSub], tB[kBatch][kSub];
-            prepare(rA, cA, tA);
-            for (;;) {
-                prepare(rB, cB, tB);
-                process(rA, cA, tA);
-                if (rB[0].n == 0) break;
-                prepare(rA, cA, tA);
-                process(rB, cB, tB);
-                if (rA[0].n == 0) break;
-            }
-            if (lane == 0) {
-                probes += wave_work;
-                my_tri += wave_hits;
-            }
+            if (gmode) walk(std::true_type{});
+            else walk(std::false_type{});
         }
     }
 
-    if (META || ENUM) {
-        if (qt != qh) drain(qt - qh);
-    }
+    if (META || ENUM) drain_queued();
     // ---- merge this workgroup's counters into the result
     flush(cur_g);
 }
