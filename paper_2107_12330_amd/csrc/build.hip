@@ -302,15 +302,20 @@ __device__ __forceinline__ uint32_t rest_len(const uint64_t *rowptr, uint32_t s,
 
 // Key of each oriented edge for the in-edge sort: (q << kbits) | k, with q
 // replaced by n (sorted past every target) when the edge has no wedge to
-// check.  Counts the edges kept.
-__global__ void k_in_keys(const uint32_t *srow, const uint32_t *col, const uint64_t *rowptr, size_t m, int kbits,
-                          uint32_t n, uint64_t *key, unsigned long long *kept)
+// check; and the record payload that travels with it through the sort: the
+// length of the rest of p's row after slot k (< 2^22) | label(p) << 24.
+// Counts the edges kept.  Slots are in row order, so every read here walks
+// memory forwards.
+__global__ void k_in_keys(const uint32_t *srow, const uint32_t *col, const uint64_t *rowptr, const uint8_t *rlab,
+                          size_t m, int kbits, uint32_t n, uint64_t *key, uint32_t *pay, unsigned long long *kept)
 {
     unsigned long long c = 0;
     for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < m; k += (size_t)gridDim.x * blockDim.x) {
         const uint32_t s = srow[k], t = col[k];
-        const bool ok = rest_len(rowptr, s, k) > 0 && rowptr[t + 1] > rowptr[t];
+        const uint32_t rest = rest_len(rowptr, s, k);
+        const bool ok = rest > 0 && rowptr[t + 1] > rowptr[t];
         key[k] = ((uint64_t)(ok ? t : n) << kbits) | k;
+        pay[k] = rest | ((uint32_t)rlab[s] << 24);
         c += ok ? 1 : 0;
     }
     c = wave_sum(c);
@@ -320,10 +325,9 @@ __global__ void k_in_keys(const uint32_t *srow, const uint32_t *col, const uint6
 // In-edges and wedge checks of every target (the sum of the remaining row
 // lengths of its in-edges).  In-edges of one target are consecutive, so each
 // wave adds one partial sum per run of equal targets.
-__global__ void k_in_work(const uint64_t *key, const uint32_t *piv, uint64_t n_in, int kbits,
-                          const uint64_t *rowptr, unsigned long long *work, uint32_t *count)
+__global__ void k_in_work(const uint64_t *key, const uint32_t *pay, uint64_t n_in, int kbits,
+                          unsigned long long *work, uint32_t *count)
 {
-    const uint64_t kmask = (1ull << kbits) - 1;
     const unsigned lane = lane_id();
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t base = blockIdx.x * (size_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < n_in; base += stride) {
@@ -331,9 +335,8 @@ __global__ void k_in_work(const uint64_t *key, const uint32_t *piv, uint64_t n_i
         const bool ok = i < n_in;
         uint64_t t = ~0ull, len = 0;
         if (ok) {
-            const uint64_t kk = key[i];
-            t = kk >> kbits;
-            len = rowptr[piv[i] + 1] - (kk & kmask) - 1;
+            t = key[i] >> kbits;
+            len = pay[i] & 0xffffffu;
         }
         const uint64_t tprev = __shfl_up(t, 1, kWave);
         const bool head = ok && (lane == 0 || tprev != t);
@@ -487,7 +490,7 @@ const T *to_device(const T *p, size_t n, uint32_t space, DArray<T> &hold, hipStr
 uint64_t graph_bytes(const tp_graph *g)
 {
     uint64_t b = g->rowptr.bytes() + g->col.bytes() + g->ets.bytes() + g->tlab.bytes() + g->rlab.bytes() +
-                 g->perm.bytes() + g->inkey.bytes() + g->inp.bytes() + g->rank_gid.bytes();
+                 g->perm.bytes() + g->inkey.bytes() + g->inpay.bytes() + g->rank_gid.bytes();
     for (int c = 0; c < kNumClasses; ++c) b += g->tiles[c].bytes();
     return b;
 }
@@ -505,8 +508,8 @@ void plan_graph(tp_graph *g, const PlanCfg &cfg, hipStream_t s)
         TP_HIP(hipMemsetAsync(incnt.get(), 0, n * sizeof(uint32_t), s));
         TP_HIP(hipMemsetAsync(work.get(), 0, n * sizeof(unsigned long long), s));
         if (g->n_in) {
-            k_in_work<<<grid_for(g->n_in, kB), kB, 0, s>>>(g->inkey.get(), g->inp.get(), g->n_in, (int)g->kbits,
-                                                           g->rowptr.get(), work.get(), incnt.get());
+            k_in_work<<<grid_for(g->n_in, kB), kB, 0, s>>>(g->inkey.get(), g->inpay.get(), g->n_in, (int)g->kbits,
+                                                           work.get(), incnt.get());
             TP_CHECK_LAUNCH();
         }
         scan_u32_to_u64(incnt.get(), cptr.get(), n, s);
@@ -758,12 +761,14 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
         if (kbits + nb + 1 > 64) fail(TP_ERR_UNSUPPORTED, "tripoll_build: graph too large for the in-edge keys");
         g->kbits = (uint32_t)kbits;
         uint64_t *ikey = keyA.get(), *ikey_alt = keyB.get();
-        uint32_t *ival = srow, *ival_alt = (srow == valA.get()) ? valB.get() : valA.get();
+        // the payloads go to the buffer that held the sorted times (copied
+        // into ets); srow's buffer is free once the keys are written
+        uint32_t *ival = (srow == valA.get()) ? valB.get() : valA.get(), *ival_alt = srow;
         DArray<unsigned long long> kept(1, s);
         TP_HIP(hipMemsetAsync(kept.get(), 0, sizeof(unsigned long long), s));
         if (m) {
-            k_in_keys<<<grid_for(m, kB), kB, 0, s>>>(srow, g->col.get(), g->rowptr.get(), m, kbits, n, ikey,
-                                                     kept.get());
+            k_in_keys<<<grid_for(m, kB), kB, 0, s>>>(srow, g->col.get(), g->rowptr.get(), g->rlab.get(), m, kbits,
+                                                     n, ikey, ival, kept.get());
             TP_CHECK_LAUNCH();
         }
         g->n_in = read_scalar(kept.get(), s);
@@ -776,7 +781,7 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
         DArray<uint64_t> &kk = (ikey == keyA.get()) ? keyA : keyB;
         DArray<uint32_t> &vv = (ival == valA.get()) ? valA : valB;
         g->inkey = std::move(kk);
-        g->inp = std::move(vv);
+        g->inpay = std::move(vv);
     }
     keyA.release();
     keyB.release();

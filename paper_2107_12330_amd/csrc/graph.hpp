@@ -17,7 +17,8 @@ struct TileDesc {
 // In-edge index: one entry per oriented edge p -> q whose remaining row is
 // non-empty, sorted by q.  The key holds q above bit `kbits` and the CSR
 // slot k of the edge in p's row below it; the wedges (p, q, r) to check are
-// the slots after k in p's row.  A second array holds p.
+// the slots after k in p's row.  A second array holds their number and
+// label(p), so that the only gather of a record is the time of p -> q.
 // Target classes of the survey plan, by d+(q).
 enum { kClassTiny = 0, kClassSmall = 1, kClassLarge = 2, kClassHuge = 3, kNumClasses = TP_NUM_CLASSES };
 
@@ -42,7 +43,7 @@ struct tp_graph {
     tp::DArray<uint32_t> perm;    // [n] rank -> original id
     uint32_t kbits = 1;           // bits of a CSR slot in an in-edge key
     tp::DArray<uint64_t> inkey;   // [n_in] (q << kbits) | k, sorted by q
-    tp::DArray<uint32_t> inp;     // [n_in] pivot p of each in-edge
+    tp::DArray<uint32_t> inpay;   // [n_in] rest of p's row after slot k | label(p) << 24
     tp::DArray<TileDesc> tiles[kNumClasses];
     uint32_t n_graphs = 0;         // > 0 for a batch of disjoint graphs
     tp::DArray<uint32_t> rank_gid; // [n] graph of each rank (batches only)

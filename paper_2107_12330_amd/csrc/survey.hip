@@ -40,9 +40,15 @@ namespace {
 
 constexpr int kSmallBlock = 256;   // 4 waves share a small target's tables
 constexpr int kLargeBlock = 1024;  // 16 waves share a large target's tables
-constexpr int kSub = 4;            // sub-rows of 64 candidates per chunk
-constexpr uint32_t kChunkCand = kSub * 64;  // candidates per chunk of a record
-constexpr int kBatch = 2;          // chunks per batch; two batches in flight
+// Candidate loads in flight per wave: a chunk is kSub sub-rows of 64
+// candidates of one record, a batch is kBatch chunks, and two batches are in
+// flight.  The per-wave form serves short rows (tiny targets, small graphs):
+// shorter chunks, more of them.
+template <bool WAVE> struct Depth {
+    static constexpr int kSub = WAVE ? 2 : 4;
+    static constexpr int kBatch = WAVE ? 2 : 1;
+    static constexpr uint32_t kChunkCand = kSub * 64;
+};
 constexpr uint32_t kRing = 128;    // per-wave ring of queued hits: slot|label(p), time(p,r), time(p,q), p
 constexpr uint64_t kChunk = 4;     // tiles claimed at a time by a workgroup
 constexpr int kRsrcWord3 = 0x00020000;  // buffer resource word 3 for raw 32-bit loads on CDNA
@@ -64,7 +70,7 @@ struct SurveyParams {
     const uint8_t *tlab;
     const uint8_t *rlab;
     const uint64_t *inkey;    // sorted in-edge keys (q << kbits) | k
-    const uint32_t *inp;      // pivot of each in-edge
+    const uint32_t *inpay;    // rest of the pivot's row | label(pivot) << 24
     uint32_t kbits;
     const TileDesc *tiles;
     uint64_t n_tiles;
@@ -255,9 +261,9 @@ __device__ __forceinline__ T sload(const T *p)
 // Loaded values are kept as loaded (no arithmetic on them until they are
 // read), so that no instruction waits for a load right after issuing it.
 struct RecBlock {
-    uint32_t start_lo, start_hi;  // first candidate slot
-    uint64_t rend;                // end of the pivot's row
-    uint32_t t_pq, l_p, p;
+    uint64_t key;   // (q << kbits) | k
+    uint32_t pay;   // rest of p's row | label(p) << 24
+    uint32_t t_pq;  // time(p, q)
 };
 
 // LOG_SLOTS > 0: LDS hash of Adj+(q) with 2^LOG_SLOTS slots at most.
@@ -274,6 +280,9 @@ struct RecBlock {
 template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI>
 __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
 {
+    constexpr int kSub = Depth<WAVE>::kSub;
+    constexpr int kBatch = Depth<WAVE>::kBatch;
+    constexpr uint32_t kChunkCand = Depth<WAVE>::kChunkCand;
     constexpr int kWaves = BLOCK / kWave;       // waves per workgroup
     constexpr int kW = WAVE ? 1 : kWaves;       // waves sharing one table
     constexpr int kGroup = WAVE ? kWave : BLOCK;  // threads sharing one table
@@ -533,29 +542,24 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 // A block is loaded in two stages a block apart, so that no
                 // load waits on a load issued just before it (loads retire in
                 // order: such a wait would drain the candidate loads in
-                // flight): the in-edge keys of block b + 2, then the gathers
-                // (row end, time(p, q), label(p)) of block b + 1 from keys
-                // that arrived long ago.  Lanes past the wave's last record
-                // load the tile's first record; they are never read.
+                // flight): the records of block b + 2, then the gather of
+                // time(p, q) for block b + 1 from keys that arrived long ago.
+                // Lanes past the wave's last record load the tile's first
+                // record; they are never read.
                 struct KeyBlock {
                     uint64_t key;
-                    uint32_t p;
+                    uint32_t pay;
                 };
                 auto load_keys = [&](uint32_t blk) -> KeyBlock {
                     const uint32_t i = min(blk * kWave + lane, nw - 1);
                     const uint64_t e = d.e0 + ((uint64_t)(uint32_t)wl + (uint64_t)i * kW) * d.stride;
-                    return KeyBlock{P.inkey[e], P.inp[e]};
+                    return KeyBlock{P.inkey[e], P.inpay[e]};
                 };
                 auto gather = [&](const KeyBlock &kb) -> RecBlock {
-                    const uint64_t k = kb.key & kmask;
-                    const uint64_t st = k + 1;
                     RecBlock r;
-                    r.start_lo = (uint32_t)st;
-                    r.start_hi = (uint32_t)(st >> 32);
-                    r.rend = P.rowptr[kb.p + 1];
-                    r.t_pq = (META || ENUM) ? P.ets[k] : 0u;
-                    r.l_p = (META || ENUM) ? (uint32_t)P.rlab[kb.p] : 0u;
-                    r.p = kb.p;
+                    r.key = kb.key;
+                    r.pay = kb.pay;
+                    r.t_pq = (META || ENUM) ? P.ets[kb.key & kmask] : 0u;
                     return r;
                 };
                 RecBlock blk_cur = gather(load_keys(0));
@@ -568,15 +572,25 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 auto read_rec = [&](uint32_t i) -> WaveRec {
                     const uint32_t l = i & (kWave - 1);
                     WaveRec r;
-                    r.start = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(blk_cur.start_lo, l) |
-                              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(blk_cur.start_hi, l) << 32);
-                    const uint64_t rend = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)blk_cur.rend, l) |
-                                          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(blk_cur.rend >> 32), l)
-                                           << 32);
-                    r.len = (uint32_t)(rend - r.start);
+                    const uint64_t key = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)blk_cur.key, l) |
+                                         ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(blk_cur.key >> 32), l)
+                                          << 32);
+                    const uint32_t pay = __builtin_amdgcn_readlane(blk_cur.pay, l);
+                    r.start = (key & kmask) + 1;
+                    r.len = pay & 0xffffffu;
                     r.t_pq = (META || ENUM) ? __builtin_amdgcn_readlane(blk_cur.t_pq, l) : 0;
-                    r.l_p = (META || ENUM) ? __builtin_amdgcn_readlane(blk_cur.l_p, l) : 0;
-                    r.p = ENUM ? __builtin_amdgcn_readlane(blk_cur.p, l) : 0;
+                    r.l_p = (META || ENUM) ? pay >> 24 : 0;
+                    r.p = 0;
+                    if (ENUM) {
+                        // the pivot owns the row that holds slot start - 1
+                        uint32_t a = 0, b = P.n;  // rowptr[a] <= start - 1 < rowptr[b]
+                        while (b - a > 1) {
+                            const uint32_t mid = (a + b) >> 1;
+                            if (sload(P.rowptr + mid) <= r.start - 1) a = mid;
+                            else b = mid;
+                        }
+                        r.p = a;
+                    }
                     return r;
                 };
                 uint32_t i = 0;   // current record (wave-local index)
@@ -848,7 +862,7 @@ SurveyParams make_params(const tp_graph *g, const tp_survey_spec *sp, unsigned l
     P.tlab = g->tlab.get();
     P.rlab = g->rlab.get();
     P.inkey = g->inkey.get();
-    P.inp = g->inp.get();
+    P.inpay = g->inpay.get();
     P.kbits = g->kbits;
     P.tile_counter = counter;
     P.out = out;
