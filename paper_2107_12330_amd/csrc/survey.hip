@@ -55,12 +55,17 @@ constexpr int kRsrcWord3 = 0x00020000;  // buffer resource word 3 for raw 32-bit
 constexpr uint32_t kEmpty = 0xffffffffu;
 constexpr uint32_t kMaxKicks = 64;  // cuckoo displacements before a key goes to the stash
 
-// The two cuckoo hash functions (multiplicative, with a pre-mix for the
-// second so the two are unrelated), each onto 2^log_s slots.
-__device__ __forceinline__ uint32_t hash0(uint32_t r, uint32_t log_s) { return (r * 0x9e3779b1u) >> (32 - log_s); }
+// The two cuckoo hash functions, each onto 2^log_s slots: the low bits of
+// the rank, and a multiplicative hash of the rank folded to 24 bits (a
+// full-rate 24-bit multiply; a 32-bit multiply issues at a quarter of the
+// rate).  Ranks are dense, so the low bits spread the out-neighbours of a
+// target well; keys that collide in both tables go to the stash, and a
+// target whose stash overflows is searched in HBM, so the hash quality
+// affects only speed.
+__device__ __forceinline__ uint32_t hash0(uint32_t r, uint32_t log_s) { return r & ((1u << log_s) - 1u); }
 __device__ __forceinline__ uint32_t hash1(uint32_t r, uint32_t log_s)
 {
-    return ((r ^ (r >> 16)) * 0x85ebca6bu) >> (32 - log_s);
+    return (uint32_t)__umul24(r ^ (r >> 12), 0x9e3779u) >> (32 - log_s);
 }
 
 struct SurveyParams {
@@ -428,7 +433,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
         if (MULTI) reduce_multi(h, valid, cnt, slot_lds, P.n_slots, P.slot_words, lut, P.lut_shift, P.slot_labels);
         my_tri += tri;
         my_spread += spread;
-        qh += count;
+        qh = __builtin_amdgcn_readfirstlane(qh + count);
     };
     auto drain_queued = [&]() {
         if (qt == qh) return;
@@ -699,11 +704,14 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                             }
                             if (m) {
                                 if ((m >> lane) & 1ull) {
-                                    const uint32_t pos = qt + (uint32_t)__popcll(m & lt_mask);
-                                    ring[pos & (kRing - 1)] =
+                                    // position among the wave's hits: hits in the lanes below
+                                    const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                                        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                                    ring[(qt + below) & (kRing - 1)] =
                                         make_uint4(slot | (chs[c].l_p << 22), tpr[c][sr], chs[c].t_pq, chs[c].p);
                                 }
-                                qt += (uint32_t)__popcll(m);
+                                // the ring cursors are wave-uniform: keep them in scalar registers
+                                qt = __builtin_amdgcn_readfirstlane(qt + (uint32_t)__popcll(m));
                                 if (qt - qh >= (uint32_t)kWave) drain(kWave, gm);
                             }
                         }
