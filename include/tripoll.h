@@ -401,9 +401,10 @@ typedef struct {
 
 /*
  * Autotune the plan for one survey kind: for every class, time each usable
- * variant at tile caps 256, 1024 and 4096 with the survey `spec` on this
- * graph, and keep the fastest per class (the default stays unless another
- * beats it by more than 3%).  Runs real surveys (cost: a few times one
+ * variant at tile caps 256, 1024, 4096 and 16384 with the survey `spec` on
+ * this graph, and keep the fastest per class (the default -- the class's own
+ * variant, 1024 records per tile, 16384 for the large class -- stays unless
+ * another beats it by more than 3%).  Runs real surveys (cost: a few times one
  * survey).  Synchronous; sets the plan on the graph.  Not to be called while
  * surveys of the graph are in flight.
  */

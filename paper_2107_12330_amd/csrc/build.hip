@@ -791,7 +791,7 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
 
     // ---- phase 7: work per target and the tile plan per class
     PlanCfg cfg{};
-    for (int c = 0; c < kNumClasses; ++c) cfg.tile_records[c] = kTileRecords;
+    for (int c = 0; c < kNumClasses; ++c) cfg.tile_records[c] = default_tile_records(c);
     plan_graph(g.get(), cfg, s);
     TP_HIP(hipEventRecord(ev[8], s));
     TP_HIP(hipStreamSynchronize(s));

@@ -19,11 +19,13 @@ constexpr int kSmallLogSlots = 10;
 constexpr int kLargeLogSlots = 12;
 constexpr uint32_t kStash = 32;          // keys the cuckoo insertion could not place
 
-// By default a tile holds at most kTileRecords in-edge records of one target
-// and about kTileWorkPerRecord * kTileRecords wedge checks; the tuner may
-// choose another record cap per class.
+// A tile holds at most `cap` in-edge records of one target and about
+// kTileWorkPerRecord * cap wedge checks.  Default caps per target class:
+// 1024 records, and 16384 for the large class, whose workgroups stall for
+// the first records of every tile; the tuner may choose others.
 constexpr uint32_t kTileRecords = 1024;
 constexpr uint64_t kTileWorkPerRecord = 256;
+inline uint32_t default_tile_records(int cls) { return cls == 2 ? 16384u : kTileRecords; }
 
 // Slots of padding after the last oriented edge in the target and time
 // arrays, so that a wave may load 64 consecutive slots from any row start.

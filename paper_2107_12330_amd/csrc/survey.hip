@@ -1269,7 +1269,7 @@ extern "C" tp_status tripoll_tune(tp_graph *g, const tp_survey_spec *spec, void 
         DArray<unsigned long long> buf(TP_RESULT_WORDS, s);
         zero_u64<<<grid_for(TP_RESULT_WORDS, 256), 256, 0, s>>>(buf.get(), TP_RESULT_WORDS);
         TP_CHECK_LAUNCH();
-        static const uint32_t kCaps[] = {256, 1024, 4096};
+        static const uint32_t kCaps[] = {256, 1024, 4096, 16384};
         static const std::vector<uint32_t> kCands[kNumClasses] = {
             {TP_VAR_WAVE_TABLE, TP_VAR_GROUP_TABLE, TP_VAR_WAVE_SEARCH},
             {TP_VAR_GROUP_TABLE, TP_VAR_SEARCH, TP_VAR_WAVE_SEARCH},
@@ -1281,7 +1281,7 @@ extern "C" tp_status tripoll_tune(tp_graph *g, const tp_survey_spec *spec, void 
         for (int c = 0; c < kNumClasses; ++c) {
             best[c] = -1.f;
             best_v[c] = TP_VAR_DEFAULT;
-            best_cap[c] = kTileRecords;
+            best_cap[c] = default_tile_records(c);
         }
         for (uint32_t cap : kCaps) {
             PlanCfg cfg{};
@@ -1295,7 +1295,7 @@ extern "C" tp_status tripoll_tune(tp_graph *g, const tp_survey_spec *spec, void 
                     (void)time_class(g, &sp, buf.get(), c, v, 1, s);
                     const float ms = time_class(g, &sp, buf.get(), c, v, 2, s);
                     ++r.trials;
-                    if (cap == kTileRecords && v == dflt) r.default_ms[c] = ms;
+                    if (cap == default_tile_records(c) && v == dflt) r.default_ms[c] = ms;
                     if (best[c] < 0.f || ms < best[c]) {
                         best[c] = ms;
                         best_v[c] = v;
@@ -1308,7 +1308,7 @@ extern "C" tp_status tripoll_tune(tp_graph *g, const tp_survey_spec *spec, void 
         PlanCfg fin{};
         for (int c = 0; c < kNumClasses; ++c) {
             fin.variant[c] = TP_VAR_DEFAULT;
-            fin.tile_records[c] = kTileRecords;
+            fin.tile_records[c] = default_tile_records(c);
             if (best[c] >= 0.f && best[c] < 0.97f * r.default_ms[c]) {
                 fin.variant[c] = best_v[c];
                 fin.tile_records[c] = best_cap[c];
