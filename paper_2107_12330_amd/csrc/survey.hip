@@ -263,6 +263,12 @@ __device__ __forceinline__ T sload(const T *p)
 // `len` slots of p's row starting at `start`.
 // One in-edge as the wave walks it: the candidates of p -> q are the `len`
 // slots of p's row starting at `start`.  A block holds one in-edge per lane.
+// In-edge records as loaded: key (q << kbits) | k and payload.
+struct KeyBlock {
+    uint64_t key;
+    uint32_t pay;
+};
+
 // Loaded values are kept as loaded (no arithmetic on them until they are
 // read), so that no instruction waits for a load right after issuing it.
 struct RecBlock {
@@ -461,6 +467,23 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
         const uint64_t t_end = min(t_begin + kClaim, P.n_tiles);
         for (uint64_t ti = t_begin; ti < t_end; ++ti) {
             const TileDesc d = sload(P.tiles + (P.n_tiles - 1 - ti));
+            // this wave's records: tile records wl, wl + kW, wl + 2kW, ...;
+            // lane l of block b holds record 64b + l.  The first two blocks
+            // are requested before the table is rebuilt, so that their
+            // latency hides behind it.  Lanes past the wave's last record
+            // load the tile's first record; they are never read.
+            const uint32_t ncnt = d.cnt;
+            const uint32_t nw = ncnt > (uint32_t)wl ? (ncnt - (uint32_t)wl + kW - 1) / kW : 0u;
+            auto load_keys = [&](uint32_t blk) -> KeyBlock {
+                const uint32_t i = min(blk * kWave + lane, nw - 1);
+                const uint64_t e = d.e0 + ((uint64_t)(uint32_t)wl + (uint64_t)i * kW) * d.stride;
+                return KeyBlock{P.inkey[e], P.inpay[e]};
+            };
+            KeyBlock kb0{0, 0}, kb1{0, 0};
+            if (nw) {
+                kb0 = load_keys(0);
+                kb1 = load_keys(1);
+            }
             if (d.q != cur_q) {
                 // a new target: reduce the hits still queued against the old
                 // table, then rebuild it once every wave is done with it
@@ -539,27 +562,13 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
             // walk itself issues no memory access.
             auto walk = [&](auto gm) {
                 constexpr bool G = decltype(gm)::value;
-                const uint32_t ncnt = d.cnt;
-                const uint32_t nw = ncnt > (uint32_t)wl ? (ncnt - (uint32_t)wl + kW - 1) / kW : 0u;
                 if (nw == 0) return;
                 const uint64_t kmask = (1ull << P.kbits) - 1;
-                // lane l of block b holds this wave's in-edge 64b + l (tile record w + (64b + l) kW)
                 // A block is loaded in two stages a block apart, so that no
                 // load waits on a load issued just before it (loads retire in
                 // order: such a wait would drain the candidate loads in
                 // flight): the records of block b + 2, then the gather of
                 // time(p, q) for block b + 1 from keys that arrived long ago.
-                // Lanes past the wave's last record load the tile's first
-                // record; they are never read.
-                struct KeyBlock {
-                    uint64_t key;
-                    uint32_t pay;
-                };
-                auto load_keys = [&](uint32_t blk) -> KeyBlock {
-                    const uint32_t i = min(blk * kWave + lane, nw - 1);
-                    const uint64_t e = d.e0 + ((uint64_t)(uint32_t)wl + (uint64_t)i * kW) * d.stride;
-                    return KeyBlock{P.inkey[e], P.inpay[e]};
-                };
                 auto gather = [&](const KeyBlock &kb) -> RecBlock {
                     RecBlock r;
                     r.key = kb.key;
@@ -567,8 +576,8 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                     r.t_pq = (META || ENUM) ? P.ets[kb.key & kmask] : 0u;
                     return r;
                 };
-                RecBlock blk_cur = gather(load_keys(0));
-                RecBlock blk_nxt = gather(load_keys(1));
+                RecBlock blk_cur = gather(kb0);
+                RecBlock blk_nxt = gather(kb1);
                 KeyBlock key_nxt = load_keys(2);
                 struct WaveRec {
                     uint64_t start;
