@@ -11,6 +11,12 @@ Survey outputs are selected by name:
   "label_table"   counts per sorted vertex-label multiset (colex index)
   "spread_count"  triangles with max t - min t < spread_lt
   "open_close"    32 x 32 joint (open, close) bins (Algorithm 4)
+  "max_edge"      Algorithm 3: over triangles with pairwise distinct vertex
+                  labels, counts of the largest edge time t3 in 1024 bins
+                  t3 >> max_edge_shift (the last bin takes the rest)
+  "degree_table"  counts per sorted triple of ceil(log2 d(v)) over the three
+                  vertices (the degree metadata of the evaluation), indexed
+                  like the label table, 5984 entries (values 0..31)
 Filters: window=(t_lo, t_hi) keeps triangles whose three times lie in the
 closed range; label_mask=set of multiset indices keeps only those.
 """
@@ -26,13 +32,16 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-OUT_BITS = {"count": 1, "close_hist": 2, "label_table": 4, "spread_count": 8, "open_close": 16}
+OUT_BITS = {"count": 1, "close_hist": 2, "label_table": 4, "spread_count": 8, "open_close": 16,
+            "max_edge": 32, "degree_table": 64}
 TABLE_MAX = 816
+MAX_EDGE_BINS = 1024
+DEGREE_MAX = 5984  # C(34, 3): multisets of three values in 0..31
 
 
 class _Spec(ctypes.Structure):
     _fields_ = [("outputs", ctypes.c_uint32), ("filters", ctypes.c_uint32),
-                ("n_labels", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("n_labels", ctypes.c_uint32), ("max_edge_shift", ctypes.c_uint32),
                 ("spread_lt", ctypes.c_uint64), ("t_lo", ctypes.c_uint64), ("t_hi", ctypes.c_uint64),
                 ("label_mask", ctypes.c_uint64 * ((TABLE_MAX + 63) // 64))]
 
@@ -41,7 +50,9 @@ class _Result(ctypes.Structure):
     _fields_ = [("triangles", ctypes.c_uint64), ("spread_count", ctypes.c_uint64),
                 ("wedges", ctypes.c_uint64), ("close_hist", ctypes.c_uint64 * 32),
                 ("label_table", ctypes.c_uint64 * TABLE_MAX),
-                ("open_close", ctypes.c_uint64 * 1024)]
+                ("open_close", ctypes.c_uint64 * 1024),
+                ("max_edge", ctypes.c_uint64 * MAX_EDGE_BINS),
+                ("degree_table", ctypes.c_uint64 * DEGREE_MAX)]
 
 
 TRI_DTYPE = np.dtype([("a", "<u4"), ("b", "<u4"), ("c", "<u4"),
@@ -124,7 +135,8 @@ def clean(n: int, src: np.ndarray, dst: np.ndarray, ts: np.ndarray | None):
 
 
 def survey_clean(n: int, u, v, t, vlab, outputs=("count",), n_labels: int = 4, spread_lt: int = 0,
-                 window=None, label_mask=None, threads: int = 0, records: bool = False):
+                 window=None, label_mask=None, threads: int = 0, records: bool = False,
+                 max_edge_shift: int = 0):
     """Survey an already-cleaned graph.  Returns a dict of results (and the
     triangle records as a structured array when records=True)."""
     lib = _load()
@@ -132,6 +144,7 @@ def survey_clean(n: int, u, v, t, vlab, outputs=("count",), n_labels: int = 4, s
     sp.outputs = sum(OUT_BITS[o] for o in outputs)
     sp.n_labels = n_labels
     sp.spread_lt = spread_lt
+    sp.max_edge_shift = max_edge_shift
     if window is not None:
         sp.filters |= 1
         sp.t_lo, sp.t_hi = int(window[0]), int(window[1])
@@ -160,13 +173,17 @@ def survey_clean(n: int, u, v, t, vlab, outputs=("count",), n_labels: int = 4, s
                            ctypes.byref(res), threads, _ptr(recs), cap, ctypes.byref(nrec))
     if rc == -3:
         raise ValueError("vertex label >= n_labels")
+    if rc == -4:
+        raise ValueError("max_edge_shift must be below 32")
     if rc != 0:
         raise RuntimeError("oracle_survey failed: %d" % rc)
     out = dict(triangles=int(res.triangles), spread_count=int(res.spread_count),
                wedges=int(res.wedges),
                close_hist=np.frombuffer(bytes(res.close_hist), np.uint64).copy(),
                label_table=np.frombuffer(bytes(res.label_table), np.uint64)[:table_size(n_labels)].copy(),
-               open_close=np.frombuffer(bytes(res.open_close), np.uint64).reshape(32, 32).copy())
+               open_close=np.frombuffer(bytes(res.open_close), np.uint64).reshape(32, 32).copy(),
+               max_edge=np.frombuffer(bytes(res.max_edge), np.uint64).copy(),
+               degree_table=np.frombuffer(bytes(res.degree_table), np.uint64).copy())
     if records:
         out["records"] = recs[:int(nrec.value)]
     return out

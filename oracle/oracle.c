@@ -24,6 +24,18 @@
  *   - Algorithms 2 and 4: the counting callback and the closure-time callback
  *     (t1 <= t2 <= t3 the sorted edge timestamps; close = ceil(log2(t3 - t1)),
  *     open = ceil(log2(t2 - t1))).
+ *   - Algorithm 3: among triangles whose three vertex labels are pairwise
+ *     distinct, the distribution of the largest edge metadata (here the edge
+ *     time t3).  The paper counts exact values in a counting set; here the
+ *     count is kept per 2^shift-wide range of t3 (bin t3 >> shift, the last
+ *     of 1024 bins taking everything above), which is the exact counting set
+ *     whenever every t3 >> shift is below 1024.
+ *   - Metadata-overhead experiment of the evaluation (vertex degree as the
+ *     metadata): counts of the triple (ceil(log2 d(p)), ceil(log2 d(q)),
+ *     ceil(log2 d(r))) over all triangles, p, q, r in the degree order.
+ *     Because the three are in degree order the triple is non-decreasing, so
+ *     it is the sorted triple of the three vertices' values and is counted by
+ *     its multiset index, like the label table.
  *
  * The oracle orders vertices by (degree, original id), i.e. the paper's order
  * with the identity as tie-break, and keeps every out-list sorted by original
@@ -49,18 +61,22 @@
 #define ORC_OUT_LABEL_TABLE 4u
 #define ORC_OUT_SPREAD 8u
 #define ORC_OUT_OPEN_CLOSE 16u
+#define ORC_OUT_MAX_EDGE 32u
+#define ORC_OUT_DEGREE_TABLE 64u
 
 #define ORC_FILT_WINDOW 1u
 #define ORC_FILT_LABEL_MASK 2u
 
 #define ORC_MAX_LABELS 16
 #define ORC_TABLE_MAX 816 /* C(16+2, 3) */
+#define ORC_MAX_EDGE_BINS 1024
+#define ORC_DEGREE_MAX 5984 /* C(32+2, 3): degree bins 0..31 */
 
 typedef struct {
     uint32_t outputs;
     uint32_t filters;
     uint32_t n_labels;
-    uint32_t reserved;
+    uint32_t max_edge_shift; /* Algorithm 3 bins: t3 >> max_edge_shift */
     uint64_t spread_lt;   /* spread counter: max(t) - min(t) < spread_lt */
     uint64_t t_lo, t_hi;  /* window filter: all three t in [t_lo, t_hi] */
     uint64_t label_mask[(ORC_TABLE_MAX + 63) / 64];
@@ -73,6 +89,8 @@ typedef struct {
     uint64_t close_hist[32];
     uint64_t label_table[ORC_TABLE_MAX];
     uint64_t open_close[32 * 32];
+    uint64_t max_edge[ORC_MAX_EDGE_BINS];
+    uint64_t degree_table[ORC_DEGREE_MAX];
 } orc_result;
 
 /* ------------------------------------------------------------------------ */
@@ -116,7 +134,8 @@ uint32_t oracle_msidx(uint32_t a, uint32_t b, uint32_t c)
 
 static void callback(const orc_spec *sp, orc_result *acc,
                      uint32_t t_pq, uint32_t t_pr, uint32_t t_qr,
-                     uint8_t l_p, uint8_t l_q, uint8_t l_r)
+                     uint8_t l_p, uint8_t l_q, uint8_t l_r,
+                     uint64_t d_p, uint64_t d_q, uint64_t d_r)
 {
     /* prefilters */
     if (sp->filters & ORC_FILT_WINDOW) {
@@ -147,6 +166,14 @@ static void callback(const orc_spec *sp, orc_result *acc,
         acc->spread_count += (close < sp->spread_lt) ? 1u : 0u;
     if (sp->outputs & ORC_OUT_OPEN_CLOSE)
         acc->open_close[oracle_bin(open) * 32 + oracle_bin(close)] += 1;
+    if ((sp->outputs & ORC_OUT_MAX_EDGE) && l_p != l_q && l_q != l_r && l_p != l_r) {
+        /* the largest of the three edge times, t3, in its range of 2^shift */
+        uint64_t b = (uint64_t)t3 >> sp->max_edge_shift;
+        if (b > ORC_MAX_EDGE_BINS - 1) b = ORC_MAX_EDGE_BINS - 1;
+        acc->max_edge[b] += 1;
+    }
+    if (sp->outputs & ORC_OUT_DEGREE_TABLE)
+        acc->degree_table[oracle_msidx(oracle_bin(d_p), oracle_bin(d_q), oracle_bin(d_r))] += 1;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -208,6 +235,7 @@ typedef struct {
     uint64_t *start;   /* [n+1] */
     uint32_t *nbr;     /* [m] */
     uint32_t *tim;     /* [m] */
+    uint64_t *deg;     /* [n] undirected degree d(v) of the cleaned graph */
 } orc_graph;
 
 typedef struct {
@@ -268,18 +296,18 @@ static int orient(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev
     }
     free(tmp);
     free(fill);
-    free(deg);
+    g->deg = deg;
     return 0;
 oom:
     free(tmp); free(fill); free(deg);
     free(g->start); free(g->nbr); free(g->tim);
-    g->start = NULL; g->nbr = NULL; g->tim = NULL;
+    g->start = NULL; g->nbr = NULL; g->tim = NULL; g->deg = NULL;
     return -2;
 }
 
 static void free_graph(orc_graph *g)
 {
-    free(g->start); free(g->nbr); free(g->tim);
+    free(g->start); free(g->nbr); free(g->tim); free(g->deg);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -316,6 +344,7 @@ static void emit_record(orc_tri *rec, uint32_t p, uint32_t q, uint32_t r,
 
 /*
  * Survey of the cleaned graph (u[i] < v[i], each pair once, times t[i]).
+ * The Algorithm 3 output needs max_edge_shift < 32.
  * If `records` is non-NULL the triangles are also written there (at most
  * `capacity`; the count is returned in *n_records), in no particular order.
  * Returns 0, or -2 on allocation failure, -3 if a label >= n_labels is met
@@ -327,6 +356,7 @@ int oracle_survey(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev
 {
     orc_graph g;
     memset(out, 0, sizeof(*out));
+    if ((sp->outputs & ORC_OUT_MAX_EDGE) && sp->max_edge_shift > 31) return -4;
     if ((sp->outputs & ORC_OUT_LABEL_TABLE || sp->filters & ORC_FILT_LABEL_MASK) && vlab) {
         for (uint32_t v = 0; v < n; ++v)
             if (vlab[v] >= sp->n_labels) return -3;
@@ -370,7 +400,7 @@ int oracle_survey(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev
                     const uint32_t t_pr = g.tim[x], t_qr = g.tim[y];
                     const uint8_t l_p = vlab ? vlab[p] : 0, l_q = vlab ? vlab[q] : 0,
                                   l_r = vlab ? vlab[r] : 0;
-                    callback(sp, acc, t_pq, t_pr, t_qr, l_p, l_q, l_r);
+                    callback(sp, acc, t_pq, t_pr, t_qr, l_p, l_q, l_r, g.deg[p], g.deg[q], g.deg[r]);
                     if (records) {
                         uint64_t slot;
 #pragma omp atomic capture
@@ -391,6 +421,8 @@ int oracle_survey(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev
                 for (int b = 0; b < 32; ++b) out->close_hist[b] += acc->close_hist[b];
                 for (int b = 0; b < ORC_TABLE_MAX; ++b) out->label_table[b] += acc->label_table[b];
                 for (int b = 0; b < 32 * 32; ++b) out->open_close[b] += acc->open_close[b];
+                for (int b = 0; b < ORC_MAX_EDGE_BINS; ++b) out->max_edge[b] += acc->max_edge[b];
+                for (int b = 0; b < ORC_DEGREE_MAX; ++b) out->degree_table[b] += acc->degree_table[b];
             }
         }
         free(acc);

@@ -56,12 +56,18 @@ def triangles(n: int, edges: dict):
     return out
 
 
-def survey(n, src, dst, ts, vlab, n_labels=4, spread_lt=0, window=None, label_mask=None):
+def survey(n, src, dst, ts, vlab, n_labels=4, spread_lt=0, window=None, label_mask=None, max_edge_shift=0):
     edges = clean_dict(np.asarray(src), np.asarray(dst), np.asarray(ts))
     tris = triangles(n, edges)
     idx_of = colex_multisets(n_labels)
+    deg_idx = colex_multisets(32)
+    degree = [0] * n
+    for a, b in edges:
+        degree[a] += 1
+        degree[b] += 1
     res = dict(triangles=0, spread_count=0, close_hist=np.zeros(32, np.uint64),
                label_table=np.zeros(len(idx_of), np.uint64), open_close=np.zeros((32, 32), np.uint64),
+               max_edge=np.zeros(1024, np.uint64), degree_table=np.zeros(len(deg_idx), np.uint64),
                m=len(edges), tris=tris)
     for a, b, c, tab, tac, tbc in tris:
         times = sorted((tab, tac, tbc))
@@ -79,4 +85,10 @@ def survey(n, src, dst, ts, vlab, n_labels=4, spread_lt=0, window=None, label_ma
         res["open_close"][ceil_log2_bin(opn), ceil_log2_bin(close)] += 1
         if close < spread_lt:
             res["spread_count"] += 1
+        # Algorithm 3: pairwise distinct vertex labels, largest edge time
+        if len({int(vlab[a]), int(vlab[b]), int(vlab[c])}) == 3:
+            res["max_edge"][min(1023, times[2] // 2 ** max_edge_shift)] += 1
+        # degree metadata: sorted triple of ceil(log2 d)
+        dl = tuple(sorted(ceil_log2_bin(degree[x]) for x in (a, b, c)))
+        res["degree_table"][deg_idx[dl]] += 1
     return res

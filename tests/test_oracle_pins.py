@@ -17,7 +17,7 @@ import synth
 from tests import brute
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-ALL_OUT = ("count", "close_hist", "label_table", "spread_count", "open_close")
+ALL_OUT = ("count", "close_hist", "label_table", "spread_count", "open_close", "max_edge", "degree_table")
 
 
 def run(n, edges, labels=None, **kw):
@@ -137,6 +137,81 @@ def test_complete_graph_label_classes():
     assert r["label_table"].sum() == math.comb(n, 3)
 
 
+# -------------------------------------------------------------- Algorithm 3 and degree triples
+
+
+@pytest.mark.parametrize("n,shift", [(8, 0), (16, 0), (16, 2), (40, 0), (40, 3)])
+def test_max_edge_complete_graph_closed_form(n, shift):
+    # K_n with ts(u,v) = max(u,v): the largest edge time of triangle a<b<c is c,
+    # and vertex c closes C(c,2) triangles; distinct labels (v mod 16) hold for
+    # all triangles when n <= 16 and for those with distinct residues otherwise
+    labels = [v % 16 for v in range(n)]
+    r = run(n, complete(n, lambda u, v: max(u, v)), labels, n_labels=16, max_edge_shift=shift)
+    exp = np.zeros(1024, np.uint64)
+    for c in range(n):
+        for a, b in combinations(range(c), 2):
+            if len({labels[a], labels[b], labels[c]}) == 3:
+                exp[c >> shift] += 1
+    if n <= 16:
+        assert exp.sum() == math.comb(n, 3)
+        for c in range(n):
+            assert int(exp[c]) == math.comb(c, 2) or shift
+    assert (r["max_edge"] == exp).all()
+
+
+def test_max_edge_label_classes_and_saturation():
+    # three label classes: every distinct-label triangle takes one vertex of
+    # each class, n_a*n_b*n_c of them; two classes give none
+    sizes = [4, 3, 5]
+    labels = sum(([c] * s for c, s in enumerate(sizes)), [])
+    n = len(labels)
+    r = run(n, complete(n, lambda u, v: 5000 + u + v), labels, n_labels=4, max_edge_shift=0)
+    assert r["max_edge"].sum() == 4 * 3 * 5
+    assert r["max_edge"][1023] == 4 * 3 * 5  # every time >= 1023 lands in the last bin
+    r2 = run(n, complete(n), [0 if x < 2 else 1 for x in labels], n_labels=4)
+    assert r2["max_edge"].sum() == 0
+    # the distinct-label triangles are exactly the label-table cells a<b<c
+    idx = brute.colex_multisets(4)
+    assert r["max_edge"].sum() == sum(int(r["label_table"][idx[(a, b, c)]])
+                                      for a, b, c in combinations(range(4), 3))
+
+
+def test_max_edge_shift_range():
+    with pytest.raises(ValueError):
+        run(4, complete(4), outputs=("count", "max_edge"), max_edge_shift=32)
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 9, 17, 33])
+def test_degree_table_complete_graph(n):
+    # every vertex of K_n has degree n-1
+    b = oracle.bin_of(n - 1)
+    r = run(n, complete(n))
+    exp = np.zeros(oracle.DEGREE_MAX, np.uint64)
+    exp[brute.colex_multisets(32)[(b, b, b)]] = math.comb(n, 3)
+    assert (r["degree_table"] == exp).all()
+
+
+@pytest.mark.parametrize("k", [2, 3, 5, 9, 100])
+def test_degree_table_friendship_and_wheel(k):
+    idx = brute.colex_multisets(32)
+    # friendship graph F_k: centre of degree 2k, blades of degree 2
+    fr = []
+    for i in range(k):
+        a, c = 1 + 2 * i, 2 + 2 * i
+        fr += [(0, a, 0), (0, c, 0), (a, c, 0)]
+    r = run(2 * k + 1, fr)
+    exp = np.zeros(oracle.DEGREE_MAX, np.uint64)
+    exp[idx[tuple(sorted((1, 1, math.ceil(math.log2(2 * k)))))]] = k
+    assert (r["degree_table"] == exp).all()
+    # wheel of k >= 4 spokes: hub degree k, rim degree 3 (ceil(log2 3) = 2)
+    if k >= 4:
+        wheel = [(0, i, 0) for i in range(1, k + 1)] + [(i, i % k + 1, 0) for i in range(1, k + 1)]
+        r = run(k + 1, wheel)
+        exp = np.zeros(oracle.DEGREE_MAX, np.uint64)
+        exp[idx[(2, 2, math.ceil(math.log2(k)))]] = k
+        assert (r["degree_table"] == exp).all()
+
+
 def test_zero_triangle_families():
     star = [(0, i, i) for i in range(1, 50)]
     assert run(50, star)["triangles"] == 0
@@ -229,6 +304,8 @@ def test_against_brute_force(seed, n, M, L):
     assert (r["close_hist"] == b["close_hist"]).all()
     assert (r["label_table"] == b["label_table"]).all()
     assert (r["open_close"] == b["open_close"]).all()
+    assert (r["max_edge"] == b["max_edge"]).all()
+    assert (r["degree_table"] == b["degree_table"]).all()
     assert r["spread_count"] == b["spread_count"]
     # exactly once, with the same six metadata items
     rec = r["records"]
@@ -351,6 +428,10 @@ def test_sums_equal_triangles():
     g = synth.generate(w.graph)
     r = oracle.survey(g["n"], g["src"], g["dst"], g["ts"], g["vlab"], outputs=ALL_OUT, n_labels=4)
     assert r["close_hist"].sum() == r["label_table"].sum() == r["open_close"].sum() == r["triangles"]
+    assert r["degree_table"].sum() == r["triangles"]
+    idx = brute.colex_multisets(4)
+    distinct = sum(int(r["label_table"][idx[(a, b, c)]]) for a, b, c in combinations(range(4), 3))
+    assert r["max_edge"].sum() == distinct > 0
 
 
 def test_label_out_of_range_rejected():
