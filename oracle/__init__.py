@@ -19,6 +19,9 @@ Survey outputs are selected by name:
                   like the label table, 5984 entries (values 0..31)
 Filters: window=(t_lo, t_hi) keeps triangles whose three times lie in the
 closed range; label_mask=set of multiset indices keeps only those.
+
+participation() gives the local counts: triangles at each vertex and at each
+edge of the cleaned graph, under the same filters.
 """
 from __future__ import annotations
 
@@ -90,6 +93,9 @@ def _load():
     lib.oracle_survey.argtypes = [ctypes.c_uint32, ctypes.c_uint64, p, p, p, p,
                                   ctypes.POINTER(_Spec), ctypes.POINTER(_Result), ctypes.c_int,
                                   p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.oracle_participation.restype = ctypes.c_int
+    lib.oracle_participation.argtypes = [ctypes.c_uint32, ctypes.c_uint64, p, p, p, p, ctypes.POINTER(_Spec), p, p,
+                                         ctypes.c_int]
     for f in ("oracle_sizeof_spec", "oracle_sizeof_result", "oracle_sizeof_tri"):
         getattr(lib, f).restype = ctypes.c_uint64
     assert lib.oracle_sizeof_spec() == ctypes.sizeof(_Spec)
@@ -205,3 +211,30 @@ def survey(n: int, src, dst, ts, vlab, **kw):
     out = survey_clean(n, u, v, t, vlab, **kw)
     out["m"] = len(u)
     return out
+
+
+def participation(n: int, src, dst, ts, vlab, n_labels: int = 4, window=None, label_mask=None, threads: int = 0):
+    """Clean the raw edge list, then count the triangles at every vertex (by
+    id) and at every edge.  Returns (vertex_counts, (u, v, t, edge_counts))
+    with the cleaned edges sorted by (u, v), u < v."""
+    u, v, t = clean(n, src, dst, ts)
+    lib = _load()
+    sp = _Spec()
+    sp.n_labels = n_labels
+    if window is not None:
+        sp.filters |= 1
+        sp.t_lo, sp.t_hi = int(window[0]), int(window[1])
+    if label_mask is not None:
+        sp.filters |= 2
+        for idx in label_mask:
+            sp.label_mask[idx // 64] |= 1 << (idx % 64)
+    vlab = None if vlab is None else np.ascontiguousarray(vlab, np.uint8)
+    vc = np.zeros(max(n, 1), np.uint64)
+    ec = np.zeros(max(len(u), 1), np.uint64)
+    rc = lib.oracle_participation(n, len(u), _ptr(u), _ptr(v), _ptr(t), _ptr(vlab), ctypes.byref(sp), _ptr(vc),
+                                  _ptr(ec), threads)
+    if rc == -3:
+        raise ValueError("vertex label >= n_labels")
+    if rc != 0:
+        raise RuntimeError("oracle_participation failed: %d" % rc)
+    return vc[:n], (u, v, t, ec[:len(u)])

@@ -30,6 +30,10 @@
  *     count is kept per 2^shift-wide range of t3 (bin t3 >> shift, the last
  *     of 1024 bins taking everything above), which is the exact counting set
  *     whenever every t3 >> shift is below 1024.
+ *   - Local participation (Introduction; Triangle Counting subsection): per
+ *     vertex and per edge, the number of triangles that contain it (the
+ *     counters of clustering coefficients and truss decomposition), under
+ *     the same prefilters as the surveys.
  *   - Metadata-overhead experiment of the evaluation (vertex degree as the
  *     metadata): counts of the triple (ceil(log2 d(p)), ceil(log2 d(q)),
  *     ceil(log2 d(r))) over all triangles, p, q, r in the degree order.
@@ -132,23 +136,32 @@ uint32_t oracle_msidx(uint32_t a, uint32_t b, uint32_t c)
     return (uint32_t)(choose(c + 2, 3) + choose(b + 1, 2) + a);
 }
 
+/* The prefilters: all three times in the closed window, and the label
+ * multiset's bit set in the mask. */
+static int passes(const orc_spec *sp, uint32_t t_pq, uint32_t t_pr, uint32_t t_qr,
+                  uint8_t l_p, uint8_t l_q, uint8_t l_r)
+{
+    if (sp->filters & ORC_FILT_WINDOW) {
+        if (t_pq < sp->t_lo || t_pq > sp->t_hi) return 0;
+        if (t_pr < sp->t_lo || t_pr > sp->t_hi) return 0;
+        if (t_qr < sp->t_lo || t_qr > sp->t_hi) return 0;
+    }
+    if (sp->filters & ORC_FILT_LABEL_MASK) {
+        const uint32_t idx = oracle_msidx(l_p, l_q, l_r);
+        if (!((sp->label_mask[idx / 64] >> (idx % 64)) & 1u)) return 0;
+    }
+    return 1;
+}
+
 static void callback(const orc_spec *sp, orc_result *acc,
                      uint32_t t_pq, uint32_t t_pr, uint32_t t_qr,
                      uint8_t l_p, uint8_t l_q, uint8_t l_r,
                      uint64_t d_p, uint64_t d_q, uint64_t d_r)
 {
-    /* prefilters */
-    if (sp->filters & ORC_FILT_WINDOW) {
-        if (t_pq < sp->t_lo || t_pq > sp->t_hi) return;
-        if (t_pr < sp->t_lo || t_pr > sp->t_hi) return;
-        if (t_qr < sp->t_lo || t_qr > sp->t_hi) return;
-    }
+    if (!passes(sp, t_pq, t_pr, t_qr, l_p, l_q, l_r)) return;
     uint32_t idx = 0;
-    if (sp->outputs & ORC_OUT_LABEL_TABLE || sp->filters & ORC_FILT_LABEL_MASK)
+    if (sp->outputs & ORC_OUT_LABEL_TABLE)
         idx = oracle_msidx(l_p, l_q, l_r);
-    if (sp->filters & ORC_FILT_LABEL_MASK) {
-        if (!((sp->label_mask[idx / 64] >> (idx % 64)) & 1u)) return;
-    }
     /* sorted timestamps t1 <= t2 <= t3 */
     uint32_t t1 = t_pq, t2 = t_pr, t3 = t_qr, t;
     if (t1 > t2) { t = t1; t1 = t2; t2 = t; }
@@ -236,10 +249,12 @@ typedef struct {
     uint32_t *nbr;     /* [m] */
     uint32_t *tim;     /* [m] */
     uint64_t *deg;     /* [n] undirected degree d(v) of the cleaned graph */
+    uint64_t *eid;     /* [m] position of each oriented edge in the cleaned list */
 } orc_graph;
 
 typedef struct {
     uint32_t v, t;
+    uint64_t e;
 } nb_t;
 
 static int nb_cmp(const void *x, const void *y)
@@ -263,9 +278,10 @@ static int orient(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev
     g->start = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
     g->nbr = (uint32_t *)malloc((m ? m : 1) * sizeof(uint32_t));
     g->tim = (uint32_t *)malloc((m ? m : 1) * sizeof(uint32_t));
+    g->eid = (uint64_t *)malloc((m ? m : 1) * sizeof(uint64_t));
     uint64_t *fill = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
     nb_t *tmp = NULL;
-    if (!deg || !g->start || !g->nbr || !g->tim || !fill) goto oom;
+    if (!deg || !g->start || !g->nbr || !g->tim || !g->eid || !fill) goto oom;
     for (uint64_t i = 0; i < m; ++i) { deg[eu[i]]++; deg[ev[i]]++; }
     /* out-degree counts, then row starts */
     for (uint64_t i = 0; i < m; ++i) {
@@ -279,6 +295,7 @@ static int orient(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev
         const uint64_t at = g->start[s] + fill[s]++;
         g->nbr[at] = d;
         g->tim[at] = et[i];
+        g->eid[at] = i;
     }
     /* sort each out-list by original id */
     uint64_t maxrow = 0;
@@ -290,9 +307,17 @@ static int orient(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev
     if (!tmp) goto oom;
     for (uint32_t v = 0; v < n; ++v) {
         const uint64_t b = g->start[v], len = g->start[v + 1] - b;
-        for (uint64_t j = 0; j < len; ++j) { tmp[j].v = g->nbr[b + j]; tmp[j].t = g->tim[b + j]; }
+        for (uint64_t j = 0; j < len; ++j) {
+            tmp[j].v = g->nbr[b + j];
+            tmp[j].t = g->tim[b + j];
+            tmp[j].e = g->eid[b + j];
+        }
         qsort(tmp, len, sizeof(nb_t), nb_cmp);
-        for (uint64_t j = 0; j < len; ++j) { g->nbr[b + j] = tmp[j].v; g->tim[b + j] = tmp[j].t; }
+        for (uint64_t j = 0; j < len; ++j) {
+            g->nbr[b + j] = tmp[j].v;
+            g->tim[b + j] = tmp[j].t;
+            g->eid[b + j] = tmp[j].e;
+        }
     }
     free(tmp);
     free(fill);
@@ -300,14 +325,14 @@ static int orient(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev
     return 0;
 oom:
     free(tmp); free(fill); free(deg);
-    free(g->start); free(g->nbr); free(g->tim);
-    g->start = NULL; g->nbr = NULL; g->tim = NULL; g->deg = NULL;
+    free(g->start); free(g->nbr); free(g->tim); free(g->eid);
+    g->start = NULL; g->nbr = NULL; g->tim = NULL; g->deg = NULL; g->eid = NULL;
     return -2;
 }
 
 static void free_graph(orc_graph *g)
 {
-    free(g->start); free(g->nbr); free(g->tim); free(g->deg);
+    free(g->start); free(g->nbr); free(g->tim); free(g->deg); free(g->eid);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -430,6 +455,71 @@ int oracle_survey(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev
     if (n_records) *n_records = n_rec;
     free_graph(&g);
     return err;
+}
+
+/*
+ * Local participation counts of the cleaned graph (u[i] < v[i], each pair
+ * once): for every triangle that passes the spec's prefilters, one for each
+ * of its three vertices (vcount, by original id, n entries) and each of its
+ * three edges (ecount, by position in the cleaned list, m entries).  Either
+ * output may be NULL.  Returns 0, -2 on allocation failure, -3 for a label
+ * >= n_labels while the label mask is used.
+ */
+int oracle_participation(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev, const uint32_t *et,
+                         const uint8_t *vlab, const orc_spec *sp, uint64_t *vcount, uint64_t *ecount,
+                         int n_threads)
+{
+    orc_graph g;
+    if (vcount) memset(vcount, 0, (size_t)n * sizeof(uint64_t));
+    if (ecount) memset(ecount, 0, (size_t)m * sizeof(uint64_t));
+    if ((sp->filters & ORC_FILT_LABEL_MASK) && vlab) {
+        for (uint32_t v = 0; v < n; ++v)
+            if (vlab[v] >= sp->n_labels) return -3;
+    }
+    if (orient(n, m, eu, ev, et, &g) != 0) return -2;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    int64_t p;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (p = 0; p < (int64_t)n; ++p) {
+        const uint64_t pb = g.start[p], pe = g.start[p + 1];
+        for (uint64_t i = pb; i < pe; ++i) {
+            const uint32_t q = g.nbr[i];
+            uint64_t x = pb, y = g.start[q];
+            const uint64_t ye = g.start[q + 1];
+            while (x < pe && y < ye) {
+                if (g.nbr[x] < g.nbr[y]) { ++x; continue; }
+                if (g.nbr[x] > g.nbr[y]) { ++y; continue; }
+                const uint32_t r = g.nbr[x];
+                const uint8_t l_p = vlab ? vlab[p] : 0, l_q = vlab ? vlab[q] : 0, l_r = vlab ? vlab[r] : 0;
+                if (passes(sp, g.tim[i], g.tim[x], g.tim[y], l_p, l_q, l_r)) {
+                    if (vcount) {
+#pragma omp atomic
+                        vcount[p] += 1;
+#pragma omp atomic
+                        vcount[q] += 1;
+#pragma omp atomic
+                        vcount[r] += 1;
+                    }
+                    if (ecount) {
+#pragma omp atomic
+                        ecount[g.eid[i]] += 1;
+#pragma omp atomic
+                        ecount[g.eid[x]] += 1;
+#pragma omp atomic
+                        ecount[g.eid[y]] += 1;
+                    }
+                }
+                ++x;
+                ++y;
+            }
+        }
+    }
+    free_graph(&g);
+    return 0;
 }
 
 /* Sizes of the structs, so a binding can check its own layout. */

@@ -437,3 +437,77 @@ def test_sums_equal_triangles():
 def test_label_out_of_range_rejected():
     with pytest.raises(ValueError):
         run(3, complete(3), [0, 1, 5], n_labels=4)
+
+
+# -------------------------------------------------------------- local participation
+
+def part(n, edges, labels=None, **kw):
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 3)
+    src, dst, ts = (e[:, i].astype(np.uint32) for i in range(3))
+    vlab = np.zeros(n, np.uint8) if labels is None else np.asarray(labels, np.uint8)
+    vc, (u, v, t, ec) = oracle.participation(n, src, dst, ts, vlab, **kw)
+    return vc, {(int(a), int(b)): int(c) for a, b, c in zip(u, v, ec)}
+
+
+@pytest.mark.parametrize("n", [3, 4, 7, 20])
+def test_participation_complete_graph(n):
+    vc, ec = part(n, complete(n))
+    assert (vc == math.comb(n - 1, 2)).all()
+    assert len(ec) == math.comb(n, 2) and set(ec.values()) == {n - 2}
+
+
+@pytest.mark.parametrize("k", [4, 5, 12])
+def test_participation_wheel_and_friendship(k):
+    wheel = [(0, i, 0) for i in range(1, k + 1)] + [(i, i % k + 1, 0) for i in range(1, k + 1)]
+    vc, ec = part(k + 1, wheel)
+    assert vc[0] == k and (vc[1:] == 2).all()
+    for (a, b), c in ec.items():
+        assert c == (2 if a == 0 else 1)
+    fr = []
+    for i in range(k):
+        a, b = 1 + 2 * i, 2 + 2 * i
+        fr += [(0, a, 0), (0, b, 0), (a, b, 0)]
+    vc, ec = part(2 * k + 1, fr)
+    assert vc[0] == k and (vc[1:] == 1).all() and set(ec.values()) == {1}
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_participation_against_brute_force(seed):
+    rng = np.random.default_rng(40 + seed)
+    n, L = int(rng.integers(30, 150)), 4
+    src, dst, ts, vlab = _random_graph(rng, n, int(rng.integers(n, 12 * n)), tbits=12, L=L)
+    window = None if seed % 2 == 0 else (500, 3500)
+    mask = None if seed < 2 else [0, 3, 7, 11, 19]
+    b = brute.survey(n, src, dst, ts, vlab, n_labels=L)
+    idx_of = brute.colex_multisets(L)
+    want_v = np.zeros(n, np.uint64)
+    want_e = {}
+    kept = 0
+    for a, bb, c, tab, tac, tbc in b["tris"]:
+        if window is not None and not all(window[0] <= x <= window[1] for x in (tab, tac, tbc)):
+            continue
+        if mask is not None and idx_of[tuple(sorted((int(vlab[a]), int(vlab[bb]), int(vlab[c]))))] not in mask:
+            continue
+        kept += 1
+        for x in (a, bb, c):
+            want_v[x] += 1
+        for e in ((a, bb), (a, c), (bb, c)):
+            want_e[e] = want_e.get(e, 0) + 1
+    vc, (u, v, t, ec) = oracle.participation(n, src, dst, ts, vlab, n_labels=L, window=window, label_mask=mask)
+    assert np.array_equal(vc, want_v)
+    got_e = {(int(a), int(bb)): int(c) for a, bb, c in zip(u, v, ec) if c}
+    assert got_e == want_e
+    # each triangle at v holds two of v's edges
+    half = np.zeros(n, np.uint64)
+    np.add.at(half, u, ec)
+    np.add.at(half, v, ec)
+    assert np.array_equal(half, 2 * vc)
+    assert vc.sum() == ec.sum() == 3 * kept
+
+
+def test_participation_sums_on_workload1():
+    w = synth.workload(1)
+    g = synth.generate(w.graph)
+    r = oracle.survey(g["n"], g["src"], g["dst"], g["ts"], g["vlab"], outputs=("count",), n_labels=4)
+    vc, (u, v, t, ec) = oracle.participation(g["n"], g["src"], g["dst"], g["ts"], g["vlab"], n_labels=4)
+    assert vc.sum() == ec.sum() == 3 * r["triangles"]
