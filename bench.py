@@ -48,7 +48,7 @@ def kernel_key(c: int, v: int, meta: bool) -> str:
     v = resolve_variant(c, v)
     log_slots, block, wave = {1: (6, 256, "true"), 2: (12, 1024, "false") if c == 2 else (10, 256, "false"),
                               3: (0, 256, "false"), 4: (0, 256, "true")}[v]
-    return "survey_kernel<%d,%d,%s,%s,false,false>" % (log_slots, block, wave, "true" if meta else "false")
+    return "survey_kernel<%d,%d,%s,%s,false,false,0>" % (log_slots, block, wave, "true" if meta else "false")
 
 
 def log(*a):

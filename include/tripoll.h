@@ -164,13 +164,29 @@ tp_status tripoll_graph_export(const tp_graph *g, uint64_t *rowptr, uint32_t *co
  *   LABEL_TABLE  label_table[C(c+2,3)+C(b+1,2)+a] += 1   (label-multiset survey)
  *   SPREAD_COUNT spread_count += (t3 - t1 < spread_lt)
  *   OPEN_CLOSE   open_close[32*bin(t2 - t1) + bin(t3 - t1)] += 1 (Algorithm 4, joint)
+ *   MAX_EDGE     if a, b, c are pairwise distinct:
+ *                max_edge[min(1023, t3 >> max_edge_shift)] += 1
+ *                (Algorithm 3: the distribution of the largest edge metadata
+ *                over triangles whose vertex labels all differ; the paper's
+ *                counting set of exact values is kept per 2^max_edge_shift
+ *                range of t3, exact when every t3 >> shift < 1024)
+ *   DEGREE_TABLE with x <= y <= z the values bin(d(v)) of the three vertices
+ *                (d the undirected degree of the cleaned graph):
+ *                degree_table[C(z+2,3)+C(y+1,2)+x] += 1
+ *                (the degree-metadata survey of the evaluation, which counts
+ *                triples of ceil(log2 d) of p, q, r; in the degree order
+ *                d(p) <= d(q) <= d(r), so that triple is already sorted)
  * with bin(D) = 0 for D <= 1 and min(31, ceil(log2 D)) otherwise, computed
- * exactly in integers.  The triangle count is always produced. */
+ * exactly in integers.  The triangle count is always produced.  MAX_EDGE and
+ * DEGREE_TABLE are produced by tripoll_survey and tripoll_survey_async only
+ * (batches and served requests return TP_ERR_UNSUPPORTED for them). */
 #define TP_OUT_COUNT 0x01u
 #define TP_OUT_CLOSE_HIST 0x02u
 #define TP_OUT_LABEL_TABLE 0x04u
 #define TP_OUT_SPREAD_COUNT 0x08u
 #define TP_OUT_OPEN_CLOSE 0x10u
+#define TP_OUT_MAX_EDGE 0x20u
+#define TP_OUT_DEGREE_TABLE 0x40u
 
 /* Prefilters applied before every reduction (the conditional of the
  * callbacks in Algorithms 3 and 4):
@@ -181,6 +197,8 @@ tp_status tripoll_graph_export(const tp_graph *g, uint64_t *rowptr, uint32_t *co
 
 #define TP_MAX_LABELS 16u
 #define TP_TABLE_MAX 816u /* C(16+2, 3) */
+#define TP_MAX_EDGE_BINS 1024u
+#define TP_DEGREE_MAX 5984u /* C(32+2, 3): three values in 0..31 */
 
 /* Intersection strategy (tests and tuning).  AUTO picks per target vertex. */
 #define TP_STRAT_AUTO 0u
@@ -210,6 +228,8 @@ typedef struct {
     uint64_t spread_lt;      /* SPREAD_COUNT threshold */
     uint64_t t_lo, t_hi;     /* WINDOW bounds, closed; t_lo <= t_hi */
     uint64_t label_mask[13]; /* LABEL_MASK bitset over multiset indices */
+    uint32_t max_edge_shift; /* MAX_EDGE bin width 2^max_edge_shift, 0..31 */
+    uint32_t reserved;       /* must be 0 */
 } tp_survey_spec;
 
 /* Host result.  Unrequested outputs are zero. */
@@ -220,6 +240,8 @@ typedef struct {
     uint64_t close_hist[32];
     uint64_t label_table[TP_TABLE_MAX];
     uint64_t open_close[32 * 32];
+    uint64_t max_edge[TP_MAX_EDGE_BINS];
+    uint64_t degree_table[TP_DEGREE_MAX];
     float kernel_ms;         /* device time of the intersection kernels */
     float total_ms;          /* device time of the whole survey call */
     float class_ms[TP_NUM_CLASSES]; /* device time of the kernel of each target class */
@@ -234,7 +256,9 @@ typedef struct {
 #define TP_RW_HIST 3u
 #define TP_RW_TABLE (TP_RW_HIST + 32u)
 #define TP_RW_OPEN_CLOSE (TP_RW_TABLE + TP_TABLE_MAX)
-#define TP_RW_SCRATCH (TP_RW_OPEN_CLOSE + 1024u)
+#define TP_RW_MAX_EDGE (TP_RW_OPEN_CLOSE + 1024u)
+#define TP_RW_DEGREE (TP_RW_MAX_EDGE + TP_MAX_EDGE_BINS)
+#define TP_RW_SCRATCH (TP_RW_DEGREE + TP_DEGREE_MAX)
 #define TP_RW_SCRATCH_WORDS 4u
 #define TP_RESULT_WORDS (TP_RW_SCRATCH + TP_RW_SCRATCH_WORDS)
 
@@ -242,7 +266,9 @@ typedef struct {
  * Survey a graph (Algorithm 1 with the reductions above).  Synchronous: the
  * result is on the host when it returns.
  * Errors: TP_ERR_INVALID for NULL arguments, n_labels outside 1..16, a graph
- * label >= n_labels when labels are used, or t_lo > t_hi; TP_ERR_DEVICE.
+ * label >= n_labels when labels are used, t_lo > t_hi, max_edge_shift > 31
+ * or reserved != 0; TP_ERR_UNSUPPORTED for MAX_EDGE or DEGREE_TABLE on a
+ * batch; TP_ERR_DEVICE.
  */
 tp_status tripoll_survey(const tp_graph *g, const tp_survey_spec *spec, tp_survey_result *out,
                          void *stream);
@@ -267,6 +293,26 @@ tp_status tripoll_survey_async(const tp_graph *g, const tp_survey_spec *spec, ui
  */
 tp_status tripoll_enumerate(const tp_graph *g, uint32_t *dev_records, uint64_t capacity,
                             uint64_t *n_found, void *stream);
+
+/*
+ * Local participation counts (Introduction; the Triangle Counting
+ * subsection of the evaluation: the per-vertex counts behind clustering
+ * coefficients and the per-edge counts behind truss decomposition).  For
+ * every triangle that passes the spec's prefilters (WINDOW, LABEL_MASK; the
+ * spec's outputs are ignored), one is added to the counter of each of its
+ * three vertices and each of its three edges.  Synchronous.
+ *   vertex_counts  device uint64[n_vertices] indexed by original vertex id,
+ *                  overwritten; or NULL
+ *   edge_counts    device uint64[n_edges] indexed by CSR slot of the oriented
+ *                  graph (tripoll_graph_export gives each slot's endpoints:
+ *                  row = rank of one end, col = rank of the other), overwritten;
+ *                  or NULL (then a temporary is allocated)
+ *   triangles      host; receives the number of triangles counted; or NULL
+ * The sums of both arrays are three times *triangles.
+ * Errors: as tripoll_survey; TP_ERR_UNSUPPORTED for a batch.
+ */
+tp_status tripoll_participation(const tp_graph *g, const tp_survey_spec *spec, uint64_t *vertex_counts,
+                                uint64_t *edge_counts, uint64_t *triangles, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Batches of independent graphs                                             */

@@ -101,77 +101,125 @@ __global__ void k_canon(const uint32_t *src, const uint32_t *dst, const uint32_t
 
 // ------------------------------------------------------------ phase 2
 
+// A block takes a tile of kCompTile consecutive sorted pairs and wave w the
+// tile's w-th part, 64 consecutive pairs at a time (lane l takes pair
+// 64 j + l), so that every load is coalesced; the unique pairs leave in the
+// same order.
 constexpr int kCompItems = 16;
 constexpr size_t kCompTile = (size_t)kB * kCompItems;
+constexpr size_t kCompWave = (size_t)kWave * kCompItems;
 
-__device__ __forceinline__ bool is_head(const uint64_t *keys, size_t i)
+// Is pair i the first of its run?  `k` is keys[i]; the previous key comes
+// from the lane below, or from memory for lane 0.
+__device__ __forceinline__ bool run_head(const uint64_t *keys, size_t i, size_t n, uint64_t k)
 {
-    return i == 0 || keys[i] != keys[i - 1];
+    uint64_t prev = __shfl_up(k, 1, kWave);
+    if (lane_id() == 0 && i < n) prev = i ? keys[i - 1] : ~k;
+    return i < n && prev != k;
+}
+
+// Unique pairs of this wave's part of the tile.
+__device__ __forceinline__ uint64_t wave_heads(const uint64_t *keys, size_t n, size_t wbase)
+{
+    uint64_t c = 0;
+    for (int j = 0; j < kCompItems; ++j) {
+        const size_t i = wbase + (size_t)j * kWave + lane_id();
+        const uint64_t k = i < n ? keys[i] : 0ull;
+        c += (uint64_t)__popcll(__ballot(run_head(keys, i, n, k)));
+    }
+    return c;
 }
 
 __global__ __launch_bounds__(kB) void k_dedup_count(const uint64_t *keys, size_t n, uint64_t *tile_cnt)
 {
     __shared__ uint64_t tmp[kB / kWave];
-    const size_t base = blockIdx.x * kCompTile + (size_t)threadIdx.x * kCompItems;
-    uint64_t c = 0;
-    for (int j = 0; j < kCompItems; ++j) {
-        const size_t i = base + j;
-        if (i < n && is_head(keys, i)) ++c;
+    const int w = threadIdx.x / kWave;
+    const uint64_t c = wave_heads(keys, n, blockIdx.x * kCompTile + (size_t)w * kCompWave);
+    if (lane_id() == 0) tmp[w] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int x = 0; x < kB / kWave; ++x) t += tmp[x];
+        tile_cnt[blockIdx.x] = t;
     }
-    uint64_t tot;
-    (void)block_excl_scan<kB>(c, tmp, tot);
-    if (threadIdx.x == 0) tile_cnt[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(kB) void k_dedup_write(const uint64_t *keys, const uint32_t *vals, size_t n,
                                                     const uint64_t *tile_off, uint64_t *ukey, uint32_t *uts)
 {
     __shared__ uint64_t tmp[kB / kWave];
-    const size_t base = blockIdx.x * kCompTile + (size_t)threadIdx.x * kCompItems;
-    uint64_t c = 0;
+    const int w = threadIdx.x / kWave;
+    const unsigned lane = lane_id();
+    const size_t wbase = blockIdx.x * kCompTile + (size_t)w * kCompWave;
+    const uint64_t c = wave_heads(keys, n, wbase);
+    if (lane == 0) tmp[w] = c;
+    __syncthreads();
+    uint64_t pos = tile_off[blockIdx.x];
+    for (int x = 0; x < w; ++x) pos += tmp[x];
     for (int j = 0; j < kCompItems; ++j) {
-        const size_t i = base + j;
-        if (i < n && is_head(keys, i)) ++c;
-    }
-    uint64_t tot;
-    uint64_t pos = tile_off[blockIdx.x] + block_excl_scan<kB>(c, tmp, tot);
-    for (int j = 0; j < kCompItems; ++j) {
-        const size_t i = base + j;
-        if (i < n && is_head(keys, i)) {
-            const uint64_t k = keys[i];
+        const size_t i = wbase + (size_t)j * kWave + lane;
+        const uint64_t k = i < n ? keys[i] : 0ull;
+        const bool head = run_head(keys, i, n, k);
+        const uint64_t b = __ballot(head);
+        if (head) {
+            // the earliest time of the run
             uint32_t t = vals[i];
             for (size_t x = i + 1; x < n && keys[x] == k; ++x) t = min(t, vals[x]);
-            ukey[pos] = k;
-            uts[pos] = t;
-            ++pos;
+            const uint64_t at = pos + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+            ukey[at] = k;
+            uts[at] = t;
         }
+        pos += (uint64_t)__popcll(b);
     }
 }
 
 // ------------------------------------------------------------ phase 3
 
-// d(v) over the unique pairs (sorted by lower endpoint): each wave adds one
-// count per run of equal lower endpoints, so hubs see few atomics.
-__global__ void k_degree(const uint64_t *ukey, size_t m, int nb, uint32_t *deg)
+// Add the lengths of the runs of equal values among a wave's 64 values
+// (sorted; lanes with ok == false form a suffix) to cnt[value]: one atomic
+// per run, to increasing addresses.
+__device__ __forceinline__ void add_runs(uint64_t v, bool ok, uint32_t *cnt)
 {
-    const uint64_t mask = (1ull << nb) - 1;
     const unsigned lane = lane_id();
+    const uint64_t prev = __shfl_up(v, 1, kWave);
+    const bool head = ok && (lane == 0 || prev != v);
+    const uint64_t heads = __ballot(head);
+    const uint32_t valid = (uint32_t)__popcll(__ballot(ok));
+    if (head) {
+        const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
+        const uint32_t next = above ? (uint32_t)__ffsll((long long)above) - 1 : valid;
+        atomicAdd(&cnt[v], next - lane);
+    }
+}
+
+// d(v) counts each unique pair at both ends.  The pairs are sorted by their
+// lower end, so that half is counted by runs; the higher ends are sorted on
+// their own first (k_high_ends, a 32-bit radix sort) and counted the same
+// way, instead of one scattered atomic per pair.
+__global__ void k_degree_low(const uint64_t *ukey, size_t m, int nb, uint32_t *deg)
+{
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t base = blockIdx.x * (size_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < m; base += stride) {
-        const size_t i = base + lane;
+        const size_t i = base + lane_id();
         const bool ok = i < m;
-        const uint64_t k = ok ? ukey[i] : ~0ull;
-        const uint64_t lo = k >> nb;
-        const uint64_t prev = __shfl_up(lo, 1, kWave);
-        const bool head = ok && (lane == 0 || prev != lo);
-        const uint64_t heads = __ballot(head);
-        const uint32_t valid = (uint32_t)__popcll(__ballot(ok));  // valid lanes are a prefix
-        if (head) {
-            const uint64_t above = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
-            const uint32_t next = above ? (uint32_t)__ffsll((long long)above) - 1 : valid;
-            atomicAdd(&deg[lo], next - lane);
-        }
-        if (ok) atomicAdd(&deg[k & mask], 1u);
+        add_runs(ok ? ukey[i] >> nb : ~0ull, ok, deg);
+    }
+}
+
+__global__ void k_high_ends(const uint64_t *ukey, size_t m, int nb, uint32_t *hi)
+{
+    const uint64_t mask = (1ull << nb) - 1;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x)
+        hi[i] = (uint32_t)(ukey[i] & mask);
+}
+
+__global__ void k_degree_runs(const uint32_t *v, size_t m, uint32_t *deg)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t base = blockIdx.x * (size_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < m; base += stride) {
+        const size_t i = base + lane_id();
+        const bool ok = i < m;
+        add_runs(ok ? v[i] : ~0ull, ok, deg);
     }
 }
 
@@ -235,6 +283,38 @@ __global__ void k_rank_scatter(const uint32_t *perm, uint32_t n, const uint8_t *
     }
 }
 
+// ceil(log2 d) for d >= 2 (the bit length of d - 1); 0 for d <= 1; cap 31
+__device__ __forceinline__ uint32_t degree_bin(uint32_t d)
+{
+    if (d <= 1) return 0;
+    const uint32_t b = 32u - (uint32_t)__clz(d - 1);
+    return b > 31 ? 31 : b;
+}
+
+// Ranks are in degree order, so the degree bins are ranges of ranks:
+// first[k] = the first rank whose bin is >= k (first[] is pre-filled with
+// 2^32 - 1 for bins above the largest).  Rank i writes the bins it opens.
+__global__ void k_dbin_rank(const uint32_t *deg, const uint32_t *perm, uint32_t n, uint32_t *first)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t b = degree_bin(deg[perm[i]]);
+        const int prev = i ? (int)degree_bin(deg[perm[i - 1]]) : -1;
+        for (int k = prev + 1; k <= (int)b; ++k) first[k] = (uint32_t)i;
+    }
+}
+
+// The same boundaries as CSR slots: rows are laid out by rank.
+__global__ void k_dbin_slot(const uint32_t *first, const uint64_t *rowptr, uint64_t *slot)
+{
+    const uint32_t k = threadIdx.x;
+    if (k < 32) slot[k] = first[k] == 0xffffffffu ? ~0ull : rowptr[first[k]];
+}
+
+__global__ void fill_u32(uint32_t *p, size_t n, uint32_t v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
 // graph id of every rank in a batch
 __global__ void k_rank_graph(const uint32_t *perm, uint32_t n, const uint32_t *voff, uint32_t n_graphs,
                              uint32_t *rank_gid)
@@ -246,7 +326,7 @@ __global__ void k_rank_graph(const uint32_t *perm, uint32_t n, const uint32_t *v
 // ------------------------------------------------------------ phase 4
 
 __global__ void k_orient(const uint64_t *ukey, const uint32_t *uts, size_t m, int nb, const uint32_t *rank,
-                         uint64_t *okey, uint32_t *ots, uint32_t *dplus)
+                         uint64_t *okey, uint32_t *ots)
 {
     const uint64_t mask = (1ull << nb) - 1;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
@@ -255,7 +335,18 @@ __global__ void k_orient(const uint64_t *ukey, const uint32_t *uts, size_t m, in
         const uint32_t s = min(a, b), t = max(a, b);
         okey[i] = pair_key(s, t, nb);
         ots[i] = uts[i];
-        atomicAdd(&dplus[s], 1u);
+    }
+}
+
+// d+(s) from the oriented pairs sorted by source: each wave adds one count
+// per run of equal sources among its 64 pairs, to increasing addresses.
+__global__ void k_dplus(const uint64_t *okey, size_t m, int nb, uint32_t *dplus)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t base = blockIdx.x * (size_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < m; base += stride) {
+        const size_t i = base + lane_id();
+        const bool ok = i < m;
+        add_runs(ok ? okey[i] >> nb : ~0ull, ok, dplus);
     }
 }
 
@@ -490,7 +581,8 @@ const T *to_device(const T *p, size_t n, uint32_t space, DArray<T> &hold, hipStr
 uint64_t graph_bytes(const tp_graph *g)
 {
     uint64_t b = g->rowptr.bytes() + g->col.bytes() + g->ets.bytes() + g->tlab.bytes() + g->rlab.bytes() +
-                 g->perm.bytes() + g->inkey.bytes() + g->inpay.bytes() + g->rank_gid.bytes();
+                 g->perm.bytes() + g->inkey.bytes() + g->inpay.bytes() + g->rank_gid.bytes() +
+                 g->dbin_rank.bytes() + g->dbin_slot.bytes();
     for (int c = 0; c < kNumClasses; ++c) b += g->tiles[c].bytes();
     return b;
 }
@@ -681,7 +773,15 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
         DArray<uint32_t> deg(n, s);
         TP_HIP(hipMemsetAsync(deg.get(), 0, n * sizeof(uint32_t), s));
         if (m) {
-            k_degree<<<grid_for(m, kB), kB, 0, s>>>(ukey, m, nb, deg.get());
+            k_degree_low<<<grid_for(m, kB), kB, 0, s>>>(ukey, m, nb, deg.get());
+            TP_CHECK_LAUNCH();
+            // the sorted (pre-dedup) pairs are no longer needed: their buffer
+            // holds the two halves of the higher-end sort
+            uint32_t *hiA = reinterpret_cast<uint32_t *>(skey), *hiB = hiA + Mcap;
+            k_high_ends<<<grid_for(m, kB), kB, 0, s>>>(ukey, m, nb, hiA);
+            TP_CHECK_LAUNCH();
+            const bool hb2 = radix_sort_u32(hiA, hiB, m, nb, s);
+            k_degree_runs<<<grid_for(m, kB), kB, 0, s>>>(hb2 ? hiB : hiA, m, deg.get());
             TP_CHECK_LAUNCH();
         }
         k_max<uint32_t><<<grid_for(n, kB), kB, 0, s>>>(deg.get(), n, c_dmax);
@@ -709,6 +809,17 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
         g->rlab.reset(n, s);
         k_rank_scatter<<<grid_for(n, kB), kB, 0, s>>>(g->perm.get(), n, vlab, rank.get(), g->rlab.get());
         TP_CHECK_LAUNCH();
+        if (!hb) {
+            // bins 0 .. bin(d_max) are in use
+            uint32_t top = 0;
+            for (uint64_t d = mx[0]; d > 1 && top < 31; ++top) d = (d + 1) / 2;
+            g->dbin_values = top + 1;
+            g->dbin_rank.reset(32, s);
+            fill_u32<<<1, 64, 0, s>>>(g->dbin_rank.get(), 32, 0xffffffffu);
+            TP_CHECK_LAUNCH();
+            k_dbin_rank<<<grid_for(n, kB), kB, 0, s>>>(deg.get(), g->perm.get(), n, g->dbin_rank.get());
+            TP_CHECK_LAUNCH();
+        }
         if (hb) {
             g->n_graphs = hb->n_graphs;
             g->rank_gid.reset(n, s);
@@ -724,7 +835,7 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
     DArray<uint32_t> dplus(n, s);
     TP_HIP(hipMemsetAsync(dplus.get(), 0, n * sizeof(uint32_t), s));
     if (m) {
-        k_orient<<<grid_for(m, kB), kB, 0, s>>>(ukey, uts, m, nb, rank.get(), skey, sval, dplus.get());
+        k_orient<<<grid_for(m, kB), kB, 0, s>>>(ukey, uts, m, nb, rank.get(), skey, sval);
         TP_CHECK_LAUNCH();
     }
     rank.release();
@@ -732,6 +843,10 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
     uint64_t *okey = ob ? ukey : skey;
     uint32_t *ots = ob ? uts : sval;
     uint32_t *spare_val = ob ? sval : uts;
+    if (m) {
+        k_dplus<<<grid_for(m, kB), kB, 0, s>>>(okey, m, nb, dplus.get());
+        TP_CHECK_LAUNCH();
+    }
     TP_HIP(hipEventRecord(ev[5], s));
 
     // ---- phase 5: CSR with co-located metadata
@@ -753,6 +868,11 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
     }
     k_row_stats<<<grid_for(n, kB), kB, 0, s>>>(g->rowptr.get(), n, c_wedge, c_dpmax);
     TP_CHECK_LAUNCH();
+    if (g->dbin_rank.get()) {
+        g->dbin_slot.reset(32, s);
+        k_dbin_slot<<<1, 64, 0, s>>>(g->dbin_rank.get(), g->rowptr.get(), g->dbin_slot.get());
+        TP_CHECK_LAUNCH();
+    }
     TP_HIP(hipEventRecord(ev[6], s));
 
     // ---- phase 6: in-edge index, a sort of the oriented edges by target

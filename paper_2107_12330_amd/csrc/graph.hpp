@@ -45,6 +45,11 @@ struct tp_graph {
     tp::DArray<uint64_t> inkey;   // [n_in] (q << kbits) | k, sorted by q
     tp::DArray<uint32_t> inpay;   // [n_in] rest of p's row after slot k | label(p) << 24
     tp::DArray<TileDesc> tiles[kNumClasses];
+    // degree bins (bin(d) = ceil(log2 d), 0 for d <= 1): ranks are in degree
+    // order, so each bin is a range of ranks and of CSR slots (single graphs)
+    uint32_t dbin_values = 0;          // bin(d_max) + 1
+    tp::DArray<uint32_t> dbin_rank;    // [32] first rank of bin >= k, or 2^32 - 1
+    tp::DArray<uint64_t> dbin_slot;    // [32] first CSR slot of a rank of bin >= k, or 2^64 - 1
     uint32_t n_graphs = 0;         // > 0 for a batch of disjoint graphs
     tp::DArray<uint32_t> rank_gid; // [n] graph of each rank (batches only)
     uint64_t n_tiles[kNumClasses] = {};

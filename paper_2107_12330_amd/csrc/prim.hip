@@ -246,7 +246,8 @@ constexpr unsigned kMaxSortBlocks = 2048;
 
 __device__ __forceinline__ unsigned digit_of(uint64_t k, int shift) { return (unsigned)(k >> shift) & 0xffu; }
 
-__global__ __launch_bounds__(kSortBlock) void radix_upsweep(const uint64_t *keys, size_t n, int shift,
+template <class K>
+__global__ __launch_bounds__(kSortBlock) void radix_upsweep(const K *keys, size_t n, int shift,
                                                             size_t tiles_per_block, uint64_t *hist)
 {
     __shared__ unsigned cnt[kRadix];
@@ -260,13 +261,15 @@ __global__ __launch_bounds__(kSortBlock) void radix_upsweep(const uint64_t *keys
     hist[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kSortBlock) void radix_downsweep(const uint64_t *keys_in, const uint32_t *vals_in,
-                                                              uint64_t *keys_out, uint32_t *vals_out, size_t n,
+// K: uint64_t or uint32_t keys; VALS: whether 32-bit values travel with them.
+template <class K, bool VALS>
+__global__ __launch_bounds__(kSortBlock) void radix_downsweep(const K *keys_in, const uint32_t *vals_in,
+                                                              K *keys_out, uint32_t *vals_out, size_t n,
                                                               int shift, size_t tiles_per_block,
                                                               const uint64_t *offsets)
 {
-    __shared__ uint64_t skey[kSortTile];
-    __shared__ uint32_t sval[kSortTile];
+    __shared__ K skey[kSortTile];
+    __shared__ uint32_t sval[VALS ? kSortTile : 1];
     __shared__ unsigned wcnt[kSortWaves][kRadix];  // per-wave running count, then per-wave base
     __shared__ unsigned tstart[kRadix];
     __shared__ unsigned tcount[kRadix];
@@ -287,7 +290,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_downsweep(const uint64_t *ke
         if (tile_lo >= n) break;
         const size_t wave_lo = tile_lo + (size_t)w * (kSortTile / kSortWaves);
 
-        uint64_t k[kSortRounds];
+        K k[kSortRounds];
         uint32_t v[kSortRounds];
         unsigned rnk[kSortRounds];
         unsigned dg[kSortRounds];
@@ -297,7 +300,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_downsweep(const uint64_t *ke
             const size_t i = wave_lo + (size_t)r * kWave + lane;
             ok[r] = i < n;
             k[r] = ok[r] ? keys_in[i] : 0;
-            v[r] = (ok[r] && vals_in) ? vals_in[i] : 0;
+            v[r] = (VALS && ok[r]) ? vals_in[i] : 0;
             dg[r] = digit_of(k[r], shift);
         }
         // stable rank of every key among equal digits of this wave's quarter
@@ -339,17 +342,17 @@ __global__ __launch_bounds__(kSortBlock) void radix_downsweep(const uint64_t *ke
             if (ok[r]) {
                 const unsigned pos = tstart[dg[r]] + wcnt[w][dg[r]] + rnk[r];
                 skey[pos] = k[r];
-                sval[pos] = v[r];
+                if (VALS) sval[pos] = v[r];
             }
         }
         __syncthreads();
         const unsigned valid = (unsigned)std::min<size_t>(kSortTile, n - tile_lo);
         for (unsigned i = threadIdx.x; i < valid; i += kSortBlock) {
-            const uint64_t key = skey[i];
+            const K key = skey[i];
             const unsigned d = digit_of(key, shift);
             const uint64_t dst = grun[d] + (i - tstart[d]);
             keys_out[dst] = key;
-            if (vals_out) vals_out[dst] = sval[i];
+            if (VALS) vals_out[dst] = sval[i];
         }
         __syncthreads();
         grun[threadIdx.x] += tcount[threadIdx.x];
@@ -358,10 +361,9 @@ __global__ __launch_bounds__(kSortBlock) void radix_downsweep(const uint64_t *ke
     }
 }
 
-}  // namespace
-
-bool radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, size_t n, int bits,
-                      hipStream_t s, int begin_bit)
+template <class K>
+bool radix_sort(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, size_t n, int bits, hipStream_t s,
+                int begin_bit)
 {
     if (n <= 1 || bits <= 0) return false;
     const size_t tiles = (n + kSortTile - 1) / kSortTile;
@@ -370,19 +372,34 @@ bool radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32
     DArray<uint64_t> hist((size_t)kRadix * nb, s);
     bool in_alt = false;
     for (int shift = begin_bit; shift < begin_bit + bits; shift += 8) {
-        const uint64_t *ki = in_alt ? keys_alt : keys;
+        const K *ki = in_alt ? keys_alt : keys;
         const uint32_t *vi = in_alt ? vals_alt : vals;
-        uint64_t *ko = in_alt ? keys : keys_alt;
+        K *ko = in_alt ? keys : keys_alt;
         uint32_t *vo = in_alt ? vals : vals_alt;
-        radix_upsweep<<<nb, kSortBlock, 0, s>>>(ki, n, shift, tpb, hist.get());
+        radix_upsweep<K><<<nb, kSortBlock, 0, s>>>(ki, n, shift, tpb, hist.get());
         TP_CHECK_LAUNCH();
         scan_u64(hist.get(), hist.get(), (size_t)kRadix * nb, false, s);
-        radix_downsweep<<<nb, kSortBlock, 0, s>>>(ki, vals ? vi : nullptr, ko, vals ? vo : nullptr, n, shift, tpb,
-                                                  hist.get());
+        if (vals)
+            radix_downsweep<K, true><<<nb, kSortBlock, 0, s>>>(ki, vi, ko, vo, n, shift, tpb, hist.get());
+        else
+            radix_downsweep<K, false><<<nb, kSortBlock, 0, s>>>(ki, nullptr, ko, nullptr, n, shift, tpb, hist.get());
         TP_CHECK_LAUNCH();
         in_alt = !in_alt;
     }
     return in_alt;
+}
+
+}  // namespace
+
+bool radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, size_t n, int bits,
+                      hipStream_t s, int begin_bit)
+{
+    return radix_sort<uint64_t>(keys, vals, keys_alt, vals_alt, n, bits, s, begin_bit);
+}
+
+bool radix_sort_u32(uint32_t *keys, uint32_t *keys_alt, size_t n, int bits, hipStream_t s, int begin_bit)
+{
+    return radix_sort<uint32_t>(keys, nullptr, keys_alt, nullptr, n, bits, s, begin_bit);
 }
 
 }  // namespace tp

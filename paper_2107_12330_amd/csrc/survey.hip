@@ -53,6 +53,10 @@ constexpr uint32_t kRing = 128;    // per-wave ring of queued hits: slot|label(p
 constexpr uint64_t kChunk = 4;     // tiles claimed at a time by a workgroup
 constexpr int kRsrcWord3 = 0x00020000;  // buffer resource word 3 for raw 32-bit loads on CDNA
 constexpr uint32_t kEmpty = 0xffffffffu;
+// kernel forms (see survey_kernel)
+constexpr int kFormSurvey = 0;
+constexpr int kFormExt = 1;
+constexpr int kFormPart = 2;
 constexpr uint32_t kMaxKicks = 64;  // cuckoo displacements before a key goes to the stash
 
 // The two cuckoo hash functions, each onto 2^log_s slots: the low bits of
@@ -83,10 +87,16 @@ struct SurveyParams {
     unsigned long long *out;  // result words (one block per graph of a batch)
     const uint32_t *rank_gid; // graph of each rank (batches), or null
     uint32_t g_stride;        // words per graph block
-    uint32_t o_tri, o_spread, o_probes, o_hist, o_table, o_oc;  // word offsets in a block
+    uint32_t o_tri, o_spread, o_probes, o_hist, o_table, o_oc, o_maxe, o_deg;  // word offsets in a block
     uint32_t outputs, filters;
     uint32_t table_words;     // entries of the label table in LDS (0 if unused)
     uint32_t oc_words;        // 1024 if OPEN_CLOSE else 0
+    uint32_t maxe_words;      // 1024 if MAX_EDGE else 0
+    uint32_t deg_words;       // entries of the degree table in LDS (0 if unused)
+    uint32_t max_edge_shift;  // MAX_EDGE bin width 2^max_edge_shift
+    unsigned long long *part_edge;  // participation: one counter per CSR slot
+    const uint32_t *dbin_rank;  // [32] first rank of degree bin >= k (DEGREE_TABLE)
+    const uint64_t *dbin_slot;  // [32] first CSR slot of a rank of degree bin >= k
     uint32_t t_lo32, t_hi32;  // window, clamped to the uint32 time range
     uint32_t spread_le;       // spread counter: close <= spread_le ...
     uint32_t spread_any;      // ... and spread_lt > 0
@@ -107,17 +117,18 @@ struct SurveyParams {
     uint32_t grid_eighths;    // share of the device the persistent grid may fill (0 or 8: all)
 };
 
-// LDS layout (dynamic): [hash keys][hash times][hash labels][hit rings]
-// [counters][label lut].
+// LDS layout (dynamic): [hash keys][hash times][hash labels]
+// [row positions][slot counts][hit rings][counters][label lut].  Positions
+// and slot counts exist in the participation form only, which has no rings.
 struct LdsLayout {
     uint32_t slots;
-    size_t off_hts, off_hlab, off_ring, off_cnt, off_lut, total;
+    size_t off_hts, off_hlab, off_hpos, off_hcnt, off_ring, off_cnt, off_lut, total;
 };
 
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 __host__ __device__ inline LdsLayout lds_layout(uint32_t slots, bool meta, uint32_t counter_words, int waves,
-                                                uint32_t lut_shift)
+                                                uint32_t lut_shift, bool part = false)
 {
     LdsLayout L;
     L.slots = slots;
@@ -127,8 +138,12 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t slots, bool meta, uint3
     L.off_hlab = o;
     if (meta) o += slots;
     o = align_up(o, 16);
+    L.off_hpos = o;
+    if (part) o += (size_t)slots * 4;
+    L.off_hcnt = o;
+    if (part) o += (size_t)slots * 4;
     L.off_ring = o;
-    if (meta) o += (size_t)waves * kRing * 16;
+    if (meta && !part) o += (size_t)waves * kRing * 16;
     L.off_cnt = o;
     o += (size_t)counter_words * 8;
     L.off_lut = o;
@@ -137,9 +152,14 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t slots, bool meta, uint3
     return L;
 }
 
-__host__ __device__ inline uint32_t counter_words(uint32_t table_words, uint32_t oc_words)
+// Counters of a workgroup: [close hist 32][label table][open/close]
+// [max-edge bins][degree table]; the last two in the extended form only.
+// A multi-request pass holds one batch-layout block per request slot.
+template <bool MULTI, int FORM>
+__host__ __device__ inline uint32_t counter_words(const SurveyParams &P)
 {
-    return 32 + table_words + oc_words;
+    if (MULTI) return P.n_slots * P.slot_words;
+    return 32 + P.table_words + P.oc_words + (FORM == kFormExt ? P.maxe_words + P.deg_words : 0u);
 }
 
 __device__ __forceinline__ uint32_t close_bin(uint32_t d)
@@ -162,11 +182,32 @@ __device__ __forceinline__ uint32_t multiset_index(uint32_t a, uint32_t b, uint3
 struct Hit {
     uint32_t t_pq, t_pr, t_qr;
     uint32_t l_p, l_q, l_r;
+    uint32_t b_p, b_q, b_r;  // degree bins (DEGREE_TABLE only)
 };
 
 // Reduce one triangle into the workgroup's counters.  Returns 1 if it passed
 // the filters.  `lut` maps the labels (a, b, c), packed in lut_shift-bit
 // fields, to the label-multiset index.
+// The prefilters alone: the window on the three times and the label-mask
+// bit of the multiset (labels must be below 2^lut_shift when it is used).
+__device__ __forceinline__ bool passes_filters(const SurveyParams &P, const Hit &h, const uint64_t *mask_lds,
+                                               const uint16_t *lut)
+{
+    const uint32_t f = P.filters;
+    if (f & TP_FILT_WINDOW) {
+        if (P.window_empty) return false;
+        if (h.t_pq < P.t_lo32 || h.t_pq > P.t_hi32 || h.t_pr < P.t_lo32 || h.t_pr > P.t_hi32 ||
+            h.t_qr < P.t_lo32 || h.t_qr > P.t_hi32)
+            return false;
+    }
+    if (f & TP_FILT_LABEL_MASK) {
+        const uint32_t idx = lut[(((h.l_p << P.lut_shift) | h.l_q) << P.lut_shift) | h.l_r];
+        if (!((mask_lds[idx >> 6] >> (idx & 63)) & 1ull)) return false;
+    }
+    return true;
+}
+
+template <bool EXT>
 __device__ __forceinline__ uint32_t reduce_hit(const SurveyParams &P, const Hit &h, unsigned long long *cnt,
                                                const uint64_t *mask_lds, const uint16_t *lut, uint32_t &spread)
 {
@@ -193,7 +234,25 @@ __device__ __forceinline__ uint32_t reduce_hit(const SurveyParams &P, const Hit 
         const uint32_t t2 = h.t_pq + h.t_pr + h.t_qr - t1 - t3;  // exact in uint32 arithmetic mod 2^32
         atomicAdd(&cnt[32 + P.table_words + close_bin(t2 - t1) * 32 + close_bin(close)], 1ull);
     }
+    if (EXT && (P.outputs & TP_OUT_MAX_EDGE)) {
+        // Algorithm 3: vertex labels pairwise distinct; bin of the largest edge time
+        if (h.l_p != h.l_q && h.l_q != h.l_r && h.l_p != h.l_r)
+            atomicAdd(&cnt[32 + P.table_words + P.oc_words + min(t3 >> P.max_edge_shift, 1023u)], 1ull);
+    }
+    if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE))
+        atomicAdd(&cnt[32 + P.table_words + P.oc_words + P.maxe_words + multiset_index(h.b_p, h.b_q, h.b_r)], 1ull);
     return 1;
+}
+
+// Degree bin of rank x: the largest k with first[k] <= x (first[0] = 0 and
+// first[] is non-decreasing, 32 entries).
+__device__ __forceinline__ uint32_t degree_bin_of(const uint32_t *first, uint32_t x)
+{
+    uint32_t b = 0;
+#pragma unroll
+    for (uint32_t step = 16; step; step >>= 1)
+        if (first[b + step] <= x) b += step;
+    return b;
 }
 
 // Reduce one hit per lane (lanes with valid == false hold none) into the
@@ -288,7 +347,11 @@ struct RecBlock {
 // pivot's row (lane i takes candidate i), so every address is a wave-uniform
 // base plus the lane.  Hits go to a per-wave ring in LDS and are reduced 64
 // at a time.
-template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI>
+// FORM: kFormSurvey for the reductions above; kFormExt adds the extended
+// reductions (max-edge bins, degree table), compiled into their own kernels
+// so that the others keep their register budget; kFormPart counts the
+// triangles at every edge (local participation) instead of reducing them.
+template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM>
 __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
 {
     constexpr int kSub = Depth<WAVE>::kSub;
@@ -302,8 +365,11 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr uint32_t kSlots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
     static_assert(!MULTI || (META && !ENUM), "multi-request passes reduce metadata");
-    const uint32_t nc = MULTI ? P.n_slots * P.slot_words : counter_words(P.table_words, P.oc_words);
-    const LdsLayout L = lds_layout(kSlots * kGroups, META || ENUM, nc * kGroups, kWaves, P.lut_shift);
+    constexpr bool EXT = FORM == kFormExt;
+    constexpr bool PART = FORM == kFormPart;
+    static_assert(!(EXT || PART) || (META && !ENUM && !MULTI), "extended forms are single-request metadata surveys");
+    const uint32_t nc = counter_words<MULTI, FORM>(P);
+    const LdsLayout L = lds_layout(kSlots * kGroups, META || ENUM, nc * kGroups, kWaves, P.lut_shift, PART);
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
     const int grp = WAVE ? w : 0;     // this thread's group
@@ -312,10 +378,13 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     uint32_t *hkey = reinterpret_cast<uint32_t *>(lds) + (size_t)grp * kSlots;
     uint32_t *hts = reinterpret_cast<uint32_t *>(lds + L.off_hts) + (size_t)grp * kSlots;
     uint8_t *hlab = lds + L.off_hlab + (size_t)grp * kSlots;
+    uint32_t *hpos = reinterpret_cast<uint32_t *>(lds + L.off_hpos) + (size_t)grp * kSlots;  // PART
+    uint32_t *hcnt = reinterpret_cast<uint32_t *>(lds + L.off_hcnt) + (size_t)grp * kSlots;  // PART
     unsigned long long *cnt_all = reinterpret_cast<unsigned long long *>(lds + L.off_cnt);
     unsigned long long *cnt = cnt_all + (size_t)grp * nc;
     uint16_t *lut = reinterpret_cast<uint16_t *>(lds + L.off_lut);
     __shared__ uint64_t mask_lds[13];
+    __shared__ uint32_t dbin_lds[32];
     __shared__ SlotSpec slot_lds[MULTI ? kMaxSlots : 1];
     __shared__ unsigned long long s_tile;
     __shared__ uint32_t s_stash_g[kGroups], s_fail_g[kGroups];
@@ -337,6 +406,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     uint4 *ring = reinterpret_cast<uint4 *>(lds + L.off_ring) + (size_t)w * kRing;
     for (uint32_t i = tid; i < nc * kGroups; i += BLOCK) cnt_all[i] = 0;
     if (tid < 13) mask_lds[tid] = P.label_mask[tid];
+    if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE) && tid < 32) dbin_lds[tid] = P.dbin_rank[tid];
     if (MULTI) {
         const uint32_t *src = reinterpret_cast<const uint32_t *>(P.slots);
         uint32_t *dst = reinterpret_cast<uint32_t *>(slot_lds);
@@ -379,7 +449,10 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
             }
             if (i < 32) word = P.o_hist + i;
             else if (i < 32 + P.table_words) word = P.o_table + (i - 32);
-            else word = P.o_oc + (i - 32 - P.table_words);
+            else if (!EXT || i < 32 + P.table_words + P.oc_words) word = P.o_oc + (i - 32 - P.table_words);
+            else if (i < 32 + P.table_words + P.oc_words + P.maxe_words)
+                word = P.o_maxe + (i - 32 - P.table_words - P.oc_words);
+            else word = P.o_deg + (i - 32 - P.table_words - P.oc_words - P.maxe_words);
             atomicAdd(&blk[word], v);
             cnt[i] = 0;
         }
@@ -393,6 +466,10 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     uint32_t dq = 0, l_q = 0, log_s = 0;
     uint32_t n_stash = 0;  // keys in the stash
     bool gmode = LOG_SLOTS == 0;  // search Adj+(q) in HBM (huge targets, or a failed table)
+    // degree bin cursor of the pivots this wave walks: bin pb spans CSR slots [pb_lo, pb_hi)
+    uint32_t pb = 0;
+    uint64_t pb_lo = 0, pb_hi = ~0ull;
+    if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE)) pb_hi = sload(P.dbin_slot + 1);
 
     // reduce the hits queued in this wave's ring, one per lane; `gm` says
     // where Adj+^m(q) is (true: HBM) at compile time, so that the table path
@@ -400,7 +477,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     auto drain = [&](uint32_t count, auto gm) {
         constexpr bool G = decltype(gm)::value;
         uint32_t tri = 0, spread = 0;
-        Hit h{0, 0, 0, 0, 0, 0};
+        Hit h{0, 0, 0, 0, 0, 0, 0, 0, 0};
         const bool valid = lane < count;
         if (valid) {
             const uint4 e = ring[(qh + lane) & (kRing - 1)];
@@ -415,6 +492,13 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
             } else {
                 h.t_qr = P.ets[kq + where];
                 h.l_r = P.tlab[kq + where];
+            }
+            if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE)) {
+                // the ring's last word holds the pivot's degree bin
+                const uint32_t r = !G ? hkey[where] : P.col[kq + where];
+                h.b_p = e.w;
+                h.b_q = degree_bin_of(dbin_lds, cur_q);
+                h.b_r = degree_bin_of(dbin_lds, r);
             }
             if (ENUM) {
                 const uint32_t r = !G ? hkey[where] : P.col[kq + where];
@@ -433,7 +517,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 }
                 tri = 1;
             } else if (!MULTI) {
-                tri = reduce_hit(P, h, cnt, mask_lds, lut, spread);
+                tri = reduce_hit<EXT>(P, h, cnt, mask_lds, lut, spread);
             }
         }
         if (MULTI) reduce_multi(h, valid, cnt, slot_lds, P.n_slots, P.slot_words, lut, P.lut_shift, P.slot_labels);
@@ -445,6 +529,18 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
         if (qt == qh) return;
         if (gmode) drain(qt - qh, std::true_type{});
         else drain(qt - qh, std::false_type{});
+    };
+    // participation: add the table's per-slot counts of edges (q, r) into
+    // their CSR slots; every thread of the group calls it once the group is
+    // done with the table
+    auto flush_part = [&]() {
+        if (!PART || LOG_SLOTS == 0 || cur_q == 0xffffffffu || gmode) return;
+        const uint32_t top = (2u << log_s) + n_stash;
+        for (uint32_t h = gtid; h < top; h += kGroup) {
+            if (hkey[h] == kEmpty) continue;
+            const uint32_t c = hcnt[h];
+            if (c) atomicAdd(&P.part_edge[kq + hpos[h]], (unsigned long long)c);
+        }
     };
 
     for (;;) {
@@ -496,6 +592,10 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                     }
                 }
                 gsync();
+                if (PART) {
+                    flush_part();
+                    gsync();
+                }
                 cur_q = d.q;
                 kq = sload(P.rowptr + cur_q);
                 dq = (uint32_t)(sload(P.rowptr + cur_q + 1) - kq);
@@ -549,6 +649,10 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                             }
                             hts[h] = P.ets[kq + i];
                             hlab[h] = P.tlab[kq + i];
+                            if (PART) {
+                                hpos[h] = i;
+                                hcnt[h] = 0;
+                            }
                         }
                     }
                 }
@@ -595,6 +699,23 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                     r.t_pq = (META || ENUM) ? __builtin_amdgcn_readlane(blk_cur.t_pq, l) : 0;
                     r.l_p = (META || ENUM) ? pay >> 24 : 0;
                     r.p = 0;
+                    if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE)) {
+                        // degree bin of the pivot, from the slot of p -> q:
+                        // a wave meets its records in increasing slot order
+                        // within a tile, so the bin cursor mostly moves forward
+                        const uint64_t s0 = r.start - 1;
+                        if (s0 < pb_lo) {
+                            pb = 0;
+                            pb_lo = 0;
+                            pb_hi = sload(P.dbin_slot + 1);
+                        }
+                        while (s0 >= pb_hi) {
+                            ++pb;
+                            pb_lo = pb_hi;
+                            pb_hi = pb < 31 ? sload(P.dbin_slot + pb + 1) : ~0ull;
+                        }
+                        r.p = pb;
+                    }
                     if (ENUM) {
                         // the pivot owns the row that holds slot start - 1
                         uint32_t a = 0, b = P.n;  // rowptr[a] <= start - 1 < rowptr[b]
@@ -617,6 +738,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 // chunk's first slot
                 struct Chunk {
                     uint32_t n, t_pq, l_p, p;
+                    uint64_t base, spq;  // slot of the first candidate, and of p -> q (participation)
                 };
                 auto next_chunk = [&](Chunk &ch) -> uint64_t {
                     uint64_t base = 0;
@@ -626,6 +748,8 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                         ch.t_pq = rec.t_pq;
                         ch.l_p = rec.l_p;
                         ch.p = rec.p;
+                        ch.base = base;
+                        ch.spq = rec.start - 1;
                         wave_work += ch.n;
                         off += kChunkCand;
                         if (off >= rec.len) {
@@ -645,6 +769,8 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                         ch.t_pq = 0;
                         ch.l_p = 0;
                         ch.p = 0;
+                        ch.base = 0;
+                        ch.spq = 0;
                     }
                     return base;
                 };
@@ -707,6 +833,33 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                                 }
                             }
                             const uint64_t m = __ballot(hit) & live;
+                            if constexpr (PART) {
+                                // local participation: one count for each edge of
+                                // every triangle that passes the prefilters
+                                bool pass = (m >> lane) & 1ull;
+                                if (pass && P.filters) {
+                                    Hit h{chs[c].t_pq, tpr[c][sr], 0, chs[c].l_p, l_q, 0, 0, 0, 0};
+                                    if constexpr (!G) {
+                                        h.t_qr = hts[slot];
+                                        h.l_r = hlab[slot];
+                                    } else {
+                                        h.t_qr = P.ets[kq + slot];
+                                        h.l_r = P.tlab[kq + slot];
+                                    }
+                                    pass = passes_filters(P, h, mask_lds, lut);
+                                }
+                                const uint64_t pm = __ballot(pass);
+                                if (pass) {
+                                    atomicAdd(&P.part_edge[chs[c].base + (uint32_t)(sr * kWave) + lane], 1ull);  // (p, r)
+                                    if constexpr (!G) atomicAdd(&hcnt[slot], 1u);  // (q, r), per table slot
+                                    else atomicAdd(&P.part_edge[kq + slot], 1ull);
+                                }
+                                if (pm) {
+                                    if (lane == 0) atomicAdd(&P.part_edge[chs[c].spq], (unsigned long long)__popcll(pm));
+                                    wave_hits += (uint32_t)__popcll(pm);
+                                }
+                                continue;
+                            }
                             if (!META && !ENUM) {
                                 wave_hits += (uint32_t)__popcll(m);
                                 continue;
@@ -750,6 +903,10 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     }
 
     if (META || ENUM) drain_queued();
+    if (PART) {
+        gsync();
+        flush_part();
+    }
     // ---- merge this workgroup's counters into the result
     flush(cur_g);
 }
@@ -759,17 +916,57 @@ __global__ void zero_u64(unsigned long long *p, size_t n)
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
+// Vertex participation from edge participation: each triangle at v holds
+// two of v's edges, so twice v's count is the sum over its edges.  One
+// thread per row adds the row's counts to its source and each to its target.
+__global__ void k_part_rows(const uint64_t *rowptr, const uint32_t *col, uint32_t n, const unsigned long long *edge,
+                            unsigned long long *acc)
+{
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
+        unsigned long long sum = 0;
+        for (uint64_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+            const unsigned long long c = edge[e];
+            if (!c) continue;
+            sum += c;
+            atomicAdd(&acc[col[e]], c);
+        }
+        if (sum) atomicAdd(&acc[v], sum);
+    }
+}
+
+__global__ void k_part_vertex(const unsigned long long *acc, const uint32_t *perm, uint32_t n, uint64_t *out)
+{
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x)
+        out[perm[v]] = acc[v] / 2;
+}
+
 uint32_t table_size(uint32_t L) { return (L + 2) * (L + 1) * L / 6; }
 
-template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI = false>
+// Dynamic LDS a workgroup may take: 160 KiB per compute unit, less room for
+// the kernel's static arrays.
+constexpr size_t kLdsLimit = 160 * 1024 - 4096;
+
+template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM>
+size_t lds_need(const SurveyParams &P)
+{
+    constexpr uint32_t groups = WAVE ? BLOCK / kWave : 1;
+    const uint32_t slots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
+    const uint32_t nc = counter_words<MULTI, FORM>(P);
+    return lds_layout(slots * groups, META || ENUM, nc * groups, BLOCK / kWave, P.lut_shift, FORM == kFormPart).total;
+}
+
+template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM>
 void launch_class(const SurveyParams &P, hipStream_t s, int device)
 {
     if (P.n_tiles == 0) return;
     constexpr uint32_t groups = WAVE ? BLOCK / kWave : 1;
     const uint32_t slots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
-    const uint32_t nc = MULTI ? P.n_slots * P.slot_words : counter_words(P.table_words, P.oc_words);
-    const LdsLayout L = lds_layout(slots * groups, META || ENUM, nc * groups, BLOCK / kWave, P.lut_shift);
-    auto kern = survey_kernel<LOG_SLOTS, BLOCK, WAVE, META, ENUM, MULTI>;
+    const uint32_t nc = counter_words<MULTI, FORM>(P);
+    const LdsLayout L = lds_layout(slots * groups, META || ENUM, nc * groups, BLOCK / kWave, P.lut_shift,
+                                   FORM == kFormPart);
+    if (L.total > kLdsLimit)
+        fail(TP_ERR_UNSUPPORTED, "tripoll_survey: the requested outputs need more LDS than a workgroup may hold");
+    auto kern = survey_kernel<LOG_SLOTS, BLOCK, WAVE, META, ENUM, MULTI, FORM>;
     // attribute and occupancy queries run once per kernel, device and LDS
     // size, so that a survey recorded into a HIP graph issues launches only
     static std::mutex mu;
@@ -813,38 +1010,52 @@ uint32_t resolve_variant(const tp_graph *g, int c, uint32_t strategy)
     return TP_VAR_GROUP_TABLE;
 }
 
-template <bool META, bool ENUM, bool MULTI = false>
+template <bool META, bool ENUM, bool MULTI = false, int FORM = kFormSurvey>
 void launch_variant(int c, uint32_t v, const SurveyParams &P, hipStream_t s, int device)
 {
+    // a table variant whose tables and counters together overflow LDS (large
+    // degree tables) searches Adj+(q) in HBM instead
+    // (per-wave forms hold counters per wave, so they overflow first)
+    const bool wave_search_fits = lds_need<0, kSmallBlock, true, META, ENUM, MULTI, FORM>(P) <= kLdsLimit;
     switch (v) {
     case TP_VAR_WAVE_TABLE:
-        launch_class<kTinyLogSlots, kSmallBlock, true, META, ENUM, MULTI>(P, s, device);
+        if (lds_need<kTinyLogSlots, kSmallBlock, true, META, ENUM, MULTI, FORM>(P) <= kLdsLimit)
+            launch_class<kTinyLogSlots, kSmallBlock, true, META, ENUM, MULTI, FORM>(P, s, device);
+        else if (wave_search_fits)
+            launch_class<0, kSmallBlock, true, META, ENUM, MULTI, FORM>(P, s, device);
+        else
+            launch_class<0, kSmallBlock, false, META, ENUM, MULTI, FORM>(P, s, device);
         break;
     case TP_VAR_GROUP_TABLE:
-        if (c == kClassLarge)
-            launch_class<kLargeLogSlots, kLargeBlock, false, META, ENUM, MULTI>(P, s, device);
+        if (c == kClassLarge && lds_need<kLargeLogSlots, kLargeBlock, false, META, ENUM, MULTI, FORM>(P) <= kLdsLimit)
+            launch_class<kLargeLogSlots, kLargeBlock, false, META, ENUM, MULTI, FORM>(P, s, device);
+        else if (c != kClassLarge && lds_need<kSmallLogSlots, kSmallBlock, false, META, ENUM, MULTI, FORM>(P) <= kLdsLimit)
+            launch_class<kSmallLogSlots, kSmallBlock, false, META, ENUM, MULTI, FORM>(P, s, device);
         else
-            launch_class<kSmallLogSlots, kSmallBlock, false, META, ENUM, MULTI>(P, s, device);
+            launch_class<0, kSmallBlock, false, META, ENUM, MULTI, FORM>(P, s, device);
         break;
     case TP_VAR_WAVE_SEARCH:
-        launch_class<0, kSmallBlock, true, META, ENUM, MULTI>(P, s, device);
+        if (wave_search_fits)
+            launch_class<0, kSmallBlock, true, META, ENUM, MULTI, FORM>(P, s, device);
+        else
+            launch_class<0, kSmallBlock, false, META, ENUM, MULTI, FORM>(P, s, device);
         break;
     default:
-        launch_class<0, kSmallBlock, false, META, ENUM, MULTI>(P, s, device);
+        launch_class<0, kSmallBlock, false, META, ENUM, MULTI, FORM>(P, s, device);
         break;
     }
 }
 
 // Launch the target classes in turn.  `timers`, when given, holds one
 // EventTimer per class around its launch.
-template <bool META, bool ENUM>
+template <bool META, bool ENUM, int FORM = kFormSurvey>
 void launch_all(const tp_graph *g, SurveyParams P, uint32_t strategy, hipStream_t s, EventTimer *timers = nullptr)
 {
     for (int c = 0; c < kNumClasses; ++c) {
         P.tiles = g->tiles[c].get();
         P.n_tiles = g->n_tiles[c];
         if (timers) timers[c].start();
-        launch_variant<META, ENUM>(c, resolve_variant(g, c, strategy), P, s, g->device);
+        launch_variant<META, ENUM, false, FORM>(c, resolve_variant(g, c, strategy), P, s, g->device);
         if (timers) timers[c].stop();
     }
 }
@@ -853,8 +1064,13 @@ void validate_spec(const tp_graph *g, const tp_survey_spec *sp)
 {
     if (!g || !sp) fail(TP_ERR_INVALID, "tripoll_survey: NULL argument");
     const uint32_t known = TP_OUT_COUNT | TP_OUT_CLOSE_HIST | TP_OUT_LABEL_TABLE | TP_OUT_SPREAD_COUNT |
-                           TP_OUT_OPEN_CLOSE;
+                           TP_OUT_OPEN_CLOSE | TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE;
     if (sp->outputs & ~known) fail(TP_ERR_INVALID, "tripoll_survey: unknown output bits");
+    if (sp->reserved != 0) fail(TP_ERR_INVALID, "tripoll_survey: reserved field must be 0");
+    if ((sp->outputs & TP_OUT_MAX_EDGE) && sp->max_edge_shift > 31)
+        fail(TP_ERR_INVALID, "tripoll_survey: max_edge_shift must be in 0..31");
+    if ((sp->outputs & (TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE)) && g->n_graphs)
+        fail(TP_ERR_UNSUPPORTED, "tripoll_survey: max-edge and degree tables are not produced for batches");
     if (sp->filters & ~(TP_FILT_WINDOW | TP_FILT_LABEL_MASK)) fail(TP_ERR_INVALID, "tripoll_survey: unknown filter bits");
     if (sp->strategy > TP_STRAT_TABLE_STRESS) fail(TP_ERR_INVALID, "tripoll_survey: unknown strategy");
     const bool labels = (sp->outputs & TP_OUT_LABEL_TABLE) || (sp->filters & TP_FILT_LABEL_MASK);
@@ -891,10 +1107,18 @@ SurveyParams make_params(const tp_graph *g, const tp_survey_spec *sp, unsigned l
     P.o_hist = TP_RW_HIST;
     P.o_table = TP_RW_TABLE;
     P.o_oc = TP_RW_OPEN_CLOSE;
+    P.o_maxe = TP_RW_MAX_EDGE;
+    P.o_deg = TP_RW_DEGREE;
     P.outputs = sp->outputs | TP_OUT_COUNT;
     P.filters = sp->filters;
     P.table_words = (sp->outputs & TP_OUT_LABEL_TABLE) ? table_size(sp->n_labels) : 0;
     P.oc_words = (sp->outputs & TP_OUT_OPEN_CLOSE) ? 1024 : 0;
+    P.maxe_words = (sp->outputs & TP_OUT_MAX_EDGE) ? TP_MAX_EDGE_BINS : 0;
+    P.max_edge_shift = sp->max_edge_shift;
+    // the degree table needs only the bins up to bin(d_max)
+    P.deg_words = ((sp->outputs & TP_OUT_DEGREE_TABLE) && !g->n_graphs) ? table_size(g->dbin_values) : 0;
+    P.dbin_rank = g->dbin_rank.get();
+    P.dbin_slot = g->dbin_slot.get();
     // close < spread_lt  <=>  close <= spread_lt - 1 (close is a uint32)
     P.spread_any = sp->spread_lt > 0;
     P.spread_le = sp->spread_lt == 0 ? 0u : (uint32_t)std::min<uint64_t>(sp->spread_lt - 1, 0xffffffffull);
@@ -920,6 +1144,8 @@ bool needs_meta(const tp_survey_spec *sp)
     return (sp->outputs & ~TP_OUT_COUNT) != 0 || sp->filters != 0;
 }
 
+bool needs_ext(const tp_survey_spec *sp) { return (sp->outputs & (TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE)) != 0; }
+
 // Enqueue a whole survey into the caller's result buffer (which also holds
 // the tile counter).  Allocates nothing.
 template <bool ENUM>
@@ -935,6 +1161,8 @@ void survey_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned long l
         P.enum_cap = enum_cap;
         P.enum_count = dev_out + TP_RW_SCRATCH + 1;
         launch_all<true, true>(g, P, TP_STRAT_AUTO, s);
+    } else if (needs_ext(sp)) {
+        launch_all<true, false, kFormExt>(g, P, sp->strategy, s, timers);
     } else if (needs_meta(sp)) {
         launch_all<true, false>(g, P, sp->strategy, s, timers);
     } else {
@@ -956,6 +1184,8 @@ uint32_t graph_count(const tp_graph *g) { return g->n_graphs ? g->n_graphs : 1u;
 // `dev_out`, followed by the tile counter.  Allocates nothing.
 void survey_batch_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned long long *dev_out, hipStream_t s)
 {
+    if (sp->outputs & (TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE))
+        fail(TP_ERR_UNSUPPORTED, "tripoll_survey_batch: max-edge and degree tables have no place in a batch block");
     const uint32_t words = batch_words(sp);
     const uint64_t total = (uint64_t)graph_count(g) * words + TP_BATCH_SCRATCH_WORDS;
     zero_u64<<<grid_for(total, 256), 256, 0, s>>>(dev_out, total);
@@ -985,6 +1215,8 @@ void copy_result(const std::vector<unsigned long long> &h, tp_survey_result *out
     for (int i = 0; i < 32; ++i) out->close_hist[i] = h[TP_RW_HIST + i];
     for (uint32_t i = 0; i < TP_TABLE_MAX; ++i) out->label_table[i] = h[TP_RW_TABLE + i];
     for (int i = 0; i < 1024; ++i) out->open_close[i] = h[TP_RW_OPEN_CLOSE + i];
+    for (uint32_t i = 0; i < TP_MAX_EDGE_BINS; ++i) out->max_edge[i] = h[TP_RW_MAX_EDGE + i];
+    for (uint32_t i = 0; i < TP_DEGREE_MAX; ++i) out->degree_table[i] = h[TP_RW_DEGREE + i];
 }
 
 }  // namespace
@@ -1039,6 +1271,48 @@ extern "C" tp_status tripoll_enumerate(const tp_graph *g, uint32_t *dev_records,
         TP_HIP(hipMemcpyAsync(&found, res.get() + TP_RW_TRIANGLES, 8, hipMemcpyDeviceToHost, s));
         TP_HIP(hipStreamSynchronize(s));
         *n_found = found;
+    });
+}
+
+extern "C" tp_status tripoll_participation(const tp_graph *g, const tp_survey_spec *spec, uint64_t *vertex_counts,
+                                           uint64_t *edge_counts, uint64_t *triangles, void *stream)
+{
+    return guard([&] {
+        validate_spec(g, spec);
+        if (g->n_graphs) fail(TP_ERR_UNSUPPORTED, "tripoll_participation: not available for batches");
+        hipStream_t s = (hipStream_t)stream;
+        // the filters of the spec apply; its outputs do not
+        tp_survey_spec sp = *spec;
+        sp.outputs = TP_OUT_COUNT;
+        DArray<unsigned long long> res(TP_RESULT_WORDS, s);
+        zero_u64<<<grid_for(TP_RESULT_WORDS, 256), 256, 0, s>>>(res.get(), TP_RESULT_WORDS);
+        TP_CHECK_LAUNCH();
+        DArray<unsigned long long> own;
+        unsigned long long *edge = reinterpret_cast<unsigned long long *>(edge_counts);
+        if (!edge) {
+            own.reset(std::max<uint64_t>(g->m, 1), s);
+            edge = own.get();
+        }
+        if (g->m) {
+            zero_u64<<<grid_for(g->m, 256), 256, 0, s>>>(edge, g->m);
+            TP_CHECK_LAUNCH();
+        }
+        SurveyParams P = make_params(g, &sp, res.get(), res.get() + TP_RW_SCRATCH);
+        P.part_edge = edge;
+        if (g->m && g->n_in) launch_all<true, false, kFormPart>(g, P, sp.strategy, s);
+        if (vertex_counts) {
+            DArray<unsigned long long> acc(g->n, s);
+            zero_u64<<<grid_for(g->n, 256), 256, 0, s>>>(acc.get(), g->n);
+            TP_CHECK_LAUNCH();
+            k_part_rows<<<grid_for(g->n, 256), 256, 0, s>>>(g->rowptr.get(), g->col.get(), g->n, edge, acc.get());
+            TP_CHECK_LAUNCH();
+            k_part_vertex<<<grid_for(g->n, 256), 256, 0, s>>>(acc.get(), g->perm.get(), g->n, vertex_counts);
+            TP_CHECK_LAUNCH();
+        }
+        unsigned long long tri = 0;
+        TP_HIP(hipMemcpyAsync(&tri, res.get() + TP_RW_TRIANGLES, 8, hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+        if (triangles) *triangles = tri;
     });
 }
 
@@ -1233,7 +1507,9 @@ float time_class(const tp_graph *g, const tp_survey_spec *sp, unsigned long long
     for (int r = 0; r < reps; ++r) {
         EventTimer t(s);
         t.start();
-        if (needs_meta(sp))
+        if (needs_ext(sp))
+            launch_variant<true, false, false, kFormExt>(c, v, P, s, g->device);
+        else if (needs_meta(sp))
             launch_variant<true, false>(c, v, P, s, g->device);
         else
             launch_variant<false, false>(c, v, P, s, g->device);

@@ -215,6 +215,8 @@ void scan_u32_to_u64(const uint32_t *in, uint64_t *out, size_t n, hipStream_t s)
 // the same size.  Returns true when the result ended in the alt buffers.
 bool radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, size_t n,
                       int bits, hipStream_t s, int begin_bit = 0);
+// The same for 32-bit keys alone.
+bool radix_sort_u32(uint32_t *keys, uint32_t *keys_alt, size_t n, int bits, hipStream_t s, int begin_bit = 0);
 
 template <class T>
 void fill(T *p, T v, size_t n, hipStream_t s);

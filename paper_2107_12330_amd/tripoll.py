@@ -22,22 +22,28 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OOM", 3: "DEVICE", 4: "BUSY", 5: "UNS
 TP_MEM_HOST, TP_MEM_DEVICE = 0, 1
 TP_TIE_MIX, TP_TIE_ID = 0, 1
 TP_OUT_COUNT, TP_OUT_CLOSE_HIST, TP_OUT_LABEL_TABLE, TP_OUT_SPREAD_COUNT, TP_OUT_OPEN_CLOSE = 1, 2, 4, 8, 16
+TP_OUT_MAX_EDGE, TP_OUT_DEGREE_TABLE = 32, 64
 TP_FILT_WINDOW, TP_FILT_LABEL_MASK = 1, 2
 TP_STRAT_AUTO, TP_STRAT_GLOBAL_SEARCH, TP_STRAT_TABLE_STRESS = 0, 1, 2
 TP_VAR_DEFAULT, TP_VAR_WAVE_TABLE, TP_VAR_GROUP_TABLE, TP_VAR_SEARCH, TP_VAR_WAVE_SEARCH = 0, 1, 2, 3, 4
 TP_NUM_CLASSES = 4
 TP_MAX_LABELS = 16
 TP_TABLE_MAX = 816
+TP_MAX_EDGE_BINS = 1024
+TP_DEGREE_MAX = 5984
 TP_RW_TRIANGLES, TP_RW_SPREAD, TP_RW_PROBES, TP_RW_HIST = 0, 1, 2, 3
 TP_RW_TABLE = TP_RW_HIST + 32
 TP_RW_OPEN_CLOSE = TP_RW_TABLE + TP_TABLE_MAX
-TP_RW_SCRATCH = TP_RW_OPEN_CLOSE + 1024
+TP_RW_MAX_EDGE = TP_RW_OPEN_CLOSE + 1024
+TP_RW_DEGREE = TP_RW_MAX_EDGE + TP_MAX_EDGE_BINS
+TP_RW_SCRATCH = TP_RW_DEGREE + TP_DEGREE_MAX
 TP_RESULT_WORDS = TP_RW_SCRATCH + 4
 TP_BW_TRIANGLES, TP_BW_SPREAD, TP_BW_PROBES, TP_BW_HIST, TP_BW_TABLE = 0, 1, 2, 3, 35
 TP_BATCH_SCRATCH_WORDS = 4
 
 OUT_BITS = {"count": TP_OUT_COUNT, "close_hist": TP_OUT_CLOSE_HIST, "label_table": TP_OUT_LABEL_TABLE,
-            "spread_count": TP_OUT_SPREAD_COUNT, "open_close": TP_OUT_OPEN_CLOSE}
+            "spread_count": TP_OUT_SPREAD_COUNT, "open_close": TP_OUT_OPEN_CLOSE,
+            "max_edge": TP_OUT_MAX_EDGE, "degree_table": TP_OUT_DEGREE_TABLE}
 
 
 class tp_edge_list(ctypes.Structure):
@@ -67,13 +73,15 @@ class tp_graph_stats(ctypes.Structure):
 class tp_survey_spec(ctypes.Structure):
     _fields_ = [("outputs", ctypes.c_uint32), ("filters", ctypes.c_uint32), ("n_labels", ctypes.c_uint32),
                 ("strategy", ctypes.c_uint32), ("spread_lt", ctypes.c_uint64), ("t_lo", ctypes.c_uint64),
-                ("t_hi", ctypes.c_uint64), ("label_mask", ctypes.c_uint64 * 13)]
+                ("t_hi", ctypes.c_uint64), ("label_mask", ctypes.c_uint64 * 13),
+                ("max_edge_shift", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class tp_survey_result(ctypes.Structure):
     _fields_ = [("triangles", ctypes.c_uint64), ("spread_count", ctypes.c_uint64), ("probes", ctypes.c_uint64),
                 ("close_hist", ctypes.c_uint64 * 32), ("label_table", ctypes.c_uint64 * TP_TABLE_MAX),
-                ("open_close", ctypes.c_uint64 * 1024), ("kernel_ms", ctypes.c_float),
+                ("open_close", ctypes.c_uint64 * 1024), ("max_edge", ctypes.c_uint64 * TP_MAX_EDGE_BINS),
+                ("degree_table", ctypes.c_uint64 * TP_DEGREE_MAX), ("kernel_ms", ctypes.c_float),
                 ("total_ms", ctypes.c_float), ("class_ms", ctypes.c_float * TP_NUM_CLASSES)]
 
 
@@ -126,6 +134,8 @@ SIGNATURES = {
     "tripoll_survey": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), ctypes.POINTER(tp_survey_result), _P]),
     "tripoll_survey_async": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, _P]),
     "tripoll_enumerate": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64), _P]),
+    "tripoll_participation": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, _P,
+                                             ctypes.POINTER(ctypes.c_uint64), _P]),
     "tripoll_build_batch": (ctypes.c_int, [ctypes.POINTER(tp_batch_edges), _P, ctypes.POINTER(_P)]),
     "tripoll_graph_count": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32)]),
     "tripoll_batch_words": (ctypes.c_uint64, [ctypes.POINTER(tp_survey_spec)]),
@@ -226,6 +236,15 @@ def tripoll_graph_count(g: int) -> int:
     v = ctypes.c_uint32(0)
     _check(load().tripoll_graph_count(g, ctypes.byref(v)))
     return v.value
+
+
+def tripoll_participation(g: int, spec: tp_survey_spec, vertex_counts: int, edge_counts: int, stream=None) -> int:
+    """Per-vertex and per-edge triangle counts into device buffers (either
+    pointer may be 0); returns the number of triangles counted."""
+    tri = ctypes.c_uint64(0)
+    _check(load().tripoll_participation(g, ctypes.byref(spec), vertex_counts or None, edge_counts or None,
+                                        ctypes.byref(tri), stream))
+    return int(tri.value)
 
 
 def tripoll_batch_words(spec: tp_survey_spec) -> int:
@@ -342,12 +361,13 @@ def table_size(n_labels: int) -> int:
 
 
 def make_spec(outputs=("count",), n_labels=4, spread_lt=0, window=None, label_mask=None,
-              strategy=TP_STRAT_AUTO) -> tp_survey_spec:
+              strategy=TP_STRAT_AUTO, max_edge_shift=0) -> tp_survey_spec:
     sp = tp_survey_spec()
     sp.outputs = sum(OUT_BITS[o] for o in outputs)
     sp.n_labels = n_labels
     sp.strategy = strategy
     sp.spread_lt = spread_lt
+    sp.max_edge_shift = max_edge_shift
     if window is not None:
         sp.filters |= TP_FILT_WINDOW
         sp.t_lo, sp.t_hi = int(window[0]), int(window[1])
@@ -363,6 +383,8 @@ def result_dict(res: tp_survey_result, n_labels: int = 16) -> dict:
                 close_hist=np.frombuffer(bytes(res.close_hist), np.uint64).copy(),
                 label_table=np.frombuffer(bytes(res.label_table), np.uint64)[:table_size(n_labels)].copy(),
                 open_close=np.frombuffer(bytes(res.open_close), np.uint64).reshape(32, 32).copy(),
+                max_edge=np.frombuffer(bytes(res.max_edge), np.uint64).copy(),
+                degree_table=np.frombuffer(bytes(res.degree_table), np.uint64).copy(),
                 kernel_ms=float(res.kernel_ms), total_ms=float(res.total_ms),
                 class_ms=[float(x) for x in res.class_ms])
 
@@ -373,7 +395,9 @@ def words_dict(words: np.ndarray, n_labels: int = 16) -> dict:
     return dict(triangles=int(w[TP_RW_TRIANGLES]), spread_count=int(w[TP_RW_SPREAD]),
                 probes=int(w[TP_RW_PROBES]), close_hist=w[TP_RW_HIST:TP_RW_HIST + 32].copy(),
                 label_table=w[TP_RW_TABLE:TP_RW_TABLE + table_size(n_labels)].copy(),
-                open_close=w[TP_RW_OPEN_CLOSE:TP_RW_OPEN_CLOSE + 1024].reshape(32, 32).copy())
+                open_close=w[TP_RW_OPEN_CLOSE:TP_RW_OPEN_CLOSE + 1024].reshape(32, 32).copy(),
+                max_edge=w[TP_RW_MAX_EDGE:TP_RW_MAX_EDGE + TP_MAX_EDGE_BINS].copy(),
+                degree_table=w[TP_RW_DEGREE:TP_RW_DEGREE + TP_DEGREE_MAX].copy())
 
 
 def stats_dict(st: tp_graph_stats) -> dict:
