@@ -295,6 +295,30 @@ tp_status tripoll_enumerate(const tp_graph *g, uint32_t *dev_records, uint64_t c
                             uint64_t *n_found, void *stream);
 
 /*
+ * Streamed enumeration: every triangle exactly once, in chunks that never
+ * overflow the caller's buffer (the full-enumeration use of the callback,
+ * Introduction, with the caller draining the buffer between chunks).
+ * tripoll_enum_open counts the triangles of every tile of the survey plan
+ * (one pass), so that each tile's records have a known place; each
+ * tripoll_enum_next then writes the records of as many whole tiles as fit
+ * in `capacity`, in the record format of tripoll_enumerate, and sets
+ * *n_written (0 once every record was written).  The spec's prefilters
+ * apply; its outputs are ignored.  Calls on one stream object must not
+ * overlap; the graph must outlive it.
+ *   total     host; receives the number of records the stream will produce
+ *   max_tile  host; receives the records of the largest tile: a capacity of
+ *             at least this always makes progress
+ * Errors: TP_ERR_INVALID for bad arguments, or when `capacity` is below the
+ * next tile's records (nothing is written then); as tripoll_survey otherwise.
+ */
+typedef struct tp_enum_stream tp_enum_stream;
+tp_status tripoll_enum_open(const tp_graph *g, const tp_survey_spec *spec, void *stream, tp_enum_stream **out,
+                            uint64_t *total, uint64_t *max_tile);
+tp_status tripoll_enum_next(tp_enum_stream *e, uint32_t *dev_records, uint64_t capacity, uint64_t *n_written,
+                            void *stream);
+tp_status tripoll_enum_close(tp_enum_stream *e);
+
+/*
  * Local participation counts (Introduction; the Triangle Counting
  * subsection of the evaluation: the per-vertex counts behind clustering
  * coefficients and the per-edge counts behind truss decomposition).  For

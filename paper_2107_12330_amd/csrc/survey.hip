@@ -104,10 +104,17 @@ struct SurveyParams {
     uint32_t lut_shift;       // labels < 2^lut_shift index the multiset table (0 if unused)
     uint32_t max_kicks;       // cuckoo displacements per key before the stash
     uint64_t label_mask[13];
-    // enumeration
+    // enumeration: records go to enum_out[enum_count++] (at most enum_cap),
+    // or, streaming, tile t's records to enum_out[tile_base[t] - chunk_base +
+    // tile_cursor[t]++]; with tile_count set, records are only counted per tile
     uint32_t *enum_out;
     uint64_t enum_cap;
     unsigned long long *enum_count;
+    const uint64_t *enum_tile_base;
+    unsigned *enum_tile_cursor;
+    unsigned *enum_tile_count;
+    uint64_t enum_chunk_base;
+    uint64_t tile_gbase;      // index of tiles[0] among all tiles of the graph
     const uint32_t *perm;
     uint32_t n;
     // multi-request passes: per slot a result block of slot_words words
@@ -459,6 +466,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
         gsync();
     };
     uint32_t cur_g = 0;  // graph whose counters the workgroup holds
+    uint64_t cur_tile = 0;  // global index of the tile being walked (enumeration)
 
     // the target whose out-list is in the LDS table, and its geometry
     uint32_t cur_q = 0xffffffffu;
@@ -478,6 +486,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
         constexpr bool G = decltype(gm)::value;
         uint32_t tri = 0, spread = 0;
         Hit h{0, 0, 0, 0, 0, 0, 0, 0, 0};
+        uint32_t e_p = 0, e_r = 0;  // ranks of p and r (enumeration)
         const bool valid = lane < count;
         if (valid) {
             const uint4 e = ring[(qh + lane) & (kRing - 1)];
@@ -501,13 +510,35 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 h.b_r = degree_bin_of(dbin_lds, r);
             }
             if (ENUM) {
-                const uint32_t r = !G ? hkey[where] : P.col[kq + where];
-                const unsigned long long at = atomicAdd(P.enum_count, 1ull);
-                if (at < P.enum_cap) {
+                e_r = !G ? hkey[where] : P.col[kq + where];
+                e_p = e.w;
+            } else if (!MULTI) {
+                tri = reduce_hit<EXT>(P, h, cnt, mask_lds, lut, spread);
+            }
+        }
+        if (ENUM) {
+            // the wave's records that pass the prefilters take consecutive
+            // places, claimed with one atomic
+            const bool pass = valid && (!P.filters || passes_filters(P, h, mask_lds, lut));
+            const uint64_t vm = __ballot(pass);
+            if (vm) {
+                const unsigned k = (unsigned)__popcll(vm);
+                unsigned long long base = 0;
+                if (lane == 0) {
+                    if (P.enum_tile_count) atomicAdd(&P.enum_tile_count[cur_tile], k);
+                    else if (P.enum_tile_base)
+                        base = P.enum_tile_base[cur_tile] - P.enum_chunk_base + atomicAdd(&P.enum_tile_cursor[cur_tile], k);
+                    else base = atomicAdd(P.enum_count, (unsigned long long)k);
+                }
+                base = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
+                       __builtin_amdgcn_readfirstlane((uint32_t)base);
+                const unsigned long long at =
+                    base + __builtin_amdgcn_mbcnt_hi((uint32_t)(vm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)vm, 0u));
+                if (pass && !P.enum_tile_count && at < P.enum_cap) {
                     uint32_t *o = P.enum_out + at * 9;
-                    o[0] = P.perm[e.w];
+                    o[0] = P.perm[e_p];
                     o[1] = P.perm[cur_q];
-                    o[2] = P.perm[r];
+                    o[2] = P.perm[e_r];
                     o[3] = h.t_pq;
                     o[4] = h.t_pr;
                     o[5] = h.t_qr;
@@ -515,10 +546,8 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                     o[7] = h.l_q;
                     o[8] = h.l_r;
                 }
-                tri = 1;
-            } else if (!MULTI) {
-                tri = reduce_hit<EXT>(P, h, cnt, mask_lds, lut, spread);
             }
+            tri = pass ? 1u : 0u;
         }
         if (MULTI) reduce_multi(h, valid, cnt, slot_lds, P.n_slots, P.slot_words, lut, P.lut_shift, P.slot_labels);
         my_tri += tri;
@@ -563,6 +592,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
         const uint64_t t_end = min(t_begin + kClaim, P.n_tiles);
         for (uint64_t ti = t_begin; ti < t_end; ++ti) {
             const TileDesc d = sload(P.tiles + (P.n_tiles - 1 - ti));
+            if (ENUM) cur_tile = P.tile_gbase + (P.n_tiles - 1 - ti);
             // this wave's records: tile records wl, wl + kW, wl + 2kW, ...;
             // lane l of block b holds record 64b + l.  The first two blocks
             // are requested before the table is rebuilt, so that their
@@ -899,6 +929,9 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
             };
             if (gmode) walk(std::true_type{});
             else walk(std::false_type{});
+            // a streamed or counted enumeration places records by tile: the
+            // ring must not carry them into the next tile
+            if (ENUM && (P.enum_tile_base || P.enum_tile_count)) drain_queued();
         }
     }
 
@@ -914,6 +947,34 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
 __global__ void zero_u64(unsigned long long *p, size_t n)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// Largest of n uint32 values into *out (zeroed by the caller).
+__global__ void k_max_u32(const unsigned *x, size_t n, unsigned long long *out)
+{
+    unsigned long long mx = 0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        mx = max(mx, (unsigned long long)x[i]);
+    mx = wave_max(mx);
+    if (lane_id() == 0 && mx) atomicMax(out, mx);
+}
+
+// The next chunk of a streamed enumeration: the largest t1 > t0 with
+// base[t1] - base[t0] <= cap (t0 itself when even one tile does not fit).
+// Writes t1, base[t0], base[t1].
+__global__ void k_enum_chunk(const uint64_t *base, uint64_t n_tiles, uint64_t t0, uint64_t cap, uint64_t *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint64_t b0 = base[t0];
+    uint64_t lo = t0, hi = n_tiles;  // base[lo] - b0 <= cap; find the last such index
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo + 1) / 2;
+        if (base[mid] - b0 <= cap) lo = mid;
+        else hi = mid - 1;
+    }
+    out[0] = lo;
+    out[1] = b0;
+    out[2] = base[lo];
 }
 
 // Vertex participation from edge participation: each triangle at v holds
@@ -1272,6 +1333,136 @@ extern "C" tp_status tripoll_enumerate(const tp_graph *g, uint32_t *dev_records,
         TP_HIP(hipStreamSynchronize(s));
         *n_found = found;
     });
+}
+
+struct tp_enum_stream {
+    const tp_graph *g = nullptr;
+    tp_survey_spec spec{};
+    uint64_t n_tiles = 0, next = 0, total = 0, max_tile = 0, emitted = 0;
+    uint64_t class_first[kNumClasses + 1] = {};  // first global tile of each class
+    DArray<uint64_t> base;       // [n_tiles + 1] first record of each tile
+    DArray<unsigned> cursor;     // [n_tiles] records written per tile
+    DArray<unsigned long long> res;
+    DArray<uint64_t> chunk;      // [3] result of k_enum_chunk
+};
+
+namespace {
+
+// Launch the enumeration form over global tiles [t0, t1), class by class.
+void enum_tiles(tp_enum_stream *e, SurveyParams P, uint64_t t0, uint64_t t1, hipStream_t s)
+{
+    const tp_graph *g = e->g;
+    for (int c = 0; c < kNumClasses; ++c) {
+        const uint64_t lo = std::max(t0, e->class_first[c]), hi = std::min(t1, e->class_first[c + 1]);
+        if (lo >= hi) continue;
+        P.tiles = g->tiles[c].get() + (lo - e->class_first[c]);
+        P.n_tiles = hi - lo;
+        P.tile_gbase = lo;
+        launch_variant<true, true>(c, resolve_variant(g, c, TP_STRAT_AUTO), P, s, g->device);
+    }
+}
+
+}  // namespace
+
+extern "C" tp_status tripoll_enum_open(const tp_graph *g, const tp_survey_spec *spec, void *stream,
+                                       tp_enum_stream **out, uint64_t *total, uint64_t *max_tile)
+{
+    return guard([&] {
+        if (!out) fail(TP_ERR_INVALID, "tripoll_enum_open: NULL output");
+        validate_spec(g, spec);
+        hipStream_t s = (hipStream_t)stream;
+        auto e = std::make_unique<tp_enum_stream>();
+        e->g = g;
+        e->spec = *spec;
+        e->spec.outputs = TP_OUT_COUNT;
+        for (int c = 0; c < kNumClasses; ++c) e->class_first[c + 1] = e->class_first[c] + g->n_tiles[c];
+        e->n_tiles = e->class_first[kNumClasses];
+        const uint64_t T = e->n_tiles;
+        e->base.reset(T + 1, s);
+        e->cursor.reset(std::max<uint64_t>(T, 1), s);
+        e->res.reset(TP_RESULT_WORDS, s);
+        e->chunk.reset(3, s);
+        DArray<unsigned> count(std::max<uint64_t>(T, 1), s);
+        zero_u64<<<grid_for(TP_RESULT_WORDS, 256), 256, 0, s>>>(e->res.get(), TP_RESULT_WORDS);
+        TP_CHECK_LAUNCH();
+        TP_HIP(hipMemsetAsync(count.get(), 0, std::max<uint64_t>(T, 1) * sizeof(unsigned), s));
+        TP_HIP(hipMemsetAsync(e->cursor.get(), 0, std::max<uint64_t>(T, 1) * sizeof(unsigned), s));
+        if (T && g->m && g->n_in) {
+            // one counting pass: the records of every tile
+            SurveyParams P = make_params(g, &e->spec, e->res.get(), e->res.get() + TP_RW_SCRATCH);
+            P.enum_tile_count = count.get();
+            enum_tiles(e.get(), P, 0, T, s);
+        }
+        if (T) scan_u32_to_u64(count.get(), e->base.get(), T, s);
+        else TP_HIP(hipMemsetAsync(e->base.get(), 0, sizeof(uint64_t), s));
+        unsigned long long *mx = e->res.get() + TP_RW_SCRATCH + 2;
+        zero_u64<<<1, 64, 0, s>>>(mx, 1);
+        TP_CHECK_LAUNCH();
+        if (T) {
+            k_max_u32<<<grid_for(T, 256), 256, 0, s>>>(count.get(), T, mx);
+            TP_CHECK_LAUNCH();
+        }
+        uint64_t h[2] = {0, 0};
+        TP_HIP(hipMemcpyAsync(&h[0], e->base.get() + T, 8, hipMemcpyDeviceToHost, s));
+        TP_HIP(hipMemcpyAsync(&h[1], mx, 8, hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+        e->total = h[0];
+        e->max_tile = h[1];
+        if (total) *total = e->total;
+        if (max_tile) *max_tile = e->max_tile;
+        *out = e.release();
+    });
+}
+
+extern "C" tp_status tripoll_enum_next(tp_enum_stream *e, uint32_t *dev_records, uint64_t capacity,
+                                       uint64_t *n_written, void *stream)
+{
+    return guard([&] {
+        if (!e || !n_written || (capacity && !dev_records)) fail(TP_ERR_INVALID, "tripoll_enum_next: bad argument");
+        hipStream_t s = (hipStream_t)stream;
+        *n_written = 0;
+        // skip tiles without records, then take as many whole tiles as fit
+        if (e->next >= e->n_tiles || e->emitted == e->total) {
+            e->next = e->n_tiles;
+            return;
+        }
+        k_enum_chunk<<<1, 64, 0, s>>>(e->base.get(), e->n_tiles, e->next, capacity, e->chunk.get());
+        TP_CHECK_LAUNCH();
+        uint64_t c[3];
+        TP_HIP(hipMemcpyAsync(c, e->chunk.get(), sizeof(c), hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+        uint64_t t1 = c[0];
+        if (c[2] == c[1]) {
+            // only empty tiles fit before the first that does not: move past them
+            e->next = t1;
+            if (e->next >= e->n_tiles) return;
+            k_enum_chunk<<<1, 64, 0, s>>>(e->base.get(), e->n_tiles, e->next, capacity, e->chunk.get());
+            TP_CHECK_LAUNCH();
+            TP_HIP(hipMemcpyAsync(c, e->chunk.get(), sizeof(c), hipMemcpyDeviceToHost, s));
+            TP_HIP(hipStreamSynchronize(s));
+            t1 = c[0];
+        }
+        if (t1 == e->next)
+            fail(TP_ERR_INVALID, "tripoll_enum_next: capacity " + std::to_string(capacity) +
+                                     " is below the next tile's records (the largest tile has " +
+                                     std::to_string(e->max_tile) + ")");
+        SurveyParams P = make_params(e->g, &e->spec, e->res.get(), e->res.get() + TP_RW_SCRATCH);
+        P.enum_out = dev_records;
+        P.enum_cap = capacity;
+        P.enum_tile_base = e->base.get();
+        P.enum_tile_cursor = e->cursor.get();
+        P.enum_chunk_base = c[1];
+        enum_tiles(e, P, e->next, t1, s);
+        TP_HIP(hipStreamSynchronize(s));
+        *n_written = c[2] - c[1];
+        e->emitted += *n_written;
+        e->next = t1;
+    });
+}
+
+extern "C" tp_status tripoll_enum_close(tp_enum_stream *e)
+{
+    return guard([&] { delete e; });
 }
 
 extern "C" tp_status tripoll_participation(const tp_graph *g, const tp_survey_spec *spec, uint64_t *vertex_counts,

@@ -136,6 +136,10 @@ SIGNATURES = {
     "tripoll_enumerate": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64), _P]),
     "tripoll_participation": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, _P,
                                              ctypes.POINTER(ctypes.c_uint64), _P]),
+    "tripoll_enum_open": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, ctypes.POINTER(_P),
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
+    "tripoll_enum_next": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64), _P]),
+    "tripoll_enum_close": (ctypes.c_int, [_P]),
     "tripoll_build_batch": (ctypes.c_int, [ctypes.POINTER(tp_batch_edges), _P, ctypes.POINTER(_P)]),
     "tripoll_graph_count": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32)]),
     "tripoll_batch_words": (ctypes.c_uint64, [ctypes.POINTER(tp_survey_spec)]),
@@ -236,6 +240,26 @@ def tripoll_graph_count(g: int) -> int:
     v = ctypes.c_uint32(0)
     _check(load().tripoll_graph_count(g, ctypes.byref(v)))
     return v.value
+
+
+def tripoll_enum_open(g: int, spec: tp_survey_spec, stream=None) -> tuple:
+    """Open a streamed enumeration; returns (handle, total records, records
+    of the largest tile)."""
+    h = _P()
+    total, mx = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(load().tripoll_enum_open(g, ctypes.byref(spec), stream, ctypes.byref(h), ctypes.byref(total),
+                                    ctypes.byref(mx)))
+    return h.value, int(total.value), int(mx.value)
+
+
+def tripoll_enum_next(e: int, dev_records: int, capacity: int, stream=None) -> int:
+    n = ctypes.c_uint64(0)
+    _check(load().tripoll_enum_next(e, dev_records, capacity, ctypes.byref(n), stream))
+    return int(n.value)
+
+
+def tripoll_enum_close(e: int) -> None:
+    _check(load().tripoll_enum_close(e))
 
 
 def tripoll_participation(g: int, spec: tp_survey_spec, vertex_counts: int, edge_counts: int, stream=None) -> int:
