@@ -17,6 +17,8 @@ Survey outputs are selected by name:
   "degree_table"  counts per sorted triple of ceil(log2 d(v)) over the three
                   vertices (the degree metadata of the evaluation), indexed
                   like the label table, 5984 entries (values 0..31)
+  "directed"      census of directed triangle types (030T, 030C, 120D, 120U,
+                  120C, 210, 300) from the directions of the raw edges
 Filters: window=(t_lo, t_hi) keeps triangles whose three times lie in the
 closed range; label_mask=set of multiset indices keeps only those.
 
@@ -36,7 +38,8 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OUT_BITS = {"count": 1, "close_hist": 2, "label_table": 4, "spread_count": 8, "open_close": 16,
-            "max_edge": 32, "degree_table": 64}
+            "max_edge": 32, "degree_table": 64, "directed": 128}
+DIRECTED_TYPES = ("030T", "030C", "120D", "120U", "120C", "210", "300")
 TABLE_MAX = 816
 MAX_EDGE_BINS = 1024
 DEGREE_MAX = 5984  # C(34, 3): multisets of three values in 0..31
@@ -55,7 +58,8 @@ class _Result(ctypes.Structure):
                 ("label_table", ctypes.c_uint64 * TABLE_MAX),
                 ("open_close", ctypes.c_uint64 * 1024),
                 ("max_edge", ctypes.c_uint64 * MAX_EDGE_BINS),
-                ("degree_table", ctypes.c_uint64 * DEGREE_MAX)]
+                ("degree_table", ctypes.c_uint64 * DEGREE_MAX),
+                ("directed", ctypes.c_uint64 * 7)]
 
 
 TRI_DTYPE = np.dtype([("a", "<u4"), ("b", "<u4"), ("c", "<u4"),
@@ -88,11 +92,13 @@ def _load():
     lib.oracle_msidx.restype = ctypes.c_uint32
     lib.oracle_msidx.argtypes = [ctypes.c_uint32] * 3
     lib.oracle_clean.restype = ctypes.c_int64
-    lib.oracle_clean.argtypes = [ctypes.c_uint32, ctypes.c_uint64, p, p, p, p, p, p]
+    lib.oracle_clean.argtypes = [ctypes.c_uint32, ctypes.c_uint64, p, p, p, p, p, p, p]
     lib.oracle_survey.restype = ctypes.c_int
-    lib.oracle_survey.argtypes = [ctypes.c_uint32, ctypes.c_uint64, p, p, p, p,
+    lib.oracle_survey.argtypes = [ctypes.c_uint32, ctypes.c_uint64, p, p, p, p, p,
                                   ctypes.POINTER(_Spec), ctypes.POINTER(_Result), ctypes.c_int,
                                   p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.oracle_directed_type.restype = ctypes.c_uint32
+    lib.oracle_directed_type.argtypes = [ctypes.c_uint32] * 3
     lib.oracle_participation.restype = ctypes.c_int
     lib.oracle_participation.argtypes = [ctypes.c_uint32, ctypes.c_uint64, p, p, p, p, ctypes.POINTER(_Spec), p, p,
                                          ctypes.c_int]
@@ -122,9 +128,14 @@ def _ptr(a):
     return None if a is None else a.ctypes.data
 
 
-def clean(n: int, src: np.ndarray, dst: np.ndarray, ts: np.ndarray | None):
+def directed_type(d01: int, d02: int, d12: int) -> int:
+    return int(_load().oracle_directed_type(d01, d02, d12))
+
+
+def clean(n: int, src: np.ndarray, dst: np.ndarray, ts: np.ndarray | None, directions: bool = False):
     """Drop self-loops, keep each undirected pair once with its earliest time.
-    Returns (u, v, t) with u < v."""
+    Returns (u, v, t) with u < v, and with directions=True also the pair's
+    direction bits (bit 0: u -> v occurs, bit 1: v -> u occurs)."""
     src = np.ascontiguousarray(src, np.uint32)
     dst = np.ascontiguousarray(dst, np.uint32)
     ts = None if ts is None else np.ascontiguousarray(ts, np.uint32)
@@ -132,17 +143,20 @@ def clean(n: int, src: np.ndarray, dst: np.ndarray, ts: np.ndarray | None):
     u = np.empty(max(M, 1), np.uint32)
     v = np.empty(max(M, 1), np.uint32)
     t = np.empty(max(M, 1), np.uint32)
-    m = _load().oracle_clean(n, M, _ptr(src), _ptr(dst), _ptr(ts), _ptr(u), _ptr(v), _ptr(t))
+    d = np.zeros(max(M, 1), np.uint8) if directions else None
+    m = _load().oracle_clean(n, M, _ptr(src), _ptr(dst), _ptr(ts), _ptr(u), _ptr(v), _ptr(t), _ptr(d))
     if m == -1:
         raise ValueError("vertex id out of range")
     if m < 0:
         raise MemoryError("oracle_clean")
+    if directions:
+        return u[:m].copy(), v[:m].copy(), t[:m].copy(), d[:m].copy()
     return u[:m].copy(), v[:m].copy(), t[:m].copy()
 
 
 def survey_clean(n: int, u, v, t, vlab, outputs=("count",), n_labels: int = 4, spread_lt: int = 0,
                  window=None, label_mask=None, threads: int = 0, records: bool = False,
-                 max_edge_shift: int = 0):
+                 max_edge_shift: int = 0, edir=None):
     """Survey an already-cleaned graph.  Returns a dict of results (and the
     triangle records as a structured array when records=True)."""
     lib = _load()
@@ -163,24 +177,27 @@ def survey_clean(n: int, u, v, t, vlab, outputs=("count",), n_labels: int = 4, s
     v = np.ascontiguousarray(v, np.uint32)
     t = np.ascontiguousarray(t, np.uint32)
     vlab = None if vlab is None else np.ascontiguousarray(vlab, np.uint8)
+    edir = None if edir is None else np.ascontiguousarray(edir, np.uint8)
     recs = None
     cap = 0
     nrec = ctypes.c_uint64(0)
     if records:
         # first pass counts the triangles, second writes them
-        rc = lib.oracle_survey(n, len(u), _ptr(u), _ptr(v), _ptr(t), _ptr(vlab), ctypes.byref(sp),
+        rc = lib.oracle_survey(n, len(u), _ptr(u), _ptr(v), _ptr(t), _ptr(edir), _ptr(vlab), ctypes.byref(sp),
                                ctypes.byref(res), threads, None, 0, ctypes.byref(nrec))
         if rc != 0:
             raise RuntimeError("oracle_survey failed: %d" % rc)
         cap = res.triangles if (sp.filters == 0) else _count_all(lib, n, u, v, t, vlab, threads)
         recs = np.zeros(max(cap, 1), TRI_DTYPE)
         res = _Result()
-    rc = lib.oracle_survey(n, len(u), _ptr(u), _ptr(v), _ptr(t), _ptr(vlab), ctypes.byref(sp),
+    rc = lib.oracle_survey(n, len(u), _ptr(u), _ptr(v), _ptr(t), _ptr(edir), _ptr(vlab), ctypes.byref(sp),
                            ctypes.byref(res), threads, _ptr(recs), cap, ctypes.byref(nrec))
     if rc == -3:
         raise ValueError("vertex label >= n_labels")
     if rc == -4:
         raise ValueError("max_edge_shift must be below 32")
+    if rc == -5:
+        raise ValueError("the directed census needs the edge directions")
     if rc != 0:
         raise RuntimeError("oracle_survey failed: %d" % rc)
     out = dict(triangles=int(res.triangles), spread_count=int(res.spread_count),
@@ -189,7 +206,8 @@ def survey_clean(n: int, u, v, t, vlab, outputs=("count",), n_labels: int = 4, s
                label_table=np.frombuffer(bytes(res.label_table), np.uint64)[:table_size(n_labels)].copy(),
                open_close=np.frombuffer(bytes(res.open_close), np.uint64).reshape(32, 32).copy(),
                max_edge=np.frombuffer(bytes(res.max_edge), np.uint64).copy(),
-               degree_table=np.frombuffer(bytes(res.degree_table), np.uint64).copy())
+               degree_table=np.frombuffer(bytes(res.degree_table), np.uint64).copy(),
+               directed=np.frombuffer(bytes(res.directed), np.uint64).copy())
     if records:
         out["records"] = recs[:int(nrec.value)]
     return out
@@ -200,14 +218,19 @@ def _count_all(lib, n, u, v, t, vlab, threads):
     sp.outputs = 1
     res = _Result()
     nrec = ctypes.c_uint64(0)
-    lib.oracle_survey(n, len(u), _ptr(u), _ptr(v), _ptr(t), _ptr(vlab), ctypes.byref(sp),
+    lib.oracle_survey(n, len(u), _ptr(u), _ptr(v), _ptr(t), None, _ptr(vlab), ctypes.byref(sp),
                       ctypes.byref(res), threads, None, 0, ctypes.byref(nrec))
     return int(res.triangles)
 
 
 def survey(n: int, src, dst, ts, vlab, **kw):
-    """Clean the raw edge list, then survey it."""
-    u, v, t = clean(n, src, dst, ts)
+    """Clean the raw edge list, then survey it (the directed census reads
+    the direction of every raw edge, src -> dst)."""
+    if "directed" in kw.get("outputs", ()):
+        u, v, t, d = clean(n, src, dst, ts, directions=True)
+        kw["edir"] = d
+    else:
+        u, v, t = clean(n, src, dst, ts)
     out = survey_clean(n, u, v, t, vlab, **kw)
     out["m"] = len(u)
     return out

@@ -34,6 +34,16 @@
  *     vertex and per edge, the number of triangles that contain it (the
  *     counters of clustering coefficients and truss decomposition), under
  *     the same prefilters as the surveys.
+ *   - Directed graphs (the remark closing the Preliminaries' storage
+ *     discussion: the oriented graph serves directed inputs too, each edge
+ *     keeping two bits of its original direction): a census of the
+ *     directed triangle types.  Each vertex pair keeps which directions
+ *     occur among its raw copies; a triangle is then one of seven types of
+ *     three connected pairs, named as in the triad census: 030T (three
+ *     one-way arcs, no cycle), 030C (a directed 3-cycle), 120D, 120U, 120C
+ *     (one mutual pair; the third vertex sends both of its arcs, receives
+ *     both, or sends one and receives one), 210 (two mutual pairs) and 300
+ *     (three mutual pairs).
  *   - Metadata-overhead experiment of the evaluation (vertex degree as the
  *     metadata): counts of the triple (ceil(log2 d(p)), ceil(log2 d(q)),
  *     ceil(log2 d(r))) over all triangles, p, q, r in the degree order.
@@ -67,6 +77,7 @@
 #define ORC_OUT_OPEN_CLOSE 16u
 #define ORC_OUT_MAX_EDGE 32u
 #define ORC_OUT_DEGREE_TABLE 64u
+#define ORC_OUT_DIRECTED 128u
 
 #define ORC_FILT_WINDOW 1u
 #define ORC_FILT_LABEL_MASK 2u
@@ -95,6 +106,7 @@ typedef struct {
     uint64_t open_close[32 * 32];
     uint64_t max_edge[ORC_MAX_EDGE_BINS];
     uint64_t degree_table[ORC_DEGREE_MAX];
+    uint64_t directed[7]; /* 030T, 030C, 120D, 120U, 120C, 210, 300 */
 } orc_result;
 
 /* ------------------------------------------------------------------------ */
@@ -153,10 +165,39 @@ static int passes(const orc_spec *sp, uint32_t t_pq, uint32_t t_pr, uint32_t t_q
     return 1;
 }
 
+/* Type of a directed triangle on vertices 0, 1, 2 given each pair's
+ * directions: d01 has bit 0 for the arc 0 -> 1 and bit 1 for 1 -> 0, and
+ * likewise d02 (0 -> 2, 2 -> 0) and d12 (1 -> 2, 2 -> 1).  Every pair has at
+ * least one arc. */
+uint32_t oracle_directed_type(uint32_t d01, uint32_t d02, uint32_t d12)
+{
+    int arc[3][3] = {{0}};
+    arc[0][1] = d01 & 1; arc[1][0] = (d01 >> 1) & 1;
+    arc[0][2] = d02 & 1; arc[2][0] = (d02 >> 1) & 1;
+    arc[1][2] = d12 & 1; arc[2][1] = (d12 >> 1) & 1;
+    int mutual = 0, x = -1, y = -1;
+    for (int i = 0; i < 3; ++i)
+        for (int j = i + 1; j < 3; ++j)
+            if (arc[i][j] && arc[j][i]) { ++mutual; x = i; y = j; }
+    if (mutual == 3) return 6;
+    if (mutual == 2) return 5;
+    if (mutual == 1) {
+        const int z = 3 - x - y;  /* the vertex outside the mutual pair */
+        const int out = arc[z][x] + arc[z][y], in = arc[x][z] + arc[y][z];
+        if (out == 2) return 2;  /* 120D */
+        if (in == 2) return 3;   /* 120U */
+        return 4;                /* 120C */
+    }
+    /* three one-way arcs: a cycle when every vertex sends exactly one */
+    for (int i = 0; i < 3; ++i)
+        if (arc[i][0] + arc[i][1] + arc[i][2] != 1) return 0;  /* 030T */
+    return 1;                                                 /* 030C */
+}
+
 static void callback(const orc_spec *sp, orc_result *acc,
                      uint32_t t_pq, uint32_t t_pr, uint32_t t_qr,
                      uint8_t l_p, uint8_t l_q, uint8_t l_r,
-                     uint64_t d_p, uint64_t d_q, uint64_t d_r)
+                     uint64_t d_p, uint64_t d_q, uint64_t d_r, uint32_t type)
 {
     if (!passes(sp, t_pq, t_pr, t_qr, l_p, l_q, l_r)) return;
     uint32_t idx = 0;
@@ -187,6 +228,15 @@ static void callback(const orc_spec *sp, orc_result *acc,
     }
     if (sp->outputs & ORC_OUT_DEGREE_TABLE)
         acc->degree_table[oracle_msidx(oracle_bin(d_p), oracle_bin(d_q), oracle_bin(d_r))] += 1;
+    if (sp->outputs & ORC_OUT_DIRECTED)
+        acc->directed[type] += 1;
+}
+
+/* Directions of the pair {x, y} as seen from x -> y, given the bits of the
+ * cleaned pair (bit 0: lower id -> higher id, bit 1: higher -> lower). */
+static uint32_t dir_from(uint32_t x, uint32_t y, uint32_t bits)
+{
+    return x < y ? bits : (((bits & 1u) << 1) | (bits >> 1));
 }
 
 /* ------------------------------------------------------------------------ */
@@ -209,9 +259,11 @@ static int rec_cmp(const void *x, const void *y)
 
 /* Returns the number m of unique undirected edges written to (u, v, t) with
  * u < v, or -1 if an endpoint is >= n, or -2 on allocation failure.  Output
- * arrays must hold n_edges entries.  ts may be NULL (all times 0). */
+ * arrays must hold n_edges entries.  ts may be NULL (all times 0).  out_dir,
+ * if not NULL, receives per pair the directions its raw copies take: bit 0
+ * for u -> v, bit 1 for v -> u. */
 int64_t oracle_clean(uint32_t n, uint64_t n_edges, const uint32_t *src, const uint32_t *dst,
-                     const uint32_t *ts, uint32_t *out_u, uint32_t *out_v, uint32_t *out_t)
+                     const uint32_t *ts, uint32_t *out_u, uint32_t *out_v, uint32_t *out_t, uint8_t *out_dir)
 {
     rec_t *r = (rec_t *)malloc((n_edges ? n_edges : 1) * sizeof(rec_t));
     if (!r) return -2;
@@ -223,16 +275,21 @@ int64_t oracle_clean(uint32_t n, uint64_t n_edges, const uint32_t *src, const ui
         const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
         r[k].key = ((uint64_t)lo << 32) | hi;
         r[k].t = ts ? ts[i] : 0u;
-        r[k].pad = 0;
+        r[k].pad = a < b ? 1u : 2u;
         ++k;
     }
     qsort(r, k, sizeof(rec_t), rec_cmp);
     int64_t m = 0;
     for (uint64_t i = 0; i < k; ++i) {
-        if (i > 0 && r[i].key == r[i - 1].key) continue; /* later copies are not earlier */
+        if (i > 0 && r[i].key == r[i - 1].key) {
+            /* later copies are not earlier, but add their direction */
+            if (out_dir) out_dir[m - 1] |= (uint8_t)r[i].pad;
+            continue;
+        }
         out_u[m] = (uint32_t)(r[i].key >> 32);
         out_v[m] = (uint32_t)(r[i].key & 0xffffffffu);
         out_t[m] = r[i].t;
+        if (out_dir) out_dir[m] = (uint8_t)r[i].pad;
         ++m;
     }
     free(r);
@@ -376,12 +433,13 @@ static void emit_record(orc_tri *rec, uint32_t p, uint32_t q, uint32_t r,
  * while the label table or mask is used.
  */
 int oracle_survey(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev, const uint32_t *et,
-                  const uint8_t *vlab, const orc_spec *sp, orc_result *out, int n_threads,
+                  const uint8_t *edir, const uint8_t *vlab, const orc_spec *sp, orc_result *out, int n_threads,
                   orc_tri *records, uint64_t capacity, uint64_t *n_records)
 {
     orc_graph g;
     memset(out, 0, sizeof(*out));
     if ((sp->outputs & ORC_OUT_MAX_EDGE) && sp->max_edge_shift > 31) return -4;
+    if ((sp->outputs & ORC_OUT_DIRECTED) && !edir) return -5;
     if ((sp->outputs & ORC_OUT_LABEL_TABLE || sp->filters & ORC_FILT_LABEL_MASK) && vlab) {
         for (uint32_t v = 0; v < n; ++v)
             if (vlab[v] >= sp->n_labels) return -3;
@@ -425,7 +483,13 @@ int oracle_survey(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev
                     const uint32_t t_pr = g.tim[x], t_qr = g.tim[y];
                     const uint8_t l_p = vlab ? vlab[p] : 0, l_q = vlab ? vlab[q] : 0,
                                   l_r = vlab ? vlab[r] : 0;
-                    callback(sp, acc, t_pq, t_pr, t_qr, l_p, l_q, l_r, g.deg[p], g.deg[q], g.deg[r]);
+                    uint32_t type = 0;
+                    if (edir) {
+                        const uint32_t P = (uint32_t)p;
+                        type = oracle_directed_type(dir_from(P, q, edir[g.eid[i]]), dir_from(P, r, edir[g.eid[x]]),
+                                                    dir_from(q, r, edir[g.eid[y]]));
+                    }
+                    callback(sp, acc, t_pq, t_pr, t_qr, l_p, l_q, l_r, g.deg[p], g.deg[q], g.deg[r], type);
                     if (records) {
                         uint64_t slot;
 #pragma omp atomic capture
@@ -448,6 +512,7 @@ int oracle_survey(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev
                 for (int b = 0; b < 32 * 32; ++b) out->open_close[b] += acc->open_close[b];
                 for (int b = 0; b < ORC_MAX_EDGE_BINS; ++b) out->max_edge[b] += acc->max_edge[b];
                 for (int b = 0; b < ORC_DEGREE_MAX; ++b) out->degree_table[b] += acc->degree_table[b];
+                for (int b = 0; b < 7; ++b) out->directed[b] += acc->directed[b];
             }
         }
         free(acc);

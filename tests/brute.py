@@ -92,3 +92,41 @@ def survey(n, src, dst, ts, vlab, n_labels=4, spread_lt=0, window=None, label_ma
         dl = tuple(sorted(ceil_log2_bin(degree[x]) for x in (a, b, c)))
         res["degree_table"][deg_idx[dl]] += 1
     return res
+
+
+# representatives of the seven directed triangle types, as arc lists on
+# vertices 0, 1, 2 (triad census names)
+_DIRECTED_REPS = {
+    0: [(0, 1), (0, 2), (1, 2)],                          # 030T
+    1: [(0, 1), (1, 2), (2, 0)],                          # 030C
+    2: [(0, 1), (0, 2), (1, 2), (2, 1)],                  # 120D
+    3: [(1, 0), (2, 0), (1, 2), (2, 1)],                  # 120U
+    4: [(0, 1), (2, 0), (1, 2), (2, 1)],                  # 120C
+    5: [(0, 1), (1, 0), (0, 2), (2, 0), (1, 2)],          # 210
+    6: [(0, 1), (1, 0), (0, 2), (2, 0), (1, 2), (2, 1)],  # 300
+}
+
+
+def _canon_arcs(arcs):
+    """Smallest arc set over the six relabellings of 0, 1, 2."""
+    from itertools import permutations
+    return min(tuple(sorted((pi[a], pi[b]) for a, b in arcs)) for pi in permutations(range(3)))
+
+
+_DIRECTED_CANON = {_canon_arcs(a): t for t, a in _DIRECTED_REPS.items()}
+
+
+def directed_census(n, src, dst):
+    """Census of directed triangle types of a directed multigraph (self-loops
+    and repeated arcs ignored), by matching each triangle's arc set to the
+    representatives up to relabelling."""
+    arcs = {(int(a), int(b)) for a, b in zip(np.asarray(src).tolist(), np.asarray(dst).tolist()) if a != b}
+    und = {}
+    for a, b in arcs:
+        und.setdefault((min(a, b), max(a, b)), set()).add((a, b))
+    out = np.zeros(7, np.uint64)
+    for a, b, c, *_ in triangles(n, {k: 0 for k in und}):
+        idx = {a: 0, b: 1, c: 2}
+        sub = [(idx[x], idx[y]) for pair in ((a, b), (a, c), (b, c)) for x, y in und[pair]]
+        out[_DIRECTED_CANON[_canon_arcs(sub)]] += 1
+    return out

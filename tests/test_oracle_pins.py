@@ -511,3 +511,51 @@ def test_participation_sums_on_workload1():
     r = oracle.survey(g["n"], g["src"], g["dst"], g["ts"], g["vlab"], outputs=("count",), n_labels=4)
     vc, (u, v, t, ec) = oracle.participation(g["n"], g["src"], g["dst"], g["ts"], g["vlab"], n_labels=4)
     assert vc.sum() == ec.sum() == 3 * r["triangles"]
+
+
+# -------------------------------------------------------------- directed census
+
+def dsurvey(n, arcs):
+    a = np.asarray(arcs, dtype=np.int64).reshape(-1, 2)
+    src, dst = a[:, 0].astype(np.uint32), a[:, 1].astype(np.uint32)
+    return oracle.survey(n, src, dst, np.zeros(len(a), np.uint32), np.zeros(n, np.uint8),
+                         outputs=("count", "directed"))
+
+
+def test_directed_types_of_single_triangles():
+    for t, arcs in brute._DIRECTED_REPS.items():
+        r = dsurvey(3, arcs)
+        exp = np.zeros(7, np.uint64)
+        exp[t] = 1
+        assert (r["directed"] == exp).all(), (oracle.DIRECTED_TYPES[t], r["directed"])
+    # a repeated arc or a reversed copy changes the pair's directions
+    assert dsurvey(3, [(0, 1), (1, 2), (2, 0), (0, 1)])["directed"][1] == 1
+    assert dsurvey(3, [(0, 1), (1, 2), (2, 0), (1, 0)])["directed"][4] == 1
+
+
+@pytest.mark.parametrize("n,seed", [(5, 1), (12, 2), (30, 3)])
+def test_directed_tournament_closed_form(n, seed):
+    # a random tournament: C(n,3) triangles, of which sum_v C(out(v), 2) are
+    # transitive (one per vertex that sends both of its arcs) and the rest cyclic
+    rng = np.random.default_rng(seed)
+    arcs = [(u, v) if rng.random() < 0.5 else (v, u) for u, v in combinations(range(n), 2)]
+    out = np.bincount([a for a, _ in arcs], minlength=n)
+    r = dsurvey(n, arcs)
+    trans = sum(math.comb(int(k), 2) for k in out)
+    assert r["directed"][0] == trans and r["directed"][1] == math.comb(n, 3) - trans
+    assert r["directed"][2:].sum() == 0
+    # every pair in both directions: all mutual
+    both = arcs + [(b, a) for a, b in arcs]
+    assert dsurvey(n, both)["directed"][6] == math.comb(n, 3)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_directed_against_brute_force(seed):
+    rng = np.random.default_rng(60 + seed)
+    n = int(rng.integers(10, 70))
+    M = int(rng.integers(n, 10 * n))
+    src = rng.integers(0, n, M).astype(np.uint32)
+    dst = rng.integers(0, n, M).astype(np.uint32)
+    r = oracle.survey(n, src, dst, np.zeros(M, np.uint32), np.zeros(n, np.uint8), outputs=("count", "directed"))
+    assert (r["directed"] == brute.directed_census(n, src, dst)).all()
+    assert r["directed"].sum() == r["triangles"]
