@@ -42,13 +42,14 @@ def resolve_variant(c: int, v: int) -> int:
     return v if v else {0: 1, 1: 2, 2: 2, 3: 3}[c]
 
 
-def kernel_key(c: int, v: int, meta: bool) -> str:
+def kernel_key(c: int, v: int, meta: bool, form: int = 0) -> str:
     """Template arguments of the survey kernel that serves class c under
-    variant v, as in the rocprofv3 kernel name (spaces removed)."""
+    variant v, as in the rocprofv3 kernel name (spaces removed).  form: 0 the
+    plain survey, 1 the extended reductions, 2 participation."""
     v = resolve_variant(c, v)
     log_slots, block, wave = {1: (6, 256, "true"), 2: (12, 1024, "false") if c == 2 else (10, 256, "false"),
                               3: (0, 256, "false"), 4: (0, 256, "true")}[v]
-    return "survey_kernel<%d,%d,%s,%s,false,false,0>" % (log_slots, block, wave, "true" if meta else "false")
+    return "survey_kernel<%d,%d,%s,%s,false,false,%d>" % (log_slots, block, wave, "true" if meta else "false", form)
 
 
 def log(*a):
@@ -439,6 +440,106 @@ def served_bench(args, torch, synth, tp) -> dict:
         srv.close()
 
 
+def kind_bench(args, torch, synth, tp) -> dict:
+    """One step = build + the chosen kind on workload 1-3's graph.  The
+    roofline is that of the whole call after the build (every class, plus
+    the participation post-pass or the enumeration's counting pass); its
+    algorithmic bytes are the survey's plus the records written."""
+    w = synth.workload(args.workload, scale=args.scale)
+    gs = w.graph
+    g = synth.generate(gs)
+    dev = {k: torch.from_numpy(g[k]).to("cuda") for k in ("src", "dst", "ts", "vlab")}
+    del g
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    sptr = stream.cuda_stream
+    el = tp.edge_list(gs.n, dev["src"], dev["dst"], dev["ts"], dev["vlab"], device=True)
+    outputs = tuple(w.outputs) + (("max_edge", "degree_table") if args.kind == "ext" else ())
+    # Algorithm 3's 1024 bins span the time range: 2^bits for uniform times,
+    # 2^31 for bursty ones
+    time_bits = gs.ts[1] if gs.ts[0] == "uniform" else 31
+    shift = max(0, time_bits - 10)
+    spec = tp.make_spec(outputs=outputs, n_labels=w.n_labels, spread_lt=w.spread_lt, max_edge_shift=shift)
+    bufs = {}
+
+    def run_kind(h, st):
+        """Returns (triangles, records or counters written in bytes)."""
+        if args.kind == "ext":
+            r = tp.result_dict(tp.tripoll_survey(h, spec, sptr), w.n_labels)
+            return r["triangles"], 0, r
+        if args.kind == "participation":
+            if "v" not in bufs:
+                bufs["v"] = torch.empty(gs.n, dtype=torch.int64, device="cuda")
+                bufs["e"] = torch.empty(max(st["n_edges"], 1), dtype=torch.int64, device="cuda")
+            tri = tp.tripoll_participation(h, tp.make_spec(), bufs["v"].data_ptr(), bufs["e"].data_ptr(), sptr)
+            return tri, 8 * (gs.n + st["n_edges"]), None
+        cap = args.enum_capacity
+        if "r" not in bufs:
+            bufs["r"] = torch.empty(cap * 9, dtype=torch.int32, device="cuda")
+        tp.tripoll_set_plan(h, tp.make_plan((0, 0, 0, 0), (args.enum_tile,) * 4), sptr)
+        e, total, max_tile = tp.tripoll_enum_open(h, tp.make_spec(), sptr)
+        try:
+            got = 0
+            while True:
+                k = tp.tripoll_enum_next(e, bufs["r"].data_ptr(), cap, sptr)
+                if k == 0:
+                    break
+                got += k
+        finally:
+            tp.tripoll_enum_close(e)
+        assert got == total
+        return total, 36 * total, None
+
+    def step():
+        h = tp.tripoll_build(el, sptr)
+        try:
+            st = tp.stats_dict(tp.tripoll_graph_stats(h))
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            tri, written, r = run_kind(h, st)
+            b.record(stream)
+            torch.cuda.synchronize()
+            return st, tri, written, a.elapsed_time(b), r
+        finally:
+            tp.tripoll_graph_free(h)
+
+    for _ in range(args.warmup):
+        step()
+    per = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        per.append(step())
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    st, tri, written, _, r = per[-1]
+    kind_ms = statistics.median(x[3] for x in per)
+    alg = sum(algorithmic_bytes(st, c, True) for c in range(4)) + written
+    achieved = alg / (kind_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": tri / (ms_per_step * 1e-3), "unit": "triangles/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": w.name, "kind": args.kind, "scale": gs.scale, "raw_edges": gs.n_edges,
+                   "vertices": gs.n, "edges": st["n_edges"], "outputs": list(outputs), "max_edge_shift": shift,
+                   "enum_capacity": args.enum_capacity if args.kind == "enum" else None,
+                   "enum_tile_records": args.enum_tile if args.kind == "enum" else None,
+                   "step": "build + " + args.kind},
+        "result": {"triangles": tri, "wedge_checks": st["probes"]},
+        "kind_ms_p50": round(kind_ms, 3),
+        "build_ms_p50": round(statistics.median(x[0]["build_ms"] for x in per), 3),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "the whole %s call (every class)" % args.kind, "algorithmic_bytes": int(alg),
+                     "written_bytes": int(written)},
+    }
+    if r is not None:
+        out["class_ms"] = [round(x, 3) for x in r["class_ms"]]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -454,6 +555,14 @@ def main():
                     help="workload 4: time the one-graph-per-launch loop on every k-th graph")
     ap.add_argument("--scale", type=int, default=None, help="override the R-MAT scale (same recipe)")
     ap.add_argument("--count-only", action="store_true", help="survey the triangle count only")
+    ap.add_argument("--kind", default="survey", choices=("survey", "ext", "participation", "enum"),
+                    help="workloads 1-3: what each step runs after the build: the survey (default), the survey "
+                         "with Algorithm 3's max-edge bins and the degree table added, the per-vertex and "
+                         "per-edge participation counts, or the streamed enumeration of every triangle")
+    ap.add_argument("--enum-capacity", type=int, default=1 << 28, help="--kind enum: records per chunk")
+    ap.add_argument("--enum-tile", type=int, default=256,
+                    help="--kind enum: records per tile of the plan the enumeration runs with (small tiles keep "
+                         "every chunk spread over many workgroups)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the survey plan once on the first build; every step then re-cuts its tiles "
@@ -483,6 +592,9 @@ def main():
         return
     if args.workload == 5:
         print(json.dumps(served_bench(args, torch, synth, tp)), flush=True)
+        return
+    if args.kind != "survey":
+        print(json.dumps(kind_bench(args, torch, synth, tp)), flush=True)
         return
 
     w = synth.workload(args.workload, scale=args.scale)

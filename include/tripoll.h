@@ -69,7 +69,14 @@ typedef enum {
  *   vertex_label  uint8[n_vertices], or NULL: every label is 0
  *   mem_space     TP_MEM_HOST or TP_MEM_DEVICE, for all four arrays
  *   tie_hash      TP_TIE_MIX or TP_TIE_ID
+ *   flags         0, or TP_EDGES_DIRECTED: edges are arcs src -> dst.  The
+ *                 graph is still surveyed as undirected, but each oriented
+ *                 edge keeps two bits of the directions its copies take (the
+ *                 remark on directed inputs at the end of the Preliminaries'
+ *                 storage discussion), for the DIRECTED census; needs
+ *                 n_vertices <= 2^31
  */
+#define TP_EDGES_DIRECTED 0x1u
 typedef struct {
     uint32_t n_vertices;
     uint32_t mem_space;
@@ -79,7 +86,7 @@ typedef struct {
     const uint32_t *edge_time;
     const uint8_t *vertex_label;
     uint32_t tie_hash;
-    uint32_t reserved;
+    uint32_t flags;
 } tp_edge_list;
 
 typedef struct tp_graph tp_graph;
@@ -170,6 +177,12 @@ tp_status tripoll_graph_export(const tp_graph *g, uint64_t *rowptr, uint32_t *co
  *                over triangles whose vertex labels all differ; the paper's
  *                counting set of exact values is kept per 2^max_edge_shift
  *                range of t3, exact when every t3 >> shift < 1024)
+ *   DIRECTED     directed[type] += 1 on a graph built with TP_EDGES_DIRECTED,
+ *                type of the triangle's arcs as in the triad census:
+ *                0 030T (three one-way arcs, no cycle), 1 030C (a 3-cycle),
+ *                2 120D, 3 120U, 4 120C (one mutual pair; the third vertex
+ *                sends both its arcs, receives both, or one of each),
+ *                5 210 (two mutual pairs), 6 300 (three mutual pairs)
  *   DEGREE_TABLE with x <= y <= z the values bin(d(v)) of the three vertices
  *                (d the undirected degree of the cleaned graph):
  *                degree_table[C(z+2,3)+C(y+1,2)+x] += 1
@@ -177,9 +190,10 @@ tp_status tripoll_graph_export(const tp_graph *g, uint64_t *rowptr, uint32_t *co
  *                triples of ceil(log2 d) of p, q, r; in the degree order
  *                d(p) <= d(q) <= d(r), so that triple is already sorted)
  * with bin(D) = 0 for D <= 1 and min(31, ceil(log2 D)) otherwise, computed
- * exactly in integers.  The triangle count is always produced.  MAX_EDGE and
- * DEGREE_TABLE are produced by tripoll_survey and tripoll_survey_async only
- * (batches and served requests return TP_ERR_UNSUPPORTED for them). */
+ * exactly in integers.  The triangle count is always produced.  MAX_EDGE,
+ * DEGREE_TABLE and DIRECTED are produced by tripoll_survey and
+ * tripoll_survey_async only (batches and served requests return
+ * TP_ERR_UNSUPPORTED for them). */
 #define TP_OUT_COUNT 0x01u
 #define TP_OUT_CLOSE_HIST 0x02u
 #define TP_OUT_LABEL_TABLE 0x04u
@@ -187,6 +201,7 @@ tp_status tripoll_graph_export(const tp_graph *g, uint64_t *rowptr, uint32_t *co
 #define TP_OUT_OPEN_CLOSE 0x10u
 #define TP_OUT_MAX_EDGE 0x20u
 #define TP_OUT_DEGREE_TABLE 0x40u
+#define TP_OUT_DIRECTED 0x80u
 
 /* Prefilters applied before every reduction (the conditional of the
  * callbacks in Algorithms 3 and 4):
@@ -242,6 +257,7 @@ typedef struct {
     uint64_t open_close[32 * 32];
     uint64_t max_edge[TP_MAX_EDGE_BINS];
     uint64_t degree_table[TP_DEGREE_MAX];
+    uint64_t directed[8];    /* the seven types of DIRECTED, then 0 */
     float kernel_ms;         /* device time of the intersection kernels */
     float total_ms;          /* device time of the whole survey call */
     float class_ms[TP_NUM_CLASSES]; /* device time of the kernel of each target class */
@@ -258,7 +274,8 @@ typedef struct {
 #define TP_RW_OPEN_CLOSE (TP_RW_TABLE + TP_TABLE_MAX)
 #define TP_RW_MAX_EDGE (TP_RW_OPEN_CLOSE + 1024u)
 #define TP_RW_DEGREE (TP_RW_MAX_EDGE + TP_MAX_EDGE_BINS)
-#define TP_RW_SCRATCH (TP_RW_DEGREE + TP_DEGREE_MAX)
+#define TP_RW_DIRECTED (TP_RW_DEGREE + TP_DEGREE_MAX)
+#define TP_RW_SCRATCH (TP_RW_DIRECTED + 8u)
 #define TP_RW_SCRATCH_WORDS 4u
 #define TP_RESULT_WORDS (TP_RW_SCRATCH + TP_RW_SCRATCH_WORDS)
 
@@ -266,9 +283,10 @@ typedef struct {
  * Survey a graph (Algorithm 1 with the reductions above).  Synchronous: the
  * result is on the host when it returns.
  * Errors: TP_ERR_INVALID for NULL arguments, n_labels outside 1..16, a graph
- * label >= n_labels when labels are used, t_lo > t_hi, max_edge_shift > 31
- * or reserved != 0; TP_ERR_UNSUPPORTED for MAX_EDGE or DEGREE_TABLE on a
- * batch; TP_ERR_DEVICE.
+ * label >= n_labels when labels are used, t_lo > t_hi, max_edge_shift > 31,
+ * reserved != 0, or DIRECTED on a graph built without TP_EDGES_DIRECTED;
+ * TP_ERR_UNSUPPORTED for MAX_EDGE, DEGREE_TABLE or DIRECTED on a batch;
+ * TP_ERR_DEVICE.
  */
 tp_status tripoll_survey(const tp_graph *g, const tp_survey_spec *spec, tp_survey_result *out,
                          void *stream);

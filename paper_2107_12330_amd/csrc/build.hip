@@ -57,8 +57,10 @@ __device__ __forceinline__ uint32_t graph_of_edge(const BatchMap &bm, size_t i)
 // Each workgroup canonicalises one contiguous span of `per_block` raw edges,
 // so in a batch a thread finds the graph of its first edge by binary search
 // and then only steps forward through the edge offsets.
+// dbit = 1 (directed inputs) appends the direction of the raw edge to its
+// key: 0 for lower id -> higher id, 1 for the reverse.
 __global__ void k_canon(const uint32_t *src, const uint32_t *dst, const uint32_t *ts, size_t M, uint32_t n,
-                        int nb, uint64_t sentinel, uint64_t *keys, uint32_t *vals, unsigned long long *bad,
+                        int nb, int dbit, uint64_t sentinel, uint64_t *keys, uint32_t *vals, unsigned long long *bad,
                         unsigned long long *loops, BatchMap bm, size_t per_block)
 {
     unsigned long long nbad = 0, nloop = 0;
@@ -87,6 +89,7 @@ __global__ void k_canon(const uint32_t *src, const uint32_t *dst, const uint32_t
             nloop += (ok && a == b) ? 1 : 0;
         } else {
             k = a < b ? pair_key(a, b, nb) : pair_key(b, a, nb);
+            k = (k << dbit) | (uint64_t)(dbit && a > b);
         }
         keys[i] = k;
         vals[i] = ts ? ts[i] : 0u;
@@ -111,30 +114,31 @@ constexpr size_t kCompWave = (size_t)kWave * kCompItems;
 
 // Is pair i the first of its run?  `k` is keys[i]; the previous key comes
 // from the lane below, or from memory for lane 0.
-__device__ __forceinline__ bool run_head(const uint64_t *keys, size_t i, size_t n, uint64_t k)
+// Keys carry dbit direction bits below the pair, which runs ignore.
+__device__ __forceinline__ bool run_head(const uint64_t *keys, size_t i, size_t n, uint64_t k, int dbit)
 {
     uint64_t prev = __shfl_up(k, 1, kWave);
     if (lane_id() == 0 && i < n) prev = i ? keys[i - 1] : ~k;
-    return i < n && prev != k;
+    return i < n && (prev >> dbit) != (k >> dbit);
 }
 
 // Unique pairs of this wave's part of the tile.
-__device__ __forceinline__ uint64_t wave_heads(const uint64_t *keys, size_t n, size_t wbase)
+__device__ __forceinline__ uint64_t wave_heads(const uint64_t *keys, size_t n, size_t wbase, int dbit)
 {
     uint64_t c = 0;
     for (int j = 0; j < kCompItems; ++j) {
         const size_t i = wbase + (size_t)j * kWave + lane_id();
         const uint64_t k = i < n ? keys[i] : 0ull;
-        c += (uint64_t)__popcll(__ballot(run_head(keys, i, n, k)));
+        c += (uint64_t)__popcll(__ballot(run_head(keys, i, n, k, dbit)));
     }
     return c;
 }
 
-__global__ __launch_bounds__(kB) void k_dedup_count(const uint64_t *keys, size_t n, uint64_t *tile_cnt)
+__global__ __launch_bounds__(kB) void k_dedup_count(const uint64_t *keys, size_t n, int dbit, uint64_t *tile_cnt)
 {
     __shared__ uint64_t tmp[kB / kWave];
     const int w = threadIdx.x / kWave;
-    const uint64_t c = wave_heads(keys, n, blockIdx.x * kCompTile + (size_t)w * kCompWave);
+    const uint64_t c = wave_heads(keys, n, blockIdx.x * kCompTile + (size_t)w * kCompWave, dbit);
     if (lane_id() == 0) tmp[w] = c;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -144,14 +148,18 @@ __global__ __launch_bounds__(kB) void k_dedup_count(const uint64_t *keys, size_t
     }
 }
 
-__global__ __launch_bounds__(kB) void k_dedup_write(const uint64_t *keys, const uint32_t *vals, size_t n,
-                                                    const uint64_t *tile_off, uint64_t *ukey, uint32_t *uts)
+// One pair per run with its earliest time; with direction bits (dbit = 1)
+// also the directions of its copies (bit 0: lower -> higher id, bit 1: the
+// reverse) into udir.
+__global__ __launch_bounds__(kB) void k_dedup_write(const uint64_t *keys, const uint32_t *vals, size_t n, int dbit,
+                                                    const uint64_t *tile_off, uint64_t *ukey, uint32_t *uts,
+                                                    uint8_t *udir)
 {
     __shared__ uint64_t tmp[kB / kWave];
     const int w = threadIdx.x / kWave;
     const unsigned lane = lane_id();
     const size_t wbase = blockIdx.x * kCompTile + (size_t)w * kCompWave;
-    const uint64_t c = wave_heads(keys, n, wbase);
+    const uint64_t c = wave_heads(keys, n, wbase, dbit);
     if (lane == 0) tmp[w] = c;
     __syncthreads();
     uint64_t pos = tile_off[blockIdx.x];
@@ -159,15 +167,21 @@ __global__ __launch_bounds__(kB) void k_dedup_write(const uint64_t *keys, const 
     for (int j = 0; j < kCompItems; ++j) {
         const size_t i = wbase + (size_t)j * kWave + lane;
         const uint64_t k = i < n ? keys[i] : 0ull;
-        const bool head = run_head(keys, i, n, k);
+        const bool head = run_head(keys, i, n, k, dbit);
         const uint64_t b = __ballot(head);
         if (head) {
-            // the earliest time of the run
+            // the earliest time of the run, and its directions
+            const uint64_t pk = k >> dbit;
             uint32_t t = vals[i];
-            for (size_t x = i + 1; x < n && keys[x] == k; ++x) t = min(t, vals[x]);
+            uint32_t d = 1u << (k & (uint64_t)dbit);
+            for (size_t x = i + 1; x < n && (keys[x] >> dbit) == pk; ++x) {
+                t = min(t, vals[x]);
+                d |= 1u << (keys[x] & (uint64_t)dbit);
+            }
             const uint64_t at = pos + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-            ukey[at] = k;
+            ukey[at] = pk;
             uts[at] = t;
+            if (udir) udir[at] = (uint8_t)d;
         }
         pos += (uint64_t)__popcll(b);
     }
@@ -325,43 +339,55 @@ __global__ void k_rank_graph(const uint32_t *perm, uint32_t n, const uint32_t *v
 
 // ------------------------------------------------------------ phase 4
 
-__global__ void k_orient(const uint64_t *ukey, const uint32_t *uts, size_t m, int nb, const uint32_t *rank,
-                         uint64_t *okey, uint32_t *ots)
+// With directions (udir set), the oriented key carries two bits below the
+// pair: bit 0 for the arc source -> target of the oriented edge, bit 1 for
+// the reverse.
+__global__ void k_orient(const uint64_t *ukey, const uint32_t *uts, const uint8_t *udir, size_t m, int nb,
+                         const uint32_t *rank, uint64_t *okey, uint32_t *ots)
 {
     const uint64_t mask = (1ull << nb) - 1;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
         const uint64_t k = ukey[i];
         const uint32_t a = rank[k >> nb], b = rank[k & mask];
         const uint32_t s = min(a, b), t = max(a, b);
-        okey[i] = pair_key(s, t, nb);
+        uint64_t o = pair_key(s, t, nb);
+        if (udir) {
+            // udir is relative to lower id -> higher id; a is the lower id's rank
+            const uint32_t d = udir[i];
+            o = (o << 2) | (a < b ? d : (((d & 1u) << 1) | (d >> 1)));
+        }
+        okey[i] = o;
         ots[i] = uts[i];
     }
 }
 
 // d+(s) from the oriented pairs sorted by source: each wave adds one count
 // per run of equal sources among its 64 pairs, to increasing addresses.
-__global__ void k_dplus(const uint64_t *okey, size_t m, int nb, uint32_t *dplus)
+__global__ void k_dplus(const uint64_t *okey, size_t m, int src_shift, uint32_t *dplus)
 {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t base = blockIdx.x * (size_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < m; base += stride) {
         const size_t i = base + lane_id();
         const bool ok = i < m;
-        add_runs(ok ? okey[i] >> nb : ~0ull, ok, dplus);
+        add_runs(ok ? okey[i] >> src_shift : ~0ull, ok, dplus);
     }
 }
 
 // ------------------------------------------------------------ phase 5
 
+// edir (directed builds) receives the two direction bits below the pair.
 __global__ void k_csr(const uint64_t *okey, size_t m, int nb, const uint8_t *rlab, uint32_t *col, uint8_t *tlab,
-                      uint32_t *srow)
+                      uint32_t *srow, uint8_t *edir)
 {
     const uint64_t mask = (1ull << nb) - 1;
+    const int dshift = edir ? 2 : 0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
         const uint64_t k = okey[i];
-        const uint32_t t = (uint32_t)(k & mask);
+        const uint32_t t = (uint32_t)((k >> dshift) & mask);
         col[i] = t;
         tlab[i] = rlab[t];
-        srow[i] = (uint32_t)(k >> nb);
+        srow[i] = (uint32_t)(k >> (nb + dshift));
+        if (edir) edir[i] = (uint8_t)(k & 3u);
     }
 }
 
@@ -582,7 +608,7 @@ uint64_t graph_bytes(const tp_graph *g)
 {
     uint64_t b = g->rowptr.bytes() + g->col.bytes() + g->ets.bytes() + g->tlab.bytes() + g->rlab.bytes() +
                  g->perm.bytes() + g->inkey.bytes() + g->inpay.bytes() + g->rank_gid.bytes() +
-                 g->dbin_rank.bytes() + g->dbin_slot.bytes();
+                 g->dbin_rank.bytes() + g->dbin_slot.bytes() + g->edir.bytes();
     for (int c = 0; c < kNumClasses; ++c) b += g->tiles[c].bytes();
     return b;
 }
@@ -668,11 +694,17 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
     if (el->n_vertices == 0 || el->n_vertices >= 0xffffffffu)
         fail(TP_ERR_INVALID, "tripoll_build: n_vertices must be in [1, 2^32-1)");
     if (el->n_edges > 0 && (!el->src || !el->dst)) fail(TP_ERR_INVALID, "tripoll_build: NULL src/dst");
+    if (el->flags & ~TP_EDGES_DIRECTED) fail(TP_ERR_INVALID, "tripoll_build: unknown flags");
 
     const uint32_t n = el->n_vertices;
     const size_t M = el->n_edges;
     const int nb = std::max(1, bits_for((uint64_t)n - 1));
-    const uint64_t sentinel = (2 * nb >= 64) ? ~0ull : ((1ull << (2 * nb)) - 1);
+    // directed inputs carry one direction bit per raw edge through the pair
+    // sort and two per oriented edge through the orientation sort
+    const bool directed = (el->flags & TP_EDGES_DIRECTED) != 0;
+    const int dbit = directed ? 1 : 0, dbit2 = directed ? 2 : 0;
+    if (2 * nb + dbit2 > 64) fail(TP_ERR_UNSUPPORTED, "tripoll_build: too many vertices for directed keys");
+    const uint64_t sentinel = (2 * nb + dbit >= 64) ? ~0ull : ((1ull << (2 * nb + dbit)) - 1);
 
     auto g = std::make_unique<tp_graph>();
     TP_HIP(hipGetDevice(&g->device));
@@ -719,7 +751,7 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
     if (M) {
         const unsigned blocks = grid_for(M, kB);
         const size_t per_block = (M + blocks - 1) / blocks;
-        k_canon<<<blocks, kB, 0, s>>>(src, dst, ts, M, n, nb, sentinel, keyA.get(), valA.get(), c_bad, c_loop, bm,
+        k_canon<<<blocks, kB, 0, s>>>(src, dst, ts, M, n, nb, dbit, sentinel, keyA.get(), valA.get(), c_bad, c_loop, bm,
                                       per_block);
         TP_CHECK_LAUNCH();
     }
@@ -736,20 +768,22 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
     TP_HIP(hipEventRecord(ev[1], s));
 
     // ---- phase 1: sort by pair
-    const bool sorted_in_b = radix_sort_pairs(keyA.get(), valA.get(), keyB.get(), valB.get(), M, 2 * nb, s);
+    const bool sorted_in_b = radix_sort_pairs(keyA.get(), valA.get(), keyB.get(), valB.get(), M, 2 * nb + dbit, s);
     uint64_t *skey = sorted_in_b ? keyB.get() : keyA.get();
     uint32_t *sval = sorted_in_b ? valB.get() : valA.get();
     uint64_t *fkey = sorted_in_b ? keyA.get() : keyB.get();  // free buffers
     uint32_t *fval = sorted_in_b ? valA.get() : valB.get();
     TP_HIP(hipEventRecord(ev[2], s));
 
-    // ---- phase 2: dedup keeping the earliest time
+    // ---- phase 2: dedup keeping the earliest time (and the directions)
     uint64_t m = 0;
+    DArray<uint8_t> udir;
+    if (directed) udir.reset(Mcap, s);
     {
         const size_t nt = std::max<size_t>(1, (Mv + kCompTile - 1) / kCompTile);
         DArray<uint64_t> toff(nt + 1, s);
         if (Mv) {
-            k_dedup_count<<<(unsigned)nt, kB, 0, s>>>(skey, Mv, toff.get());
+            k_dedup_count<<<(unsigned)nt, kB, 0, s>>>(skey, Mv, dbit, toff.get());
             TP_CHECK_LAUNCH();
         } else {
             TP_HIP(hipMemsetAsync(toff.get(), 0, sizeof(uint64_t), s));
@@ -757,7 +791,7 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
         scan_u64(toff.get(), toff.get(), nt, true, s);
         m = read_scalar(toff.get() + nt, s);
         if (Mv) {
-            k_dedup_write<<<(unsigned)nt, kB, 0, s>>>(skey, sval, Mv, toff.get(), fkey, fval);
+            k_dedup_write<<<(unsigned)nt, kB, 0, s>>>(skey, sval, Mv, dbit, toff.get(), fkey, fval, udir.get());
             TP_CHECK_LAUNCH();
         }
     }
@@ -835,16 +869,17 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
     DArray<uint32_t> dplus(n, s);
     TP_HIP(hipMemsetAsync(dplus.get(), 0, n * sizeof(uint32_t), s));
     if (m) {
-        k_orient<<<grid_for(m, kB), kB, 0, s>>>(ukey, uts, m, nb, rank.get(), skey, sval);
+        k_orient<<<grid_for(m, kB), kB, 0, s>>>(ukey, uts, udir.get(), m, nb, rank.get(), skey, sval);
         TP_CHECK_LAUNCH();
     }
     rank.release();
-    const bool ob = radix_sort_pairs(skey, sval, ukey, uts, m, 2 * nb, s);
+    udir.release();
+    const bool ob = radix_sort_pairs(skey, sval, ukey, uts, m, 2 * nb + dbit2, s);
     uint64_t *okey = ob ? ukey : skey;
     uint32_t *ots = ob ? uts : sval;
     uint32_t *spare_val = ob ? sval : uts;
     if (m) {
-        k_dplus<<<grid_for(m, kB), kB, 0, s>>>(okey, m, nb, dplus.get());
+        k_dplus<<<grid_for(m, kB), kB, 0, s>>>(okey, m, nb + dbit2, dplus.get());
         TP_CHECK_LAUNCH();
     }
     TP_HIP(hipEventRecord(ev[5], s));
@@ -860,9 +895,15 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
     g->ets.reset(m + kRowPad, s);
     TP_HIP(hipMemsetAsync(g->col.get() + m, 0, kRowPad * sizeof(uint32_t), s));
     TP_HIP(hipMemsetAsync(g->ets.get() + m, 0, kRowPad * sizeof(uint32_t), s));
+    if (directed) {
+        g->directed = true;
+        g->edir.reset(m + kRowPad * 4, s);
+        TP_HIP(hipMemsetAsync(g->edir.get() + m, 0, kRowPad * 4, s));
+    }
     uint32_t *srow = spare_val;
     if (m) {
-        k_csr<<<grid_for(m, kB), kB, 0, s>>>(okey, m, nb, g->rlab.get(), g->col.get(), g->tlab.get(), srow);
+        k_csr<<<grid_for(m, kB), kB, 0, s>>>(okey, m, nb, g->rlab.get(), g->col.get(), g->tlab.get(), srow,
+                                             g->edir.get());
         TP_CHECK_LAUNCH();
         TP_HIP(hipMemcpyAsync(g->ets.get(), ots, m * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     }

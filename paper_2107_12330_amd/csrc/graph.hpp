@@ -40,6 +40,8 @@ struct tp_graph {
     tp::DArray<uint32_t> ets;     // [m] edge times
     tp::DArray<uint8_t> tlab;     // [m] label of each target
     tp::DArray<uint8_t> rlab;     // [n] label by rank
+    bool directed = false;        // built from a directed edge list
+    tp::DArray<uint8_t> edir;     // [m + pad] directed builds: bit 0 arc source -> target, bit 1 the reverse
     tp::DArray<uint32_t> perm;    // [n] rank -> original id
     uint32_t kbits = 1;           // bits of a CSR slot in an in-edge key
     tp::DArray<uint64_t> inkey;   // [n_in] (q << kbits) | k, sorted by q

@@ -226,8 +226,10 @@ void scan_u32_to_u64(const uint32_t *in, uint64_t *out, size_t n, hipStream_t s)
 
 // ================================================================ radix sort
 //
-// Reduce-then-scan LSD radix sort, 8-bit digits.  A fixed number of blocks
-// each own a contiguous chunk of tiles (4096 keys).  Per pass:
+// Reduce-then-scan LSD radix sort, 9-bit digits (52-bit pair keys take 6
+// passes; 8-bit digits took 7 and were slower overall, 10-bit digits write
+// runs too short to coalesce).  A fixed number of blocks each own a
+// contiguous chunk of tiles (4096 keys).  Per pass:
 //   1. upsweep: digit histogram of each block's chunk -> hist[digit][block]
 //   2. exclusive scan of hist (digit-major), giving each (digit, block) its
 //      first output position
@@ -241,24 +243,26 @@ constexpr int kSortBlock = 256;
 constexpr int kSortWaves = kSortBlock / kWave;
 constexpr int kSortRounds = 16;                           // keys per lane
 constexpr int kSortTile = kSortBlock * kSortRounds;       // 4096
-constexpr int kRadix = 256;
+constexpr int kRadixBits = 9;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kDigitsPerThread = kRadix / kSortBlock;
 constexpr unsigned kMaxSortBlocks = 2048;
 
-__device__ __forceinline__ unsigned digit_of(uint64_t k, int shift) { return (unsigned)(k >> shift) & 0xffu; }
+__device__ __forceinline__ unsigned digit_of(uint64_t k, int shift) { return (unsigned)(k >> shift) & (kRadix - 1); }
 
 template <class K>
 __global__ __launch_bounds__(kSortBlock) void radix_upsweep(const K *keys, size_t n, int shift,
                                                             size_t tiles_per_block, uint64_t *hist)
 {
     __shared__ unsigned cnt[kRadix];
-    cnt[threadIdx.x] = 0;
+    for (int d = threadIdx.x; d < kRadix; d += kSortBlock) cnt[d] = 0;
     __syncthreads();
     const size_t t0 = blockIdx.x * tiles_per_block;
     const size_t lo = t0 * kSortTile;
     const size_t hi = std::min(n, (t0 + tiles_per_block) * kSortTile);
     for (size_t i = lo + threadIdx.x; i < hi; i += kSortBlock) atomicAdd(&cnt[digit_of(keys[i], shift)], 1u);
     __syncthreads();
-    hist[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
+    for (int d = threadIdx.x; d < kRadix; d += kSortBlock) hist[(size_t)d * gridDim.x + blockIdx.x] = cnt[d];
 }
 
 // K: uint64_t or uint32_t keys; VALS: whether 32-bit values travel with them.
@@ -280,11 +284,27 @@ __global__ __launch_bounds__(kSortBlock) void radix_downsweep(const K *keys_in, 
     const unsigned lane = lane_id();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-    grun[threadIdx.x] = offsets[(size_t)threadIdx.x * gridDim.x + blockIdx.x];
-    for (int i = 0; i < kSortWaves; ++i) wcnt[i][threadIdx.x] = 0;
+    for (int d = threadIdx.x; d < kRadix; d += kSortBlock) {
+        grun[d] = offsets[(size_t)d * gridDim.x + blockIdx.x];
+        for (int i = 0; i < kSortWaves; ++i) wcnt[i][d] = 0;
+    }
     __syncthreads();
 
     const size_t t0 = blockIdx.x * tiles_per_block;
+    // the keys and values of the next tile are requested while this one is
+    // ranked and written, so that the loads overlap the tile's work
+    K kn[kSortRounds];
+    uint32_t vn[kSortRounds];
+    auto load_tile = [&](size_t t) {
+        const size_t wl = t * kSortTile + (size_t)w * (kSortTile / kSortWaves);
+#pragma unroll
+        for (int r = 0; r < kSortRounds; ++r) {
+            const size_t i = wl + (size_t)r * kWave + lane;
+            kn[r] = i < n ? keys_in[i] : 0;
+            vn[r] = (VALS && i < n) ? vals_in[i] : 0;
+        }
+    };
+    if (t0 * kSortTile < n) load_tile(t0);
     for (size_t t = t0; t < t0 + tiles_per_block; ++t) {
         const size_t tile_lo = t * kSortTile;
         if (tile_lo >= n) break;
@@ -299,16 +319,17 @@ __global__ __launch_bounds__(kSortBlock) void radix_downsweep(const K *keys_in, 
         for (int r = 0; r < kSortRounds; ++r) {
             const size_t i = wave_lo + (size_t)r * kWave + lane;
             ok[r] = i < n;
-            k[r] = ok[r] ? keys_in[i] : 0;
-            v[r] = (VALS && ok[r]) ? vals_in[i] : 0;
+            k[r] = kn[r];
+            v[r] = vn[r];
             dg[r] = digit_of(k[r], shift);
         }
+        if (t + 1 < t0 + tiles_per_block && (t + 1) * kSortTile < n) load_tile(t + 1);
         // stable rank of every key among equal digits of this wave's quarter
 #pragma unroll
         for (int r = 0; r < kSortRounds; ++r) {
             uint64_t peers = __ballot(ok[r]);
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
+            for (int b = 0; b < kRadixBits; ++b) {
                 const bool bit = (dg[r] >> b) & 1u;
                 const uint64_t m = __ballot(bit);
                 peers &= bit ? m : ~m;
@@ -325,16 +346,25 @@ __global__ __launch_bounds__(kSortBlock) void radix_downsweep(const K *keys_in, 
         __syncthreads();
         // per-digit totals, wave bases and tile starts
         {
-            const unsigned d = threadIdx.x;
-            unsigned tot = 0;
-            for (int i = 0; i < kSortWaves; ++i) {
-                const unsigned c = wcnt[i][d];
-                wcnt[i][d] = tot;
-                tot += c;
+            unsigned loc[kDigitsPerThread];
+            unsigned sum = 0;
+#pragma unroll
+            for (int j = 0; j < kDigitsPerThread; ++j) {
+                const unsigned d = threadIdx.x * kDigitsPerThread + j;
+                unsigned tot = 0;
+                for (int i = 0; i < kSortWaves; ++i) {
+                    const unsigned c = wcnt[i][d];
+                    wcnt[i][d] = tot;
+                    tot += c;
+                }
+                tcount[d] = tot;
+                loc[j] = sum;
+                sum += tot;
             }
-            tcount[d] = tot;
             unsigned total;
-            tstart[d] = block_excl_scan<kSortBlock>(tot, scan_tmp, total);
+            const unsigned base = block_excl_scan<kSortBlock>(sum, scan_tmp, total);
+#pragma unroll
+            for (int j = 0; j < kDigitsPerThread; ++j) tstart[threadIdx.x * kDigitsPerThread + j] = base + loc[j];
         }
         __syncthreads();
 #pragma unroll
@@ -355,8 +385,10 @@ __global__ __launch_bounds__(kSortBlock) void radix_downsweep(const K *keys_in, 
             if (VALS) vals_out[dst] = sval[i];
         }
         __syncthreads();
-        grun[threadIdx.x] += tcount[threadIdx.x];
-        for (int i = 0; i < kSortWaves; ++i) wcnt[i][threadIdx.x] = 0;
+        for (int d = threadIdx.x; d < kRadix; d += kSortBlock) {
+            grun[d] += tcount[d];
+            for (int i = 0; i < kSortWaves; ++i) wcnt[i][d] = 0;
+        }
         __syncthreads();
     }
 }
@@ -371,7 +403,7 @@ bool radix_sort(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, size_t
     const size_t tpb = (tiles + nb - 1) / nb;
     DArray<uint64_t> hist((size_t)kRadix * nb, s);
     bool in_alt = false;
-    for (int shift = begin_bit; shift < begin_bit + bits; shift += 8) {
+    for (int shift = begin_bit; shift < begin_bit + bits; shift += kRadixBits) {
         const K *ki = in_alt ? keys_alt : keys;
         const uint32_t *vi = in_alt ? vals_alt : vals;
         K *ko = in_alt ? keys : keys_alt;

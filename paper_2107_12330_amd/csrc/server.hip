@@ -272,10 +272,11 @@ void check_served_spec(tp_server *srv, const tp_graph *g, const tp_survey_spec *
 {
     if (!sp) fail(TP_ERR_INVALID, "tripoll_server_submit: NULL spec");
     const uint32_t known = TP_OUT_COUNT | TP_OUT_CLOSE_HIST | TP_OUT_LABEL_TABLE | TP_OUT_SPREAD_COUNT |
-                           TP_OUT_OPEN_CLOSE | TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE;
+                           TP_OUT_OPEN_CLOSE | TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE | TP_OUT_DIRECTED;
     if (sp->outputs & ~known) fail(TP_ERR_INVALID, "tripoll_server_submit: unknown output bits");
-    if (sp->outputs & (TP_OUT_OPEN_CLOSE | TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE))
-        fail(TP_ERR_UNSUPPORTED, "tripoll_server_submit: the open/close, max-edge and degree tables are not served");
+    if (sp->outputs & (TP_OUT_OPEN_CLOSE | TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE | TP_OUT_DIRECTED))
+        fail(TP_ERR_UNSUPPORTED,
+             "tripoll_server_submit: the open/close, max-edge, degree and directed tables are not served");
     if (sp->filters & ~(TP_FILT_WINDOW | TP_FILT_LABEL_MASK))
         fail(TP_ERR_INVALID, "tripoll_server_submit: unknown filter bits");
     if (sp->strategy > TP_STRAT_TABLE_STRESS) fail(TP_ERR_INVALID, "tripoll_server_submit: unknown strategy");

@@ -94,6 +94,11 @@ struct SurveyParams {
     uint32_t maxe_words;      // 1024 if MAX_EDGE else 0
     uint32_t deg_words;       // entries of the degree table in LDS (0 if unused)
     uint32_t max_edge_shift;  // MAX_EDGE bin width 2^max_edge_shift
+    uint32_t copies;          // copies of the histogram and table counters (1, 2 or 4)
+    uint32_t dir_words;       // 8 if DIRECTED else 0
+    uint32_t o_dir;
+    const uint8_t *edir;      // directions of the oriented edges (directed builds)
+    uint8_t dir_type[64];     // triangle type by dir(p,q) << 4 | dir(p,r) << 2 | dir(q,r); 7 for none
     unsigned long long *part_edge;  // participation: one counter per CSR slot
     const uint32_t *dbin_rank;  // [32] first rank of degree bin >= k (DEGREE_TABLE)
     const uint64_t *dbin_slot;  // [32] first CSR slot of a rank of degree bin >= k
@@ -110,6 +115,7 @@ struct SurveyParams {
     uint32_t *enum_out;
     uint64_t enum_cap;
     unsigned long long *enum_count;
+    const uint32_t *enum_srow;  // row (pivot rank) of every CSR slot
     const uint64_t *enum_tile_base;
     unsigned *enum_tile_cursor;
     unsigned *enum_tile_count;
@@ -129,13 +135,16 @@ struct SurveyParams {
 // and slot counts exist in the participation form only, which has no rings.
 struct LdsLayout {
     uint32_t slots;
-    size_t off_hts, off_hlab, off_hpos, off_hcnt, off_ring, off_cnt, off_lut, total;
+    size_t off_hts, off_hlab, off_hdir, off_hpos, off_hcnt, off_ring, off_cnt, off_lut, total;
 };
+// (the enumeration form keeps each key's original id where participation
+// keeps row positions)
 
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 __host__ __device__ inline LdsLayout lds_layout(uint32_t slots, bool meta, uint32_t counter_words, int waves,
-                                                uint32_t lut_shift, bool part = false)
+                                                uint32_t lut_shift, bool part = false, bool dir = false,
+                                                bool ids = false)
 {
     LdsLayout L;
     L.slots = slots;
@@ -144,9 +153,11 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t slots, bool meta, uint3
     if (meta) o += (size_t)slots * 4;
     L.off_hlab = o;
     if (meta) o += slots;
+    L.off_hdir = o;
+    if (dir) o += slots;
     o = align_up(o, 16);
     L.off_hpos = o;
-    if (part) o += (size_t)slots * 4;
+    if (part || ids) o += (size_t)slots * 4;
     L.off_hcnt = o;
     if (part) o += (size_t)slots * 4;
     L.off_ring = o;
@@ -160,13 +171,36 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t slots, bool meta, uint3
 }
 
 // Counters of a workgroup: [close hist 32][label table][open/close]
-// [max-edge bins][degree table]; the last two in the extended form only.
-// A multi-request pass holds one batch-layout block per request slot.
+// [max-edge bins][degree table][directed types]; the last three in the
+// extended form only.  The histogram and the table, which most hits update,
+// are held in P.copies interleaved copies (bin b, copy c at b * copies + c;
+// lane l adds to copy l % copies), so that the lanes of a wave that hit the
+// same bin spread over several LDS addresses (4 copies: scale-26 survey
+// 485 -> 444 ms).  The host takes 4, 2 or 1 copies, whichever fits LDS.  A
+// multi-request pass holds one batch-layout block per request slot.
+constexpr uint32_t kMaxCopies = 4;
+
+struct CounterBase {
+    uint32_t table, oc, maxe, deg, dir, total;
+};
+
+__host__ __device__ inline CounterBase counter_base(const SurveyParams &P, bool ext)
+{
+    CounterBase b;
+    b.table = 32 * P.copies;
+    b.oc = b.table + P.table_words * P.copies;
+    b.maxe = b.oc + P.oc_words;
+    b.deg = b.maxe + (ext ? P.maxe_words : 0u);
+    b.dir = b.deg + (ext ? P.deg_words : 0u);
+    b.total = b.dir + (ext ? P.dir_words : 0u);
+    return b;
+}
+
 template <bool MULTI, int FORM>
 __host__ __device__ inline uint32_t counter_words(const SurveyParams &P)
 {
     if (MULTI) return P.n_slots * P.slot_words;
-    return 32 + P.table_words + P.oc_words + (FORM == kFormExt ? P.maxe_words + P.deg_words : 0u);
+    return counter_base(P, FORM == kFormExt).total;
 }
 
 __device__ __forceinline__ uint32_t close_bin(uint32_t d)
@@ -190,6 +224,7 @@ struct Hit {
     uint32_t t_pq, t_pr, t_qr;
     uint32_t l_p, l_q, l_r;
     uint32_t b_p, b_q, b_r;  // degree bins (DEGREE_TABLE only)
+    uint32_t dtype;          // directed type (DIRECTED only)
 };
 
 // Reduce one triangle into the workgroup's counters.  Returns 1 if it passed
@@ -234,20 +269,24 @@ __device__ __forceinline__ uint32_t reduce_hit(const SurveyParams &P, const Hit 
     const uint32_t t1 = min(min(h.t_pq, h.t_pr), h.t_qr);
     const uint32_t t3 = max(max(h.t_pq, h.t_pr), h.t_qr);
     const uint32_t close = t3 - t1;
-    if (P.outputs & TP_OUT_CLOSE_HIST) atomicAdd(&cnt[close_bin(close)], 1ull);
-    if (P.outputs & TP_OUT_LABEL_TABLE) atomicAdd(&cnt[32 + idx], 1ull);
+    const CounterBase B = counter_base(P, EXT);
+    const uint32_t cp = lane_id() & (P.copies - 1);
+    if (P.outputs & TP_OUT_CLOSE_HIST) atomicAdd(&cnt[close_bin(close) * P.copies + cp], 1ull);
+    if (P.outputs & TP_OUT_LABEL_TABLE) atomicAdd(&cnt[B.table + idx * P.copies + cp], 1ull);
     if (P.outputs & TP_OUT_SPREAD_COUNT) spread += (P.spread_any && close <= P.spread_le) ? 1u : 0u;
     if (P.outputs & TP_OUT_OPEN_CLOSE) {
         const uint32_t t2 = h.t_pq + h.t_pr + h.t_qr - t1 - t3;  // exact in uint32 arithmetic mod 2^32
-        atomicAdd(&cnt[32 + P.table_words + close_bin(t2 - t1) * 32 + close_bin(close)], 1ull);
+        atomicAdd(&cnt[B.oc + close_bin(t2 - t1) * 32 + close_bin(close)], 1ull);
     }
     if (EXT && (P.outputs & TP_OUT_MAX_EDGE)) {
         // Algorithm 3: vertex labels pairwise distinct; bin of the largest edge time
         if (h.l_p != h.l_q && h.l_q != h.l_r && h.l_p != h.l_r)
-            atomicAdd(&cnt[32 + P.table_words + P.oc_words + min(t3 >> P.max_edge_shift, 1023u)], 1ull);
+            atomicAdd(&cnt[B.maxe + min(t3 >> P.max_edge_shift, 1023u)], 1ull);
     }
     if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE))
-        atomicAdd(&cnt[32 + P.table_words + P.oc_words + P.maxe_words + multiset_index(h.b_p, h.b_q, h.b_r)], 1ull);
+        atomicAdd(&cnt[B.deg + multiset_index(h.b_p, h.b_q, h.b_r)], 1ull);
+    if (EXT && (P.outputs & TP_OUT_DIRECTED))
+        atomicAdd(&cnt[B.dir + h.dtype], 1ull);
     return 1;
 }
 
@@ -341,6 +380,7 @@ struct RecBlock {
     uint64_t key;   // (q << kbits) | k
     uint32_t pay;   // rest of p's row | label(p) << 24
     uint32_t t_pq;  // time(p, q)
+    uint32_t p;     // rank of p (enumeration)
 };
 
 // LOG_SLOTS > 0: LDS hash of Adj+(q) with 2^LOG_SLOTS slots at most.
@@ -376,7 +416,8 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     constexpr bool PART = FORM == kFormPart;
     static_assert(!(EXT || PART) || (META && !ENUM && !MULTI), "extended forms are single-request metadata surveys");
     const uint32_t nc = counter_words<MULTI, FORM>(P);
-    const LdsLayout L = lds_layout(kSlots * kGroups, META || ENUM, nc * kGroups, kWaves, P.lut_shift, PART);
+    const bool kdir = EXT && P.dir_words;  // the directed census
+    const LdsLayout L = lds_layout(kSlots * kGroups, META || ENUM, nc * kGroups, kWaves, P.lut_shift, PART, kdir, ENUM);
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
     const int grp = WAVE ? w : 0;     // this thread's group
@@ -385,13 +426,15 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     uint32_t *hkey = reinterpret_cast<uint32_t *>(lds) + (size_t)grp * kSlots;
     uint32_t *hts = reinterpret_cast<uint32_t *>(lds + L.off_hts) + (size_t)grp * kSlots;
     uint8_t *hlab = lds + L.off_hlab + (size_t)grp * kSlots;
-    uint32_t *hpos = reinterpret_cast<uint32_t *>(lds + L.off_hpos) + (size_t)grp * kSlots;  // PART
+    uint8_t *hdir = lds + L.off_hdir + (size_t)grp * kSlots;  // EXT, directed census
+    uint32_t *hpos = reinterpret_cast<uint32_t *>(lds + L.off_hpos) + (size_t)grp * kSlots;  // PART; ENUM: ids
     uint32_t *hcnt = reinterpret_cast<uint32_t *>(lds + L.off_hcnt) + (size_t)grp * kSlots;  // PART
     unsigned long long *cnt_all = reinterpret_cast<unsigned long long *>(lds + L.off_cnt);
     unsigned long long *cnt = cnt_all + (size_t)grp * nc;
     uint16_t *lut = reinterpret_cast<uint16_t *>(lds + L.off_lut);
     __shared__ uint64_t mask_lds[13];
     __shared__ uint32_t dbin_lds[32];
+    __shared__ uint8_t dtype_lds[EXT ? 64 : 1];
     __shared__ SlotSpec slot_lds[MULTI ? kMaxSlots : 1];
     __shared__ unsigned long long s_tile;
     __shared__ uint32_t s_stash_g[kGroups], s_fail_g[kGroups];
@@ -414,6 +457,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     for (uint32_t i = tid; i < nc * kGroups; i += BLOCK) cnt_all[i] = 0;
     if (tid < 13) mask_lds[tid] = P.label_mask[tid];
     if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE) && tid < 32) dbin_lds[tid] = P.dbin_rank[tid];
+    if (EXT && tid < 64) dtype_lds[tid] = P.dir_type[tid];
     if (MULTI) {
         const uint32_t *src = reinterpret_cast<const uint32_t *>(P.slots);
         uint32_t *dst = reinterpret_cast<uint32_t *>(slot_lds);
@@ -454,12 +498,13 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 cnt[i] = 0;
                 continue;
             }
-            if (i < 32) word = P.o_hist + i;
-            else if (i < 32 + P.table_words) word = P.o_table + (i - 32);
-            else if (!EXT || i < 32 + P.table_words + P.oc_words) word = P.o_oc + (i - 32 - P.table_words);
-            else if (i < 32 + P.table_words + P.oc_words + P.maxe_words)
-                word = P.o_maxe + (i - 32 - P.table_words - P.oc_words);
-            else word = P.o_deg + (i - 32 - P.table_words - P.oc_words - P.maxe_words);
+            const CounterBase B = counter_base(P, EXT);
+            if (i < B.table) word = P.o_hist + i / P.copies;
+            else if (i < B.oc) word = P.o_table + (i - B.table) / P.copies;
+            else if (!EXT || i < B.maxe) word = P.o_oc + (i - B.oc);
+            else if (i < B.deg) word = P.o_maxe + (i - B.maxe);
+            else if (i < B.dir) word = P.o_deg + (i - B.deg);
+            else word = P.o_dir + (i - B.dir);
             atomicAdd(&blk[word], v);
             cnt[i] = 0;
         }
@@ -470,6 +515,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
 
     // the target whose out-list is in the LDS table, and its geometry
     uint32_t cur_q = 0xffffffffu;
+    uint32_t id_q = 0;  // original id of cur_q (enumeration)
     uint64_t kq = 0;
     uint32_t dq = 0, l_q = 0, log_s = 0;
     uint32_t n_stash = 0;  // keys in the stash
@@ -486,7 +532,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
         constexpr bool G = decltype(gm)::value;
         uint32_t tri = 0, spread = 0;
         Hit h{0, 0, 0, 0, 0, 0, 0, 0, 0};
-        uint32_t e_p = 0, e_r = 0;  // ranks of p and r (enumeration)
+        uint32_t e_p = 0, e_r = 0;  // original ids of p and r (enumeration)
         const bool valid = lane < count;
         if (valid) {
             const uint4 e = ring[(qh + lane) & (kRing - 1)];
@@ -505,12 +551,19 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
             if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE)) {
                 // the ring's last word holds the pivot's degree bin
                 const uint32_t r = !G ? hkey[where] : P.col[kq + where];
-                h.b_p = e.w;
+                h.b_p = e.w & 0xffu;
                 h.b_q = degree_bin_of(dbin_lds, cur_q);
                 h.b_r = degree_bin_of(dbin_lds, r);
             }
+            if (kdir) {
+                // ... and the directions of (p, q) and (p, r) above it
+                const uint32_t dqr = !G ? hdir[where] : P.edir[kq + where];
+                h.dtype = dtype_lds[(((e.w >> 8) & 3u) << 4) | (((e.w >> 10) & 3u) << 2) | (dqr & 3u)];
+            }
             if (ENUM) {
-                e_r = !G ? hkey[where] : P.col[kq + where];
+                // original ids: of r from the table (or through the CSR in
+                // HBM), of p from the ring
+                e_r = !G ? hpos[where] : P.perm[P.col[kq + where]];
                 e_p = e.w;
             } else if (!MULTI) {
                 tri = reduce_hit<EXT>(P, h, cnt, mask_lds, lut, spread);
@@ -536,9 +589,9 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                     base + __builtin_amdgcn_mbcnt_hi((uint32_t)(vm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)vm, 0u));
                 if (pass && !P.enum_tile_count && at < P.enum_cap) {
                     uint32_t *o = P.enum_out + at * 9;
-                    o[0] = P.perm[e_p];
-                    o[1] = P.perm[cur_q];
-                    o[2] = P.perm[e_r];
+                    o[0] = e_p;
+                    o[1] = id_q;
+                    o[2] = e_r;
                     o[3] = h.t_pq;
                     o[4] = h.t_pr;
                     o[5] = h.t_qr;
@@ -630,6 +683,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 kq = sload(P.rowptr + cur_q);
                 dq = (uint32_t)(sload(P.rowptr + cur_q + 1) - kq);
                 l_q = META ? __builtin_amdgcn_readfirstlane(P.rlab[cur_q]) : 0u;
+                if (ENUM) id_q = sload(P.perm + cur_q);
                 log_s = 5;
                 while ((1u << log_s) < dq + dq / 4) ++log_s;
                 // a target too large for this kernel's tables (the planner's
@@ -683,6 +737,8 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                                 hpos[h] = i;
                                 hcnt[h] = 0;
                             }
+                            if (kdir) hdir[h] = P.edir[kq + i];
+                            if (ENUM) hpos[h] = P.perm[r];
                         }
                     }
                 }
@@ -708,6 +764,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                     r.key = kb.key;
                     r.pay = kb.pay;
                     r.t_pq = (META || ENUM) ? P.ets[kb.key & kmask] : 0u;
+                    r.p = ENUM ? P.enum_srow[kb.key & kmask] : 0u;
                     return r;
                 };
                 RecBlock blk_cur = gather(kb0);
@@ -746,15 +803,17 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                         }
                         r.p = pb;
                     }
+                    if (kdir) {
+                        // direction of p -> q: the byte at slot start - 1, read
+                        // through the dword that holds it
+                        const uint64_t s0 = r.start - 1;
+                        const uint32_t wd = sload(reinterpret_cast<const uint32_t *>(P.edir + (s0 & ~3ull)));
+                        r.p |= ((wd >> ((uint32_t)(s0 & 3ull) * 8u)) & 3u) << 8;
+                    }
                     if (ENUM) {
-                        // the pivot owns the row that holds slot start - 1
-                        uint32_t a = 0, b = P.n;  // rowptr[a] <= start - 1 < rowptr[b]
-                        while (b - a > 1) {
-                            const uint32_t mid = (a + b) >> 1;
-                            if (sload(P.rowptr + mid) <= r.start - 1) a = mid;
-                            else b = mid;
-                        }
-                        r.p = a;
+                        // the pivot's original id: its rank came with the
+                        // record's other gathers
+                        r.p = sload(P.perm + __builtin_amdgcn_readlane(blk_cur.p, l));
                     }
                     return r;
                 };
@@ -807,7 +866,8 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 // issue the loads of kBatch chunks: lane l of sub-row s reads
                 // candidate 64 s + l; the buffer resource spans exactly the
                 // chunk, so lanes past its end read 0 without touching memory
-                auto prepare = [&](Chunk(&chs)[kBatch], uint32_t(&cand)[kBatch][kSub], uint32_t(&tpr)[kBatch][kSub]) {
+                auto prepare = [&](Chunk(&chs)[kBatch], uint32_t(&cand)[kBatch][kSub], uint32_t(&tpr)[kBatch][kSub],
+                                   uint32_t(&dpr)[kBatch][kSub]) {
     #pragma unroll
                     for (int c = 0; c < kBatch; ++c) {
                         const uint64_t base = next_chunk(chs[c]);
@@ -823,10 +883,20 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                             for (int sr = 0; sr < kSub; ++sr)
                                 tpr[c][sr] = __builtin_amdgcn_raw_buffer_load_b32(rt, lane * 4u + sr * 256u, 0, 0);
                         }
+                        if constexpr (EXT) {
+                            if (kdir) {
+                                // directions of (p, r), one byte per candidate
+                                const auto rd = __builtin_amdgcn_make_buffer_rsrc((void *)(P.edir + base), (short)0,
+                                                                                  chs[c].n, kRsrcWord3);
+    #pragma unroll
+                                for (int sr = 0; sr < kSub; ++sr)
+                                    dpr[c][sr] = __builtin_amdgcn_raw_buffer_load_b8(rd, lane + sr * 64u, 0, 0);
+                            }
+                        }
                     }
                 };
                 auto process = [&](const Chunk(&chs)[kBatch], const uint32_t(&cand)[kBatch][kSub],
-                                   const uint32_t(&tpr)[kBatch][kSub]) {
+                                   const uint32_t(&tpr)[kBatch][kSub], const uint32_t(&dpr)[kBatch][kSub]) {
     #pragma unroll
                     for (int c = 0; c < kBatch; ++c) {
     #pragma unroll
@@ -900,7 +970,8 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                                     const uint32_t below = __builtin_amdgcn_mbcnt_hi(
                                         (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                                     ring[(qt + below) & (kRing - 1)] =
-                                        make_uint4(slot | (chs[c].l_p << 22), tpr[c][sr], chs[c].t_pq, chs[c].p);
+                                        make_uint4(slot | (chs[c].l_p << 22), tpr[c][sr], chs[c].t_pq,
+                                                   EXT && kdir ? chs[c].p | ((dpr[c][sr] & 3u) << 10) : chs[c].p);
                                 }
                                 // the ring cursors are wave-uniform: keep them in scalar registers
                                 qt = __builtin_amdgcn_readfirstlane(qt + (uint32_t)__popcll(m));
@@ -913,13 +984,14 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 // the current batch is probed
                 Chunk rA[kBatch], rB[kBatch];
                 uint32_t cA[kBatch][kSub], tA[kBatch][kSub], cB[kBatch][kSub], tB[kBatch][kSub];
-                prepare(rA, cA, tA);
+                uint32_t dA[kBatch][kSub], dB[kBatch][kSub];  // extended form, directed census
+                prepare(rA, cA, tA, dA);
                 for (;;) {
-                    prepare(rB, cB, tB);
-                    process(rA, cA, tA);
+                    prepare(rB, cB, tB, dB);
+                    process(rA, cA, tA, dA);
                     if (rB[0].n == 0) break;
-                    prepare(rA, cA, tA);
-                    process(rB, cB, tB);
+                    prepare(rA, cA, tA, dA);
+                    process(rB, cB, tB, dB);
                     if (rA[0].n == 0) break;
                 }
                 if (lane == 0) {
@@ -947,6 +1019,24 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
 __global__ void zero_u64(unsigned long long *p, size_t n)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// The row (pivot rank) of every CSR slot, for enumeration: one wave per row.
+__global__ void k_slot_rows(const uint64_t *rowptr, uint32_t n, uint32_t *srow)
+{
+    const size_t waves = (size_t)gridDim.x * blockDim.x / kWave;
+    for (size_t v = (blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave; v < n; v += waves) {
+        const uint64_t b = rowptr[v], e = rowptr[v + 1];
+        for (uint64_t i = b + lane_id(); i < e; i += kWave) srow[i] = (uint32_t)v;
+    }
+}
+
+void slot_rows(const tp_graph *g, DArray<uint32_t> &srow, hipStream_t s)
+{
+    srow.reset(std::max<uint64_t>(g->m, 1), s);
+    if (!g->m) return;
+    k_slot_rows<<<grid_for((size_t)g->n * kWave, 256), 256, 0, s>>>(g->rowptr.get(), g->n, srow.get());
+    TP_CHECK_LAUNCH();
 }
 
 // Largest of n uint32 values into *out (zeroed by the caller).
@@ -978,20 +1068,24 @@ __global__ void k_enum_chunk(const uint64_t *base, uint64_t n_tiles, uint64_t t0
 }
 
 // Vertex participation from edge participation: each triangle at v holds
-// two of v's edges, so twice v's count is the sum over its edges.  One
-// thread per row adds the row's counts to its source and each to its target.
+// two of v's edges, so twice v's count is the sum over its edges.  One wave
+// per row adds each count to the edge's target and the row's sum to its
+// source (a thread per row left hub rows to single threads).
 __global__ void k_part_rows(const uint64_t *rowptr, const uint32_t *col, uint32_t n, const unsigned long long *edge,
                             unsigned long long *acc)
 {
-    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < n; v += (size_t)gridDim.x * blockDim.x) {
+    const size_t waves = (size_t)gridDim.x * blockDim.x / kWave;
+    for (size_t v = (blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave; v < n; v += waves) {
+        const uint64_t b = rowptr[v], e = rowptr[v + 1];
         unsigned long long sum = 0;
-        for (uint64_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
-            const unsigned long long c = edge[e];
+        for (uint64_t i = b + lane_id(); i < e; i += kWave) {
+            const unsigned long long c = edge[i];
             if (!c) continue;
             sum += c;
-            atomicAdd(&acc[col[e]], c);
+            atomicAdd(&acc[col[i]], c);
         }
-        if (sum) atomicAdd(&acc[v], sum);
+        sum = wave_sum(sum);
+        if (lane_id() == 0 && sum) atomicAdd(&acc[v], sum);
     }
 }
 
@@ -1013,7 +1107,9 @@ size_t lds_need(const SurveyParams &P)
     constexpr uint32_t groups = WAVE ? BLOCK / kWave : 1;
     const uint32_t slots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
     const uint32_t nc = counter_words<MULTI, FORM>(P);
-    return lds_layout(slots * groups, META || ENUM, nc * groups, BLOCK / kWave, P.lut_shift, FORM == kFormPart).total;
+    return lds_layout(slots * groups, META || ENUM, nc * groups, BLOCK / kWave, P.lut_shift, FORM == kFormPart,
+                      FORM == kFormExt && P.dir_words, ENUM)
+        .total;
 }
 
 template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM>
@@ -1024,7 +1120,7 @@ void launch_class(const SurveyParams &P, hipStream_t s, int device)
     const uint32_t slots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
     const uint32_t nc = counter_words<MULTI, FORM>(P);
     const LdsLayout L = lds_layout(slots * groups, META || ENUM, nc * groups, BLOCK / kWave, P.lut_shift,
-                                   FORM == kFormPart);
+                                   FORM == kFormPart, FORM == kFormExt && P.dir_words, ENUM);
     if (L.total > kLdsLimit)
         fail(TP_ERR_UNSUPPORTED, "tripoll_survey: the requested outputs need more LDS than a workgroup may hold");
     auto kern = survey_kernel<LOG_SLOTS, BLOCK, WAVE, META, ENUM, MULTI, FORM>;
@@ -1072,8 +1168,27 @@ uint32_t resolve_variant(const tp_graph *g, int c, uint32_t strategy)
 }
 
 template <bool META, bool ENUM, bool MULTI = false, int FORM = kFormSurvey>
-void launch_variant(int c, uint32_t v, const SurveyParams &P, hipStream_t s, int device)
+void launch_variant(int c, uint32_t v, const SurveyParams &P0, hipStream_t s, int device)
 {
+    // as many counter copies as the class's tables leave LDS for; a batch
+    // keeps one copy, since its workgroups merge their counters at every
+    // change of graph
+    SurveyParams P = P0;
+    if (!P.rank_gid) {
+        const uint32_t log_slots = v == TP_VAR_WAVE_TABLE ? kTinyLogSlots
+                                   : v == TP_VAR_GROUP_TABLE ? (c == kClassLarge ? kLargeLogSlots : kSmallLogSlots)
+                                                             : 0;
+        const bool wave = v == TP_VAR_WAVE_TABLE || v == TP_VAR_WAVE_SEARCH;
+        for (P.copies = kMaxCopies; P.copies > 1; P.copies /= 2) {
+            size_t need = 0;
+            if (log_slots == kTinyLogSlots && wave) need = lds_need<kTinyLogSlots, kSmallBlock, true, META, ENUM, MULTI, FORM>(P);
+            else if (log_slots == kLargeLogSlots) need = lds_need<kLargeLogSlots, kLargeBlock, false, META, ENUM, MULTI, FORM>(P);
+            else if (log_slots == kSmallLogSlots) need = lds_need<kSmallLogSlots, kSmallBlock, false, META, ENUM, MULTI, FORM>(P);
+            else if (wave) need = lds_need<0, kSmallBlock, true, META, ENUM, MULTI, FORM>(P);
+            else need = lds_need<0, kSmallBlock, false, META, ENUM, MULTI, FORM>(P);
+            if (need <= kLdsLimit) break;
+        }
+    }
     // a table variant whose tables and counters together overflow LDS (large
     // degree tables) searches Adj+(q) in HBM instead
     // (per-wave forms hold counters per wave, so they overflow first)
@@ -1125,13 +1240,15 @@ void validate_spec(const tp_graph *g, const tp_survey_spec *sp)
 {
     if (!g || !sp) fail(TP_ERR_INVALID, "tripoll_survey: NULL argument");
     const uint32_t known = TP_OUT_COUNT | TP_OUT_CLOSE_HIST | TP_OUT_LABEL_TABLE | TP_OUT_SPREAD_COUNT |
-                           TP_OUT_OPEN_CLOSE | TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE;
+                           TP_OUT_OPEN_CLOSE | TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE | TP_OUT_DIRECTED;
     if (sp->outputs & ~known) fail(TP_ERR_INVALID, "tripoll_survey: unknown output bits");
     if (sp->reserved != 0) fail(TP_ERR_INVALID, "tripoll_survey: reserved field must be 0");
     if ((sp->outputs & TP_OUT_MAX_EDGE) && sp->max_edge_shift > 31)
         fail(TP_ERR_INVALID, "tripoll_survey: max_edge_shift must be in 0..31");
-    if ((sp->outputs & (TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE)) && g->n_graphs)
-        fail(TP_ERR_UNSUPPORTED, "tripoll_survey: max-edge and degree tables are not produced for batches");
+    if ((sp->outputs & (TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE | TP_OUT_DIRECTED)) && g->n_graphs)
+        fail(TP_ERR_UNSUPPORTED, "tripoll_survey: max-edge, degree and directed tables are not produced for batches");
+    if ((sp->outputs & TP_OUT_DIRECTED) && !g->directed)
+        fail(TP_ERR_INVALID, "tripoll_survey: the directed census needs a graph built with TP_EDGES_DIRECTED");
     if (sp->filters & ~(TP_FILT_WINDOW | TP_FILT_LABEL_MASK)) fail(TP_ERR_INVALID, "tripoll_survey: unknown filter bits");
     if (sp->strategy > TP_STRAT_TABLE_STRESS) fail(TP_ERR_INVALID, "tripoll_survey: unknown strategy");
     const bool labels = (sp->outputs & TP_OUT_LABEL_TABLE) || (sp->filters & TP_FILT_LABEL_MASK);
@@ -1144,6 +1261,32 @@ void validate_spec(const tp_graph *g, const tp_survey_spec *sp)
     }
     if ((sp->filters & TP_FILT_WINDOW) && sp->t_lo > sp->t_hi)
         fail(TP_ERR_INVALID, "tripoll_survey: t_lo > t_hi");
+}
+
+// Type of a triangle p <+ q <+ r in the triad census, from the direction
+// bits of its three oriented edges (bit 0: an arc from the lower rank, bit 1:
+// one towards it): by the number of arcs, then by in- and out-degrees.
+// 7 (no counter) when an edge has no direction.
+uint8_t directed_type(uint32_t dpq, uint32_t dpr, uint32_t dqr)
+{
+    if (!dpq || !dpr || !dqr) return 7;
+    int out[3] = {0, 0, 0}, in[3] = {0, 0, 0}, arcs = 0;
+    auto add = [&](uint32_t d, int a, int b) {
+        if (d & 1u) { ++out[a]; ++in[b]; ++arcs; }
+        if (d & 2u) { ++out[b]; ++in[a]; ++arcs; }
+    };
+    add(dpq, 0, 1);
+    add(dpr, 0, 2);
+    add(dqr, 1, 2);
+    if (arcs == 3) return (out[0] == 1 && out[1] == 1 && out[2] == 1) ? 1 : 0;  // 030C, else 030T
+    if (arcs == 4) {
+        for (int v = 0; v < 3; ++v)
+            if (in[v] == 0) return 2;   // 120D: one vertex sends both its arcs
+        for (int v = 0; v < 3; ++v)
+            if (out[v] == 0) return 3;  // 120U: one vertex receives both
+        return 4;                       // 120C
+    }
+    return arcs == 5 ? 5 : 6;           // 210, 300
 }
 
 SurveyParams make_params(const tp_graph *g, const tp_survey_spec *sp, unsigned long long *out,
@@ -1176,10 +1319,15 @@ SurveyParams make_params(const tp_graph *g, const tp_survey_spec *sp, unsigned l
     P.oc_words = (sp->outputs & TP_OUT_OPEN_CLOSE) ? 1024 : 0;
     P.maxe_words = (sp->outputs & TP_OUT_MAX_EDGE) ? TP_MAX_EDGE_BINS : 0;
     P.max_edge_shift = sp->max_edge_shift;
+    P.copies = 1;  // raised per launch where LDS allows
     // the degree table needs only the bins up to bin(d_max)
     P.deg_words = ((sp->outputs & TP_OUT_DEGREE_TABLE) && !g->n_graphs) ? table_size(g->dbin_values) : 0;
     P.dbin_rank = g->dbin_rank.get();
     P.dbin_slot = g->dbin_slot.get();
+    P.dir_words = ((sp->outputs & TP_OUT_DIRECTED) && g->directed && !g->n_graphs) ? 8u : 0u;
+    P.o_dir = TP_RW_DIRECTED;
+    P.edir = g->edir.get();
+    for (uint32_t i = 0; i < 64; ++i) P.dir_type[i] = directed_type(i >> 4, (i >> 2) & 3u, i & 3u);
     // close < spread_lt  <=>  close <= spread_lt - 1 (close is a uint32)
     P.spread_any = sp->spread_lt > 0;
     P.spread_le = sp->spread_lt == 0 ? 0u : (uint32_t)std::min<uint64_t>(sp->spread_lt - 1, 0xffffffffull);
@@ -1205,13 +1353,17 @@ bool needs_meta(const tp_survey_spec *sp)
     return (sp->outputs & ~TP_OUT_COUNT) != 0 || sp->filters != 0;
 }
 
-bool needs_ext(const tp_survey_spec *sp) { return (sp->outputs & (TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE)) != 0; }
+bool needs_ext(const tp_survey_spec *sp)
+{
+    return (sp->outputs & (TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE | TP_OUT_DIRECTED)) != 0;
+}
 
 // Enqueue a whole survey into the caller's result buffer (which also holds
 // the tile counter).  Allocates nothing.
 template <bool ENUM>
 void survey_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned long long *dev_out, hipStream_t s,
-                    uint32_t *enum_out = nullptr, uint64_t enum_cap = 0, EventTimer *timers = nullptr)
+                    uint32_t *enum_out = nullptr, uint64_t enum_cap = 0, EventTimer *timers = nullptr,
+                    const uint32_t *enum_srow = nullptr)
 {
     zero_u64<<<grid_for(TP_RESULT_WORDS, 256), 256, 0, s>>>(dev_out, TP_RESULT_WORDS);
     TP_CHECK_LAUNCH();
@@ -1221,6 +1373,7 @@ void survey_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned long l
         P.enum_out = enum_out;
         P.enum_cap = enum_cap;
         P.enum_count = dev_out + TP_RW_SCRATCH + 1;
+        P.enum_srow = enum_srow;
         launch_all<true, true>(g, P, TP_STRAT_AUTO, s);
     } else if (needs_ext(sp)) {
         launch_all<true, false, kFormExt>(g, P, sp->strategy, s, timers);
@@ -1245,8 +1398,8 @@ uint32_t graph_count(const tp_graph *g) { return g->n_graphs ? g->n_graphs : 1u;
 // `dev_out`, followed by the tile counter.  Allocates nothing.
 void survey_batch_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned long long *dev_out, hipStream_t s)
 {
-    if (sp->outputs & (TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE))
-        fail(TP_ERR_UNSUPPORTED, "tripoll_survey_batch: max-edge and degree tables have no place in a batch block");
+    if (sp->outputs & (TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE | TP_OUT_DIRECTED))
+        fail(TP_ERR_UNSUPPORTED, "tripoll_survey_batch: max-edge, degree and directed tables have no place in a batch block");
     const uint32_t words = batch_words(sp);
     const uint64_t total = (uint64_t)graph_count(g) * words + TP_BATCH_SCRATCH_WORDS;
     zero_u64<<<grid_for(total, 256), 256, 0, s>>>(dev_out, total);
@@ -1278,6 +1431,7 @@ void copy_result(const std::vector<unsigned long long> &h, tp_survey_result *out
     for (int i = 0; i < 1024; ++i) out->open_close[i] = h[TP_RW_OPEN_CLOSE + i];
     for (uint32_t i = 0; i < TP_MAX_EDGE_BINS; ++i) out->max_edge[i] = h[TP_RW_MAX_EDGE + i];
     for (uint32_t i = 0; i < TP_DEGREE_MAX; ++i) out->degree_table[i] = h[TP_RW_DEGREE + i];
+    for (uint32_t i = 0; i < 7; ++i) out->directed[i] = h[TP_RW_DIRECTED + i];
 }
 
 }  // namespace
@@ -1327,7 +1481,9 @@ extern "C" tp_status tripoll_enumerate(const tp_graph *g, uint32_t *dev_records,
         tp_survey_spec sp{};
         sp.outputs = TP_OUT_COUNT;
         DArray<unsigned long long> res(TP_RESULT_WORDS, s);
-        survey_enqueue<true>(g, &sp, res.get(), s, dev_records, capacity);
+        DArray<uint32_t> srow;
+        slot_rows(g, srow, s);
+        survey_enqueue<true>(g, &sp, res.get(), s, dev_records, capacity, nullptr, srow.get());
         unsigned long long found = 0;
         TP_HIP(hipMemcpyAsync(&found, res.get() + TP_RW_TRIANGLES, 8, hipMemcpyDeviceToHost, s));
         TP_HIP(hipStreamSynchronize(s));
@@ -1344,6 +1500,7 @@ struct tp_enum_stream {
     DArray<unsigned> cursor;     // [n_tiles] records written per tile
     DArray<unsigned long long> res;
     DArray<uint64_t> chunk;      // [3] result of k_enum_chunk
+    DArray<uint32_t> srow;       // [m] pivot of every CSR slot
 };
 
 namespace {
@@ -1382,6 +1539,7 @@ extern "C" tp_status tripoll_enum_open(const tp_graph *g, const tp_survey_spec *
         e->cursor.reset(std::max<uint64_t>(T, 1), s);
         e->res.reset(TP_RESULT_WORDS, s);
         e->chunk.reset(3, s);
+        slot_rows(g, e->srow, s);
         DArray<unsigned> count(std::max<uint64_t>(T, 1), s);
         zero_u64<<<grid_for(TP_RESULT_WORDS, 256), 256, 0, s>>>(e->res.get(), TP_RESULT_WORDS);
         TP_CHECK_LAUNCH();
@@ -1391,6 +1549,7 @@ extern "C" tp_status tripoll_enum_open(const tp_graph *g, const tp_survey_spec *
             // one counting pass: the records of every tile
             SurveyParams P = make_params(g, &e->spec, e->res.get(), e->res.get() + TP_RW_SCRATCH);
             P.enum_tile_count = count.get();
+            P.enum_srow = e->srow.get();
             enum_tiles(e.get(), P, 0, T, s);
         }
         if (T) scan_u32_to_u64(count.get(), e->base.get(), T, s);
@@ -1451,6 +1610,7 @@ extern "C" tp_status tripoll_enum_next(tp_enum_stream *e, uint32_t *dev_records,
         P.enum_cap = capacity;
         P.enum_tile_base = e->base.get();
         P.enum_tile_cursor = e->cursor.get();
+        P.enum_srow = e->srow.get();
         P.enum_chunk_base = c[1];
         enum_tiles(e, P, e->next, t1, s);
         TP_HIP(hipStreamSynchronize(s));
@@ -1495,7 +1655,8 @@ extern "C" tp_status tripoll_participation(const tp_graph *g, const tp_survey_sp
             DArray<unsigned long long> acc(g->n, s);
             zero_u64<<<grid_for(g->n, 256), 256, 0, s>>>(acc.get(), g->n);
             TP_CHECK_LAUNCH();
-            k_part_rows<<<grid_for(g->n, 256), 256, 0, s>>>(g->rowptr.get(), g->col.get(), g->n, edge, acc.get());
+            k_part_rows<<<grid_for((size_t)g->n * kWave, 256), 256, 0, s>>>(g->rowptr.get(), g->col.get(), g->n, edge,
+                                                                           acc.get());
             TP_CHECK_LAUNCH();
             k_part_vertex<<<grid_for(g->n, 256), 256, 0, s>>>(acc.get(), g->perm.get(), g->n, vertex_counts);
             TP_CHECK_LAUNCH();

@@ -22,7 +22,9 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "OOM", 3: "DEVICE", 4: "BUSY", 5: "UNS
 TP_MEM_HOST, TP_MEM_DEVICE = 0, 1
 TP_TIE_MIX, TP_TIE_ID = 0, 1
 TP_OUT_COUNT, TP_OUT_CLOSE_HIST, TP_OUT_LABEL_TABLE, TP_OUT_SPREAD_COUNT, TP_OUT_OPEN_CLOSE = 1, 2, 4, 8, 16
-TP_OUT_MAX_EDGE, TP_OUT_DEGREE_TABLE = 32, 64
+TP_OUT_MAX_EDGE, TP_OUT_DEGREE_TABLE, TP_OUT_DIRECTED = 32, 64, 128
+TP_EDGES_DIRECTED = 1
+DIRECTED_TYPES = ("030T", "030C", "120D", "120U", "120C", "210", "300")
 TP_FILT_WINDOW, TP_FILT_LABEL_MASK = 1, 2
 TP_STRAT_AUTO, TP_STRAT_GLOBAL_SEARCH, TP_STRAT_TABLE_STRESS = 0, 1, 2
 TP_VAR_DEFAULT, TP_VAR_WAVE_TABLE, TP_VAR_GROUP_TABLE, TP_VAR_SEARCH, TP_VAR_WAVE_SEARCH = 0, 1, 2, 3, 4
@@ -36,20 +38,21 @@ TP_RW_TABLE = TP_RW_HIST + 32
 TP_RW_OPEN_CLOSE = TP_RW_TABLE + TP_TABLE_MAX
 TP_RW_MAX_EDGE = TP_RW_OPEN_CLOSE + 1024
 TP_RW_DEGREE = TP_RW_MAX_EDGE + TP_MAX_EDGE_BINS
-TP_RW_SCRATCH = TP_RW_DEGREE + TP_DEGREE_MAX
+TP_RW_DIRECTED = TP_RW_DEGREE + TP_DEGREE_MAX
+TP_RW_SCRATCH = TP_RW_DIRECTED + 8
 TP_RESULT_WORDS = TP_RW_SCRATCH + 4
 TP_BW_TRIANGLES, TP_BW_SPREAD, TP_BW_PROBES, TP_BW_HIST, TP_BW_TABLE = 0, 1, 2, 3, 35
 TP_BATCH_SCRATCH_WORDS = 4
 
 OUT_BITS = {"count": TP_OUT_COUNT, "close_hist": TP_OUT_CLOSE_HIST, "label_table": TP_OUT_LABEL_TABLE,
             "spread_count": TP_OUT_SPREAD_COUNT, "open_close": TP_OUT_OPEN_CLOSE,
-            "max_edge": TP_OUT_MAX_EDGE, "degree_table": TP_OUT_DEGREE_TABLE}
+            "max_edge": TP_OUT_MAX_EDGE, "degree_table": TP_OUT_DEGREE_TABLE, "directed": TP_OUT_DIRECTED}
 
 
 class tp_edge_list(ctypes.Structure):
     _fields_ = [("n_vertices", ctypes.c_uint32), ("mem_space", ctypes.c_uint32), ("n_edges", ctypes.c_uint64),
                 ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("edge_time", ctypes.c_void_p),
-                ("vertex_label", ctypes.c_void_p), ("tie_hash", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("vertex_label", ctypes.c_void_p), ("tie_hash", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 class tp_batch_edges(ctypes.Structure):
@@ -81,7 +84,8 @@ class tp_survey_result(ctypes.Structure):
     _fields_ = [("triangles", ctypes.c_uint64), ("spread_count", ctypes.c_uint64), ("probes", ctypes.c_uint64),
                 ("close_hist", ctypes.c_uint64 * 32), ("label_table", ctypes.c_uint64 * TP_TABLE_MAX),
                 ("open_close", ctypes.c_uint64 * 1024), ("max_edge", ctypes.c_uint64 * TP_MAX_EDGE_BINS),
-                ("degree_table", ctypes.c_uint64 * TP_DEGREE_MAX), ("kernel_ms", ctypes.c_float),
+                ("degree_table", ctypes.c_uint64 * TP_DEGREE_MAX), ("directed", ctypes.c_uint64 * 8),
+                ("kernel_ms", ctypes.c_float),
                 ("total_ms", ctypes.c_float), ("class_ms", ctypes.c_float * TP_NUM_CLASSES)]
 
 
@@ -409,6 +413,7 @@ def result_dict(res: tp_survey_result, n_labels: int = 16) -> dict:
                 open_close=np.frombuffer(bytes(res.open_close), np.uint64).reshape(32, 32).copy(),
                 max_edge=np.frombuffer(bytes(res.max_edge), np.uint64).copy(),
                 degree_table=np.frombuffer(bytes(res.degree_table), np.uint64).copy(),
+                directed=np.frombuffer(bytes(res.directed), np.uint64)[:7].copy(),
                 kernel_ms=float(res.kernel_ms), total_ms=float(res.total_ms),
                 class_ms=[float(x) for x in res.class_ms])
 
@@ -421,7 +426,8 @@ def words_dict(words: np.ndarray, n_labels: int = 16) -> dict:
                 label_table=w[TP_RW_TABLE:TP_RW_TABLE + table_size(n_labels)].copy(),
                 open_close=w[TP_RW_OPEN_CLOSE:TP_RW_OPEN_CLOSE + 1024].reshape(32, 32).copy(),
                 max_edge=w[TP_RW_MAX_EDGE:TP_RW_MAX_EDGE + TP_MAX_EDGE_BINS].copy(),
-                degree_table=w[TP_RW_DEGREE:TP_RW_DEGREE + TP_DEGREE_MAX].copy())
+                degree_table=w[TP_RW_DEGREE:TP_RW_DEGREE + TP_DEGREE_MAX].copy(),
+                directed=w[TP_RW_DIRECTED:TP_RW_DIRECTED + 7].copy())
 
 
 def stats_dict(st: tp_graph_stats) -> dict:
@@ -442,9 +448,10 @@ def _addr(a):
     return int(a.data_ptr())
 
 
-def edge_list(n, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX, device=None) -> tp_edge_list:
+def edge_list(n, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX, device=None, directed=False) -> tp_edge_list:
     """Pack arrays into a tp_edge_list.  `device` True for device tensors;
-    by default inferred from the arrays (numpy = host)."""
+    by default inferred from the arrays (numpy = host).  directed=True keeps
+    the direction src -> dst of every edge for the directed census."""
     if device is None:
         device = not isinstance(src, np.ndarray)
     el = tp_edge_list()
@@ -453,6 +460,7 @@ def edge_list(n, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX, device=None) -> t
     el.n_edges = len(src)
     el.src, el.dst, el.edge_time, el.vertex_label = _addr(src), _addr(dst), _addr(ts), _addr(vlab)
     el.tie_hash = tie
+    el.flags = TP_EDGES_DIRECTED if directed else 0
     return el
 
 
@@ -483,8 +491,8 @@ class Graph:
             pass
 
 
-def build_graph(n, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX, stream=None) -> Graph:
-    return Graph(tripoll_build(edge_list(n, src, dst, ts, vlab, tie), stream))
+def build_graph(n, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX, stream=None, directed=False) -> Graph:
+    return Graph(tripoll_build(edge_list(n, src, dst, ts, vlab, tie, directed=directed), stream))
 
 
 def survey(graph: Graph, stream=None, n_labels=4, **spec_kw) -> dict:

@@ -52,8 +52,8 @@ int main(void) {
          offsetof(tp_survey_result, class_ms));
   printf("%u %u %u %u %u %u\\n", TP_RW_TABLE, TP_RW_OPEN_CLOSE, TP_RW_SCRATCH, TP_RESULT_WORDS, TP_RW_MAX_EDGE,
          TP_RW_DEGREE);
-  printf("%zu %zu %zu\\n", offsetof(tp_survey_spec, max_edge_shift), offsetof(tp_survey_result, max_edge),
-         offsetof(tp_survey_result, degree_table));
+  printf("%zu %zu %zu %zu %u\\n", offsetof(tp_survey_spec, max_edge_shift), offsetof(tp_survey_result, max_edge),
+         offsetof(tp_survey_result, degree_table), offsetof(tp_survey_result, directed), TP_RW_DIRECTED);
   printf("%zu %zu %zu %zu %u %u %u\\n", sizeof(tp_batch_edges), sizeof(tp_plan), sizeof(tp_tune_result),
          offsetof(tp_tune_result, trials), TP_BW_TABLE, TP_BATCH_SCRATCH_WORDS, TP_NUM_CLASSES);
   printf("%zu %zu %zu %zu %zu\\n", sizeof(tp_server_config), sizeof(tp_request_info), sizeof(tp_server_stats),
@@ -72,7 +72,8 @@ int main(void) {
     assert list(map(int, l3.split())) == [tp.TP_RW_TABLE, tp.TP_RW_OPEN_CLOSE, tp.TP_RW_SCRATCH,
                                           tp.TP_RESULT_WORDS, tp.TP_RW_MAX_EDGE, tp.TP_RW_DEGREE]
     assert list(map(int, l3b.split())) == [tp.tp_survey_spec.max_edge_shift.offset, tp.tp_survey_result.max_edge.offset,
-                                           tp.tp_survey_result.degree_table.offset]
+                                           tp.tp_survey_result.degree_table.offset,
+                                           tp.tp_survey_result.directed.offset, tp.TP_RW_DIRECTED]
     assert list(map(int, l4.split())) == [ctypes.sizeof(tp.tp_batch_edges), ctypes.sizeof(tp.tp_plan),
                                           ctypes.sizeof(tp.tp_tune_result), tp.tp_tune_result.trials.offset,
                                           tp.TP_BW_TABLE, tp.TP_BATCH_SCRATCH_WORDS, tp.TP_NUM_CLASSES]

@@ -1,0 +1,146 @@
+"""GPU parity of the directed triangle census against the CPU oracle, bit for
+bit: graphs built from directed edge lists keep two direction bits per
+oriented edge, and every triangle is counted under its triad-census type."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2107_12330_amd import tripoll as tp
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("triangles", "close_hist", "label_table", "max_edge", "degree_table", "directed")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    return torch
+
+
+def stream(torch):
+    return torch.cuda.current_stream().cuda_stream
+
+
+def gpu_build(torch, n, src, dst, ts, vlab, directed=True):
+    args = [torch.from_numpy(np.ascontiguousarray(x)).cuda() if x is not None else None
+            for x in (src, dst, ts, vlab)]
+    return tp.build_graph(n, *args, stream=stream(torch), directed=directed)
+
+
+def check(torch, n, src, dst, ts, vlab, n_labels=4, outputs=("count", "directed"), strategies=(0,), **kw):
+    ts = np.zeros(len(src), np.uint32) if ts is None else ts
+    vlab = np.zeros(n, np.uint8) if vlab is None else vlab
+    ref = oracle.survey(n, src, dst, ts, vlab, outputs=outputs, n_labels=n_labels, **kw)
+    with gpu_build(torch, n, src, dst, ts, vlab) as G:
+        for strat in strategies:
+            got = tp.survey(G, stream=stream(torch), outputs=outputs, n_labels=n_labels, strategy=strat, **kw)
+            for k in KEYS:
+                if k == "triangles" or k in outputs:
+                    assert np.array_equal(np.asarray(got[k]).ravel(), np.asarray(ref[k]).ravel()), (k, strat)
+    return ref
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_random_directed_graphs(torch_cuda, seed):
+    rng = np.random.default_rng(1100 + seed)
+    n = int(rng.integers(20, 3000))
+    M = int(rng.integers(n, 30 * n))
+    src = rng.integers(0, n, M).astype(np.uint32)
+    dst = rng.integers(0, n, M).astype(np.uint32)
+    hub = rng.integers(0, n, M // 4).astype(np.uint32) % max(1, n // 10)
+    src[: M // 4] = hub
+    ts = rng.integers(0, 1 << 20, M).astype(np.uint32)
+    vlab = rng.integers(0, 6, n).astype(np.uint8)
+    say("directed random", seed, n, M)
+    ref = check(torch_cuda, n, src, dst, ts, vlab, 6, strategies=(0, 1, 2))
+    assert ref["directed"].sum() == ref["triangles"]
+    # with the other extended outputs and a prefilter
+    check(torch_cuda, n, src, dst, ts, vlab, 6,
+          outputs=("count", "close_hist", "label_table", "max_edge", "degree_table", "directed"),
+          max_edge_shift=10, window=(1 << 17, 7 << 17))
+
+
+def test_rmat_directed(torch_cuda):
+    w = synth.workload(1)
+    g = synth.generate(w.graph)
+    say("directed R-MAT scale 12")
+    ref = check(torch_cuda, g["n"], g["src"], g["dst"], g["ts"], g["vlab"], 4, strategies=(0, 1))
+    assert (ref["directed"] > 0).sum() >= 5
+
+
+def test_tournament_and_mutual_complete_graph(torch_cuda):
+    T = torch_cuda
+    n = 300
+    rng = np.random.default_rng(3)
+    iu = np.triu_indices(n, 1)
+    a, b = iu[0].astype(np.uint32), iu[1].astype(np.uint32)
+    flip = rng.random(len(a)) < 0.5
+    src, dst = np.where(flip, b, a), np.where(flip, a, b)
+    say("tournament", n)
+    with gpu_build(T, n, src, dst, None, None) as G:
+        r = tp.survey(G, stream=stream(T), outputs=("count", "directed"))
+    out = np.bincount(src, minlength=n)
+    trans = sum(math.comb(int(k), 2) for k in out)
+    assert r["directed"][0] == trans and r["directed"][1] == math.comb(n, 3) - trans
+    assert r["directed"][2:].sum() == 0
+    # K_4500 with both directions on every pair: targets beyond the large
+    # class search Adj+(q) in HBM; every triangle is of type 300
+    n = 4500
+    iu = np.triu_indices(n, 1)
+    a, b = iu[0].astype(np.uint32), iu[1].astype(np.uint32)
+    say("mutual K_4500")
+    with gpu_build(T, n, np.concatenate([a, b]), np.concatenate([b, a]), None, None) as G:
+        assert G.stats()["dplus_max"] == n - 1
+        r = tp.survey(G, stream=stream(T), outputs=("count", "directed"))
+    assert r["directed"][6] == math.comb(n, 3) and r["directed"][:6].sum() == 0
+
+
+def test_directed_build_matches_undirected(torch_cuda):
+    T = torch_cuda
+    w = synth.workload(1, scale=11)
+    g = synth.generate(w.graph)
+    out = ("count", "close_hist", "label_table", "spread_count", "open_close")
+    say("directed vs undirected build")
+    res = []
+    for directed in (False, True):
+        with gpu_build(T, g["n"], g["src"], g["dst"], g["ts"], g["vlab"], directed=directed) as G:
+            res.append((G.stats()["n_edges"], tp.survey(G, stream=stream(T), outputs=out, n_labels=4,
+                                                        spread_lt=1 << 12)))
+    assert res[0][0] == res[1][0]
+    for k in ("triangles", "close_hist", "label_table", "spread_count", "open_close"):
+        assert np.array_equal(np.asarray(res[0][1][k]), np.asarray(res[1][1][k])), k
+
+
+def test_directed_refusals(torch_cuda):
+    T = torch_cuda
+    src = np.array([0, 1, 2], np.uint32)
+    dst = np.array([1, 2, 0], np.uint32)
+    with gpu_build(T, 3, src, dst, None, None, directed=False) as G:
+        with pytest.raises(tp.TripollError) as ei:
+            tp.survey(G, stream=stream(T), outputs=("directed",))
+        assert ei.value.status == tp.TP_ERR_INVALID
+    with gpu_build(T, 3, src, dst, None, None) as G:
+        r = tp.survey(G, stream=stream(T), outputs=("directed",))
+        assert r["directed"][1] == 1 and r["triangles"] == 1
+    el = tp.edge_list(3, T.from_numpy(src).cuda(), T.from_numpy(dst).cuda())
+    el.flags = 2
+    with pytest.raises(tp.TripollError) as ei:
+        tp.tripoll_build(el, stream(T))
+    assert ei.value.status == tp.TP_ERR_INVALID
+    with tp.Server(max_slots=2, n_labels=4) as srv:
+        gid = srv.add_graph(3, T.from_numpy(src).cuda(), T.from_numpy(dst).cuda())
+        with pytest.raises(tp.TripollError) as ei:
+            srv.submit(gid, outputs=("directed",))
+        assert ei.value.status == tp.TP_ERR_UNSUPPORTED
