@@ -91,3 +91,46 @@ def test_scale22_invariances():
         check_against_golden(tp.survey(G, stream=stream, strategy=tp.TP_STRAT_GLOBAL_SEARCH, **kw), gold)
     del dev
     torch.cuda.empty_cache()
+
+
+def test_scale22_extended_outputs():
+    """Algorithm 3's bins, the degree table, the directed census and the
+    participation counts at full size, against the oracle's stored values."""
+    import torch
+    from tests.golden.make_golden import participation_checksums
+    path = os.path.join(GOLDEN, "golden_ext_w2_s22.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle result for the extended outputs")
+    gold = json.load(open(path))
+    w = synth.workload(2, scale=22)
+    dev = device_graph(torch, w)
+    stream = torch.cuda.current_stream().cuda_stream
+    n = w.graph.n
+    with tp.build_graph(n, dev["src"], dev["dst"], dev["ts"], dev["vlab"], stream=stream, directed=True) as G:
+        st = G.stats()
+        assert st["n_edges"] == gold["m"]
+        say("extended survey")
+        got = tp.survey(G, stream=stream, outputs=("count", "max_edge", "degree_table", "directed"),
+                        n_labels=gold["n_labels"], max_edge_shift=gold["max_edge_shift"])
+        assert got["triangles"] == gold["triangles"]
+        assert np.array_equal(got["max_edge"], np.array(gold["max_edge"], np.uint64))
+        deg = np.zeros(tp.TP_DEGREE_MAX, np.uint64)
+        for i, c in gold["degree_table"].items():
+            deg[int(i)] = c
+        assert np.array_equal(got["degree_table"], deg)
+        assert np.array_equal(got["directed"], np.array(gold["directed"], np.uint64))
+        say("participation")
+        m = st["n_edges"]
+        vc = torch.zeros(n, dtype=torch.int64, device="cuda")
+        ec = torch.zeros(m, dtype=torch.int64, device="cuda")
+        tri = tp.tripoll_participation(G.handle, tp.make_spec(), vc.data_ptr(), ec.data_ptr(), stream)
+        assert tri == gold["triangles"]
+        ex = tp.export(G)
+        rid = ex["rank_to_id"].astype(np.int64)
+        row = np.repeat(np.arange(n), np.diff(ex["rowptr"].astype(np.int64)))
+        a, b = rid[row], rid[ex["col"].astype(np.int64)]
+        got_p = participation_checksums(n, vc.cpu().numpy().view(np.uint64), np.minimum(a, b), np.maximum(a, b),
+                                        ec.cpu().numpy().view(np.uint64))
+        assert got_p == gold["participation"]
+    del dev
+    torch.cuda.empty_cache()
