@@ -108,6 +108,48 @@ def cpu_baseline(scale: int, threads: int) -> dict:
                       % (threads, scale, r["triangles"], dt)}
 
 
+def oracle_table(threads: int, workloads=(1, 2), sample_scale: int | None = None) -> dict:
+    """The oracle's own times per workload, on this host: the clean
+    (single-threaded) and the survey (orient + intersect + reduce) timed
+    apart, the survey on one thread and on `threads`.  Workloads 1 and 2 at
+    their full sizes; optionally the scale-26 recipe at `sample_scale` (the
+    oracle does not finish the full size in a few minutes)."""
+    import oracle
+    import synth
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    rows = []
+    cases = [(wl, None) for wl in workloads] + ([(3, sample_scale)] if sample_scale else [])
+    for wl, scale in cases:
+        w = synth.workload(wl, scale=scale)
+        g = synth.generate(w.graph)
+        L = int(w.graph.labels[1])
+        t0 = time.perf_counter()
+        u, v, t = oracle.clean(g["n"], g["src"], g["dst"], g["ts"])
+        clean_s = time.perf_counter() - t0
+        row = {"workload": wl, "scale": w.graph.scale, "raw_edges": int(len(g["src"])), "edges": int(len(u)),
+               "outputs": list(w.outputs), "clean_s": round(clean_s, 3)}
+        for th in sorted({1, threads}):
+            t0 = time.perf_counter()
+            r = oracle.survey_clean(g["n"], u, v, t, g["vlab"], outputs=w.outputs, n_labels=L,
+                                    spread_lt=w.spread_lt, threads=th)
+            dt = time.perf_counter() - t0
+            row["survey_s_%d_threads" % th] = round(dt, 3)
+            row["triangles"] = int(r["triangles"])
+            log("oracle workload %d scale %d: clean %.2f s, survey on %d threads %.2f s"
+                % (wl, w.graph.scale, clean_s, th, dt))
+        rows.append(row)
+        del g, u, v, t
+    return {"oracle_table": rows, "host": {"cpu_model": model, "cores_visible": len(os.sched_getaffinity(0)),
+                                           "threads": threads}}
+
+
 def batch_bench(args, torch, synth, tp) -> dict:
     """Batched form: every graph of the batch built and surveyed together,
     against the same graphs built and surveyed one launch sequence each.
@@ -568,6 +610,8 @@ def main():
                     help="autotune the survey plan once on the first build; every step then re-cuts its tiles "
                          "with the chosen plan (inside the timed step)")
     ap.add_argument("--cpu-scale", type=int, default=21)
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="time the oracle alone (no GPU): clean and survey per workload, one thread and all")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter calibration)")
     args = ap.parse_args()
@@ -577,6 +621,11 @@ def main():
               "(the survey shards by splitting the work prefix, see the design notes)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+
+    if args.oracle_table:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, len(os.sched_getaffinity(0)))
+        print(json.dumps(oracle_table(threads)), flush=True)
+        return
 
     import torch
     import synth

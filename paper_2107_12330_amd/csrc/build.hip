@@ -417,20 +417,35 @@ __device__ __forceinline__ uint32_t rest_len(const uint64_t *rowptr, uint32_t s,
     return (uint32_t)(rowptr[s + 1] - k - 1);
 }
 
+// One bit per vertex: whether its row is non-empty (bit v & 63 of word
+// v >> 6).  At one bit per vertex the array stays in cache, where the row
+// pointers of random targets would not.
+__global__ void k_has_out(const uint64_t *rowptr, uint32_t n, uint64_t *bits)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t base = blockIdx.x * (size_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < n; base += stride) {
+        const size_t v = base + lane_id();
+        const bool b = v < n && rowptr[v + 1] > rowptr[v];
+        const uint64_t word = __ballot(b);
+        if (lane_id() == 0) bits[base >> 6] = word;
+    }
+}
+
 // Key of each oriented edge for the in-edge sort: (q << kbits) | k, with q
 // replaced by n (sorted past every target) when the edge has no wedge to
 // check; and the record payload that travels with it through the sort: the
 // length of the rest of p's row after slot k (< 2^22) | label(p) << 24.
 // Counts the edges kept.  Slots are in row order, so every read here walks
-// memory forwards.
-__global__ void k_in_keys(const uint32_t *srow, const uint32_t *col, const uint64_t *rowptr, const uint8_t *rlab,
-                          size_t m, int kbits, uint32_t n, uint64_t *key, uint32_t *pay, unsigned long long *kept)
+// memory forwards, but for the bit of q.
+__global__ void k_in_keys(const uint32_t *srow, const uint32_t *col, const uint64_t *rowptr, const uint64_t *has_out,
+                          const uint8_t *rlab, size_t m, int kbits, uint32_t n, uint64_t *key, uint32_t *pay,
+                          unsigned long long *kept)
 {
     unsigned long long c = 0;
     for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < m; k += (size_t)gridDim.x * blockDim.x) {
         const uint32_t s = srow[k], t = col[k];
         const uint32_t rest = rest_len(rowptr, s, k);
-        const bool ok = rest > 0 && rowptr[t + 1] > rowptr[t];
+        const bool ok = rest > 0 && ((has_out[t >> 6] >> (t & 63)) & 1ull);
         key[k] = ((uint64_t)(ok ? t : n) << kbits) | k;
         pay[k] = rest | ((uint32_t)rlab[s] << 24);
         c += ok ? 1 : 0;
@@ -927,9 +942,13 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
         uint32_t *ival = (srow == valA.get()) ? valB.get() : valA.get(), *ival_alt = srow;
         DArray<unsigned long long> kept(1, s);
         TP_HIP(hipMemsetAsync(kept.get(), 0, sizeof(unsigned long long), s));
+        DArray<uint64_t> has_out;
         if (m) {
-            k_in_keys<<<grid_for(m, kB), kB, 0, s>>>(srow, g->col.get(), g->rowptr.get(), g->rlab.get(), m, kbits,
-                                                     n, ikey, ival, kept.get());
+            has_out.reset((n + 63) / 64, s);
+            k_has_out<<<grid_for(n, kB), kB, 0, s>>>(g->rowptr.get(), n, has_out.get());
+            TP_CHECK_LAUNCH();
+            k_in_keys<<<grid_for(m, kB), kB, 0, s>>>(srow, g->col.get(), g->rowptr.get(), has_out.get(),
+                                                     g->rlab.get(), m, kbits, n, ikey, ival, kept.get());
             TP_CHECK_LAUNCH();
         }
         g->n_in = read_scalar(kept.get(), s);
