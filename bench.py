@@ -32,14 +32,15 @@ METRIC = "triangles surveyed/s + HBM GB/s at R-MAT scale 26; p50/p99 survey late
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2107_12330_amd", "csrc", "survey.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "survey_traffic.json")
-CLASS_NAMES = ("tiny (d+(q) <= 51)", "small (d+(q) <= 819)", "large (d+(q) <= 3276)", "huge (d+(q) > 3276)")
+CLASS_NAMES = ("tiny (d+(q) <= 51)", "small (d+(q) <= 819)", "large (d+(q) <= 3276)",
+               "huge (d+(q) > 3276, in pieces of Adj+(q))")
 VARIANT_NAMES = {1: "LDS cuckoo tables, one per wave", 2: "LDS cuckoo tables, one per workgroup",
                  3: "HBM binary search, a workgroup per tile", 4: "HBM binary search, a wave per tile"}
 
 
 def resolve_variant(c: int, v: int) -> int:
     """The variant a class runs with (the library's default when 0)."""
-    return v if v else {0: 1, 1: 2, 2: 2, 3: 3}[c]
+    return v if v else {0: 1, 1: 2, 2: 2, 3: 2}[c]
 
 
 def kernel_key(c: int, v: int, meta: bool, form: int = 0) -> str:
@@ -47,7 +48,7 @@ def kernel_key(c: int, v: int, meta: bool, form: int = 0) -> str:
     variant v, as in the rocprofv3 kernel name (spaces removed).  form: 0 the
     plain survey, 1 the extended reductions, 2 participation."""
     v = resolve_variant(c, v)
-    log_slots, block, wave = {1: (6, 256, "true"), 2: (12, 1024, "false") if c == 2 else (10, 256, "false"),
+    log_slots, block, wave = {1: (6, 256, "true"), 2: (12, 1024, "false") if c >= 2 else (10, 256, "false"),
                               3: (0, 256, "false"), 4: (0, 256, "true")}[v]
     return "survey_kernel<%d,%d,%s,%s,false,false,%d>" % (log_slots, block, wave, "true" if meta else "false", form)
 

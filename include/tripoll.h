@@ -94,7 +94,9 @@ typedef struct tp_graph tp_graph;
 /* Target classes of the survey plan, by d+(q) (the out-degree of the middle
  * vertex of a wedge): 0 tiny d+ <= 51, 1 small <= 819, 2 large <= 3276,
  * 3 huge.  The class decides where Adj+(q) is kept while the wedges through
- * q are checked. */
+ * q are checked.  A huge target's Adj+(q) is cut into ceil(d+ / 3276) runs
+ * of consecutive ranks (pieces), each checked against only the candidates
+ * in its rank range; the planner cuts the in-edge records accordingly. */
 #define TP_NUM_CLASSES 4
 
 /* Graph statistics.  Degrees are of the cleaned simple graph; d+ is the
@@ -223,9 +225,10 @@ tp_status tripoll_graph_export(const tp_graph *g, uint64_t *rowptr, uint32_t *co
 
 /* How a target class searches Adj+(q) (survey plan variants):
  *   TP_VAR_DEFAULT      the class's own choice: per-wave LDS tables (tiny),
- *                       per-workgroup LDS tables (small, large), HBM (huge)
+ *                       per-workgroup LDS tables (small, large, and huge
+ *                       one piece at a time)
  *   TP_VAR_WAVE_TABLE   LDS cuckoo tables, one per wave (tiny class only)
- *   TP_VAR_GROUP_TABLE  LDS cuckoo tables, one per workgroup (not huge)
+ *   TP_VAR_GROUP_TABLE  LDS cuckoo tables, one per workgroup
  *   TP_VAR_SEARCH       binary search of Adj+(q) in HBM, a workgroup per tile
  *   TP_VAR_WAVE_SEARCH  binary search of Adj+(q) in HBM, a wave per tile */
 #define TP_VAR_DEFAULT 0u
@@ -473,7 +476,7 @@ tp_status tripoll_get_plan(const tp_graph *g, tp_plan *out);
  * Replace the plan of a graph (re-cuts the tiles on `stream`; synchronous).
  * Not to be called while surveys of the graph are in flight.
  * Errors: TP_ERR_INVALID for an unknown variant, a variant the class cannot
- * use (tables for the huge class, per-wave tables outside the tiny class) or
+ * use (per-wave tables outside the tiny class) or
  * a tile cap that is not a power of two in [16, 65536].
  */
 tp_status tripoll_set_plan(tp_graph *g, const tp_plan *plan, void *stream);

@@ -511,8 +511,19 @@ __device__ __forceinline__ uint32_t tiles_of(uint64_t cnt, uint64_t work, uint32
     return (uint32_t)t;
 }
 
+// Records of piece j of target q (pieces of huge targets; pos[] is the
+// exclusive scan of the cut flags, fbase[] the first flag of each target):
+// [first, first + count) in the piece record arrays.
+__device__ __forceinline__ void piece_records(const uint64_t *fbase, const uint64_t *pos, size_t q, uint32_t j,
+                                              uint64_t cnt, uint64_t &first, uint64_t &count)
+{
+    first = pos[fbase[q] + j * cnt];
+    count = pos[fbase[q] + (j + 1) * cnt] - first;
+}
+
 __global__ void k_plan_count(const uint64_t *cptr, const unsigned long long *work, const uint64_t *rowptr,
-                             uint32_t n, TileCaps caps, uint32_t *tcnt /* [classes][n] */)
+                             const uint64_t *fbase, const uint64_t *pos, uint32_t n, TileCaps caps,
+                             uint32_t *tcnt /* [classes][n] */)
 {
     for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
         const uint64_t cnt = cptr[q + 1] - cptr[q];
@@ -526,27 +537,115 @@ __global__ void k_plan_count(const uint64_t *cptr, const unsigned long long *wor
                 wc = caps.work[i];
             }
         }
-        const uint32_t t = tiles_of(cnt, work[q], rc, wc);
+        uint32_t t = 0;
+        if (c == kClassHuge && cnt) {
+            // each piece of Adj+(q) has its own records and tiles; it sees
+            // about 1/S of the target's wedge checks
+            const uint32_t S = piece_count(rowptr[q + 1] - rowptr[q]);
+            for (uint32_t j = 0; j < S; ++j) {
+                uint64_t first, count;
+                piece_records(fbase, pos, q, j, cnt, first, count);
+                t += tiles_of(count, (work[q] + S - 1) / S, rc, wc);
+            }
+        } else {
+            t = tiles_of(cnt, work[q], rc, wc);
+        }
         for (int i = 0; i < kNumClasses; ++i) tcnt[(size_t)i * n + q] = (i == c) ? t : 0u;
     }
 }
 
-__global__ void k_plan_write(const uint64_t *cptr, const uint64_t *tile_off, const uint32_t *tcnt, uint32_t n,
-                             TileDesc *tiles)
+// The tiles of target q, dealing its records round-robin; for a huge
+// target, the tiles of each piece in turn over that piece's records.
+__global__ void k_plan_write(const uint64_t *cptr, const unsigned long long *work, const uint64_t *rowptr,
+                             const uint64_t *fbase, const uint64_t *pos, const uint64_t *tile_off,
+                             const uint32_t *tcnt, uint32_t n, TileCaps caps, int cls, TileDesc *tiles)
 {
     for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
         const uint32_t t = tcnt[q];
         if (!t) continue;
-        const uint64_t c0 = cptr[q], cnt = cptr[q + 1] - c0;
-        const uint64_t base = tile_off[q];
-        for (uint32_t j = 0; j < t; ++j) {
-            TileDesc d;
-            d.q = (uint32_t)q;
-            d.cnt = (uint32_t)((cnt - j + t - 1) / t);  // records j, j + t, ... of the target
-            d.e0 = c0 + j;
-            d.stride = t;
-            d.pad = 0;
-            tiles[base + j] = d;
+        const uint64_t cnt = cptr[q + 1] - cptr[q];
+        uint64_t at = tile_off[q];
+        auto deal = [&](uint64_t first, uint64_t count, uint32_t tj, uint32_t piece) {
+            for (uint32_t i = 0; i < tj; ++i) {
+                TileDesc d;
+                d.q = (uint32_t)q;
+                d.cnt = (uint32_t)((count - i + tj - 1) / tj);  // records i, i + tj, ...
+                d.e0 = first + i;
+                d.stride = tj;
+                d.piece = piece;
+                tiles[at++] = d;
+            }
+        };
+        if (cls == kClassHuge) {
+            const uint32_t S = piece_count(rowptr[q + 1] - rowptr[q]);
+            for (uint32_t j = 0; j < S; ++j) {
+                uint64_t first, count;
+                piece_records(fbase, pos, q, j, cnt, first, count);
+                deal(first, count, tiles_of(count, (work[q] + S - 1) / S, caps.rec[cls], caps.work[cls]), j);
+            }
+        } else {
+            deal(cptr[q], cnt, t, 0);
+        }
+    }
+}
+
+// ---- records of huge targets, cut to the pieces of Adj+(q)
+
+// Number of the `len` sorted ranks at `a` that are below x (binary search).
+__device__ __forceinline__ uint32_t count_below(const uint32_t *a, uint32_t len, uint32_t x)
+{
+    uint32_t lo = 0, hi = len;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Cut flags per target: S * (records) for a huge target, else none.
+__global__ void k_piece_slots(const uint64_t *cptr, const uint64_t *rowptr, uint32_t n, uint32_t *slots)
+{
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+        const uint64_t dq = rowptr[q + 1] - rowptr[q];
+        slots[q] = class_of(dq) == kClassHuge ? (uint32_t)(piece_count(dq) * (cptr[q + 1] - cptr[q])) : 0u;
+    }
+}
+
+// For every record p -> q of a huge target and every piece j of Adj+(q):
+// the candidates of the record (the rest of p's row, sorted by rank) whose
+// ranks lie in the piece's range [first key of piece j, first key of piece
+// j + 1).  WRITE false: flag[fbase[q] + j cnt + r] = (any candidates), r the
+// record's place among q's records.  WRITE true: the record cut to the
+// piece, at pos[] of its flag.
+template <bool WRITE>
+__global__ void k_piece_cut(const uint64_t *inkey, const uint32_t *inpay, uint64_t n_in, int kbits,
+                            const uint64_t *cptr, const uint64_t *rowptr, const uint32_t *col, const uint64_t *fbase,
+                            uint32_t *flag, const uint64_t *pos, uint64_t *pkey, uint32_t *ppay)
+{
+    const uint64_t kmask = (1ull << kbits) - 1;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n_in; e += (size_t)gridDim.x * blockDim.x) {
+        const uint64_t key = inkey[e];
+        const uint64_t q = key >> kbits;
+        const uint64_t kq = rowptr[q], dq = rowptr[q + 1] - kq;
+        if (class_of(dq) != kClassHuge) continue;
+        const uint32_t S = piece_count(dq), psz = piece_size(dq);
+        const uint64_t cnt = cptr[q + 1] - cptr[q], r = e - cptr[q];
+        const uint64_t k = key & kmask;
+        const uint32_t pay = inpay[e], len = pay & 0xffffffu;
+        const uint32_t *cand = col + k + 1;
+        uint32_t lo = 0;
+        for (uint32_t j = 0; j < S; ++j) {
+            const uint32_t hi = j + 1 < S ? count_below(cand, len, col[kq + (uint64_t)(j + 1) * psz]) : len;
+            const uint64_t f = fbase[q] + j * cnt + r;
+            if (!WRITE) {
+                flag[f] = hi > lo ? 1u : 0u;
+            } else if (hi > lo) {
+                // q + lo < 2n fits above bit kbits, as q <= n does
+                pkey[pos[f]] = ((q + lo) << kbits) | k;
+                ppay[pos[f]] = (pay & 0xff000000u) | (hi - lo);
+            }
+            lo = hi;
         }
     }
 }
@@ -569,7 +668,8 @@ __global__ void k_work_stats(const unsigned long long *work, uint32_t n, unsigne
 
 // Per-class totals of the plan: records, staged out-list entries, probes.
 __global__ void k_plan_stats(const uint64_t *cptr, const unsigned long long *work, const uint64_t *rowptr,
-                             const uint32_t *tcnt, uint32_t n, unsigned long long *out /* [3][classes] */)
+                             const uint64_t *fbase, const uint64_t *pos, const uint32_t *tcnt, uint32_t n,
+                             TileCaps caps, unsigned long long *out /* [3][classes] */)
 {
     unsigned long long rec[kNumClasses] = {}, stg[kNumClasses] = {}, prb[kNumClasses] = {};
     for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
@@ -577,11 +677,27 @@ __global__ void k_plan_stats(const uint64_t *cptr, const unsigned long long *wor
         const int c = class_of(dq);
         const uint32_t t = tcnt[(size_t)c * n + q];
         if (!t) continue;
+        // a huge target: the records cut to its pieces, each piece staged by
+        // each of its tiles
+        uint64_t nrec = cptr[q + 1] - cptr[q], staged = (uint64_t)t * dq;
+        if (c == kClassHuge) {
+            const uint32_t S = piece_count(dq), psz = piece_size(dq);
+            const uint64_t cnt = nrec;
+            nrec = 0;
+            staged = 0;
+            for (uint32_t j = 0; j < S; ++j) {
+                uint64_t first, count;
+                piece_records(fbase, pos, q, j, cnt, first, count);
+                nrec += count;
+                staged += (uint64_t)tiles_of(count, (work[q] + S - 1) / S, caps.rec[c], caps.work[c]) *
+                          min((uint64_t)psz, dq - (uint64_t)j * psz);
+            }
+        }
 #pragma unroll
         for (int i = 0; i < kNumClasses; ++i) {
             if (i == c) {
-                rec[i] += cptr[q + 1] - cptr[q];
-                stg[i] += (unsigned long long)t * dq;
+                rec[i] += nrec;
+                stg[i] += staged;
                 prb[i] += work[q];
             }
         }
@@ -623,7 +739,8 @@ uint64_t graph_bytes(const tp_graph *g)
 {
     uint64_t b = g->rowptr.bytes() + g->col.bytes() + g->ets.bytes() + g->tlab.bytes() + g->rlab.bytes() +
                  g->perm.bytes() + g->inkey.bytes() + g->inpay.bytes() + g->rank_gid.bytes() +
-                 g->dbin_rank.bytes() + g->dbin_slot.bytes() + g->edir.bytes();
+                 g->dbin_rank.bytes() + g->dbin_slot.bytes() + g->edir.bytes() + g->piece_key.bytes() +
+                 g->piece_pay.bytes();
     for (int c = 0; c < kNumClasses; ++c) b += g->tiles[c].bytes();
     return b;
 }
@@ -647,13 +764,50 @@ void plan_graph(tp_graph *g, const PlanCfg &cfg, hipStream_t s)
         }
         scan_u32_to_u64(incnt.get(), cptr.get(), n, s);
     }
+    // the records of huge targets cut to the pieces of Adj+(q): a flag per
+    // (record, piece), laid out target by target and piece by piece; the
+    // scan of the flags places every cut record
+    DArray<uint64_t> fbase, pos;
+    g->piece_key.release();
+    g->piece_pay.release();
+    g->n_piece_recs = 0;
+    if (g->n_in && g->stats.dplus_max > kLargeMaxDeg) {
+        fbase.reset((size_t)n + 1, s);
+        {
+            DArray<uint32_t> slots(n, s);
+            k_piece_slots<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), g->rowptr.get(), n, slots.get());
+            TP_CHECK_LAUNCH();
+            scan_u32_to_u64(slots.get(), fbase.get(), n, s);
+        }
+        const uint64_t nf = read_scalar(fbase.get() + n, s);
+        pos.reset(nf + 1, s);
+        {
+            DArray<uint32_t> flag(std::max<uint64_t>(nf, 1), s);
+            k_piece_cut<false><<<grid_for(g->n_in, kB), kB, 0, s>>>(
+                g->inkey.get(), g->inpay.get(), g->n_in, (int)g->kbits, cptr.get(), g->rowptr.get(), g->col.get(),
+                fbase.get(), flag.get(), nullptr, nullptr, nullptr);
+            TP_CHECK_LAUNCH();
+            scan_u32_to_u64(flag.get(), pos.get(), nf, s);
+        }
+        const uint64_t nr = read_scalar(pos.get() + nf, s);
+        g->n_piece_recs = nr;
+        g->piece_key.reset(std::max<uint64_t>(nr, 1), s);
+        g->piece_pay.reset(std::max<uint64_t>(nr, 1), s);
+        if (nr) {
+            k_piece_cut<true><<<grid_for(g->n_in, kB), kB, 0, s>>>(
+                g->inkey.get(), g->inpay.get(), g->n_in, (int)g->kbits, cptr.get(), g->rowptr.get(), g->col.get(),
+                fbase.get(), nullptr, pos.get(), g->piece_key.get(), g->piece_pay.get());
+            TP_CHECK_LAUNCH();
+        }
+    }
     TileCaps caps;
     for (int c = 0; c < kNumClasses; ++c) {
         caps.rec[c] = cfg.tile_records[c];
         caps.work[c] = kTileWorkPerRecord * cfg.tile_records[c];
     }
     DArray<uint32_t> tcnt((size_t)kNumClasses * n, s);
-    k_plan_count<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), work.get(), g->rowptr.get(), n, caps, tcnt.get());
+    k_plan_count<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), work.get(), g->rowptr.get(), fbase.get(), pos.get(), n,
+                                                caps, tcnt.get());
     TP_CHECK_LAUNCH();
     for (int c = 0; c < kNumClasses; ++c) {
         DArray<uint64_t> toff((size_t)n + 1, s);
@@ -662,8 +816,9 @@ void plan_graph(tp_graph *g, const PlanCfg &cfg, hipStream_t s)
         g->n_tiles[c] = nt;
         g->tiles[c].reset(std::max<uint64_t>(nt, 1), s);
         if (nt) {
-            k_plan_write<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), toff.get(), tcnt.get() + (size_t)c * n, n,
-                                                        g->tiles[c].get());
+            k_plan_write<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), work.get(), g->rowptr.get(), fbase.get(),
+                                                        pos.get(), toff.get(), tcnt.get() + (size_t)c * n, n, caps,
+                                                        c, g->tiles[c].get());
             TP_CHECK_LAUNCH();
         }
     }
@@ -671,7 +826,8 @@ void plan_graph(tp_graph *g, const PlanCfg &cfg, hipStream_t s)
     constexpr int kStat = 3 * kNumClasses;
     DArray<unsigned long long> pst(kStat + 2, s);
     TP_HIP(hipMemsetAsync(pst.get(), 0, (kStat + 2) * sizeof(unsigned long long), s));
-    k_plan_stats<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), work.get(), g->rowptr.get(), tcnt.get(), n, pst.get());
+    k_plan_stats<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), work.get(), g->rowptr.get(), fbase.get(), pos.get(),
+                                                tcnt.get(), n, caps, pst.get());
     TP_CHECK_LAUNCH();
     k_work_stats<<<grid_for(n, kB), kB, 0, s>>>(work.get(), n, pst.get() + kStat, pst.get() + kStat + 1);
     TP_CHECK_LAUNCH();
@@ -972,6 +1128,7 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
     // ---- phase 7: work per target and the tile plan per class
     PlanCfg cfg{};
     for (int c = 0; c < kNumClasses; ++c) cfg.tile_records[c] = default_tile_records(c);
+    g->stats.dplus_max = read_scalar(c_dpmax, s);  // the plan cuts huge targets' records
     plan_graph(g.get(), cfg, s);
     TP_HIP(hipEventRecord(ev[8], s));
     TP_HIP(hipStreamSynchronize(s));

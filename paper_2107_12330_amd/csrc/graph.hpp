@@ -5,13 +5,14 @@
 
 // One tile of survey work: `cnt` in-edge records of target q, records e0,
 // e0 + stride, e0 + 2 stride, ...  (the tiles of a target interleave, so
-// each gets a fair share of long and short rows).
+// each gets a fair share of long and short rows), checked against piece
+// `piece` of Adj+(q) (always 0 but for huge targets; see piece_count).
 struct TileDesc {
     uint32_t q;
     uint32_t cnt;
     uint64_t e0;
     uint32_t stride;
-    uint32_t pad;
+    uint32_t piece;
 };
 
 // In-edge index: one entry per oriented edge p -> q whose remaining row is
@@ -46,6 +47,14 @@ struct tp_graph {
     uint32_t kbits = 1;           // bits of a CSR slot in an in-edge key
     tp::DArray<uint64_t> inkey;   // [n_in] (q << kbits) | k, sorted by q
     tp::DArray<uint32_t> inpay;   // [n_in] rest of p's row after slot k | label(p) << 24
+    // the in-edge records of huge targets cut to each piece of Adj+(q)
+    // (plan.hpp): for every target and piece in turn, the records with
+    // candidates in the piece, in in-edge order; key ((q + skip) << kbits) | k
+    // with skip the candidates below the piece's ranks, payload the
+    // candidates in the piece | label(p) << 24
+    uint64_t n_piece_recs = 0;
+    tp::DArray<uint64_t> piece_key;
+    tp::DArray<uint32_t> piece_pay;
     tp::DArray<TileDesc> tiles[kNumClasses];
     // degree bins (bin(d) = ceil(log2 d), 0 for d <= 1): ranks are in degree
     // order, so each bin is a range of ranks and of CSR slots (single graphs)

@@ -22,8 +22,10 @@
 // from an atomic counter.  Targets are split into four classes by d+(q), and
 // each class runs one variant of the kernel (the survey plan): LDS tables
 // per wave for tiny targets, LDS tables per workgroup of <= 2 x 1024 or
-// <= 2 x 4096 slots for small and large ones, binary search of Adj+(q) in
-// HBM for huge ones; any class may be switched to HBM search.
+// <= 2 x 4096 slots for small and large ones, and for huge ones the large
+// tables again, one piece of Adj+(q) at a time (plan.hpp), over in-edge
+// records cut to each piece's candidates by the planner; any class may be
+// switched to binary search of Adj+(q) in HBM.
 #include <algorithm>
 #include <map>
 #include <memory>
@@ -80,6 +82,14 @@ struct SurveyParams {
     const uint8_t *rlab;
     const uint64_t *inkey;    // sorted in-edge keys (q << kbits) | k
     const uint32_t *inpay;    // rest of the pivot's row | label(pivot) << 24
+    // the records of the huge class's tiles, one per (record, piece) with
+    // candidates in the piece: key ((q + skip) << kbits) | k (skip: the
+    // candidates of the rest of p's row below the piece's ranks), payload as
+    // inpay with the candidates in the piece; inkey and inpay while
+    // piece_recs is set
+    const uint64_t *piece_key;
+    const uint32_t *piece_pay;
+    uint32_t piece_recs;
     uint32_t kbits;
     const TileDesc *tiles;
     uint64_t n_tiles;
@@ -364,11 +374,8 @@ __device__ __forceinline__ T sload(const T *p)
     return v;
 }
 
-// One in-edge record as the wave walks it: the candidates of p -> q are the
-// `len` slots of p's row starting at `start`.
-// One in-edge as the wave walks it: the candidates of p -> q are the `len`
-// slots of p's row starting at `start`.  A block holds one in-edge per lane.
-// In-edge records as loaded: key (q << kbits) | k and payload.
+// In-edge records as loaded: key (q << kbits) | k (or a piece's record) and
+// payload.  A block holds one in-edge per lane.
 struct KeyBlock {
     uint64_t key;
     uint32_t pay;
@@ -452,7 +459,6 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     };
 
     const uint32_t lane = lane_id();
-    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     uint4 *ring = reinterpret_cast<uint4 *>(lds + L.off_ring) + (size_t)w * kRing;
     for (uint32_t i = tid; i < nc * kGroups; i += BLOCK) cnt_all[i] = 0;
     if (tid < 13) mask_lds[tid] = P.label_mask[tid];
@@ -514,10 +520,11 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
     uint64_t cur_tile = 0;  // global index of the tile being walked (enumeration)
 
     // the target whose out-list is in the LDS table, and its geometry
-    uint32_t cur_q = 0xffffffffu;
+    uint32_t cur_q = 0xffffffffu, cur_piece = 0;
     uint32_t id_q = 0;  // original id of cur_q (enumeration)
     uint64_t kq = 0;
     uint32_t dq = 0, l_q = 0, log_s = 0;
+    uint32_t pk0 = 0, pn = 0;  // the table holds Adj+(q) slots [kq + pk0, kq + pk0 + pn)
     uint32_t n_stash = 0;  // keys in the stash
     bool gmode = LOG_SLOTS == 0;  // search Adj+(q) in HBM (huge targets, or a failed table)
     // degree bin cursor of the pivots this wave walks: bin pb spans CSR slots [pb_lo, pb_hi)
@@ -663,9 +670,10 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 kb0 = load_keys(0);
                 kb1 = load_keys(1);
             }
-            if (d.q != cur_q) {
-                // a new target: reduce the hits still queued against the old
-                // table, then rebuild it once every wave is done with it
+            if (d.q != cur_q || d.piece != cur_piece) {
+                // a new target (or piece): reduce the hits still queued
+                // against the old table, then rebuild it once every wave is
+                // done with it
                 if (META || ENUM) drain_queued();
                 if (P.rank_gid) {
                     const uint32_t g = sload(P.rank_gid + d.q);
@@ -680,12 +688,15 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                     gsync();
                 }
                 cur_q = d.q;
+                cur_piece = d.piece;
                 kq = sload(P.rowptr + cur_q);
                 dq = (uint32_t)(sload(P.rowptr + cur_q + 1) - kq);
                 l_q = META ? __builtin_amdgcn_readfirstlane(P.rlab[cur_q]) : 0u;
                 if (ENUM) id_q = sload(P.perm + cur_q);
+                pk0 = min(cur_piece, piece_count(dq)) * piece_size(dq);
+                pn = pk0 < dq ? min(dq - pk0, piece_size(dq)) : 0u;
                 log_s = 5;
-                while ((1u << log_s) < dq + dq / 4) ++log_s;
+                while ((1u << log_s) < pn + pn / 4) ++log_s;
                 // a target too large for this kernel's tables (the planner's
                 // classes never send one) is searched in HBM
                 if (LOG_SLOTS > 0) gmode = log_s > (uint32_t)LOG_SLOTS;
@@ -701,8 +712,8 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                     // cuckoo insertion: a key evicted from one table moves to
                     // its slot in the other; keys still homeless after
                     // kMaxKicks moves go to the stash
-                    for (uint32_t i = gtid; i < dq; i += kGroup) {
-                        uint32_t cur = P.col[kq + i];
+                    for (uint32_t i = gtid; i < pn; i += kGroup) {
+                        uint32_t cur = P.col[kq + pk0 + i];
                         uint32_t t = 0;
                         for (uint32_t it = 0; it < P.max_kicks; ++it) {
                             const uint32_t h = t == 0 ? hash0(cur, log_s) : S + hash1(cur, log_s);
@@ -721,8 +732,8 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                     gmode = __builtin_amdgcn_readfirstlane(s_fail) != 0;
                     // the metadata of every key goes beside its final slot
                     if ((META || ENUM) && !gmode) {
-                        for (uint32_t i = gtid; i < dq; i += kGroup) {
-                            const uint32_t r = P.col[kq + i];
+                        for (uint32_t i = gtid; i < pn; i += kGroup) {
+                            const uint32_t r = P.col[kq + pk0 + i];
                             uint32_t h = hash0(r, log_s);
                             if (hkey[h] != r) {
                                 h = S + hash1(r, log_s);
@@ -731,13 +742,13 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                                     while (hkey[h] != r) ++h;
                                 }
                             }
-                            hts[h] = P.ets[kq + i];
-                            hlab[h] = P.tlab[kq + i];
+                            hts[h] = P.ets[kq + pk0 + i];
+                            hlab[h] = P.tlab[kq + pk0 + i];
                             if (PART) {
-                                hpos[h] = i;
+                                hpos[h] = pk0 + i;
                                 hcnt[h] = 0;
                             }
-                            if (kdir) hdir[h] = P.edir[kq + i];
+                            if (kdir) hdir[h] = P.edir[kq + pk0 + i];
                             if (ENUM) hpos[h] = P.perm[r];
                         }
                     }
@@ -765,13 +776,20 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                     r.pay = kb.pay;
                     r.t_pq = (META || ENUM) ? P.ets[kb.key & kmask] : 0u;
                     r.p = ENUM ? P.enum_srow[kb.key & kmask] : 0u;
+                    if (!PART && !EXT && P.piece_recs) {
+                        // a record cut to a piece: once its slot's gathers
+                        // are issued, the slot moves past the skipped
+                        // candidates (the forms that need the slot of p -> q
+                        // later skip them record by record)
+                        r.key = (kb.key & kmask) + ((kb.key >> P.kbits) - cur_q);
+                    }
                     return r;
                 };
                 RecBlock blk_cur = gather(kb0);
                 RecBlock blk_nxt = gather(kb1);
                 KeyBlock key_nxt = load_keys(2);
                 struct WaveRec {
-                    uint64_t start;
+                    uint64_t k, start;  // slot of p -> q, first candidate
                     uint32_t len, t_pq, l_p, p;
                 };
                 auto read_rec = [&](uint32_t i) -> WaveRec {
@@ -781,7 +799,9 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                                          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(blk_cur.key >> 32), l)
                                           << 32);
                     const uint32_t pay = __builtin_amdgcn_readlane(blk_cur.pay, l);
-                    r.start = (key & kmask) + 1;
+                    r.k = key & kmask;
+                    r.start = r.k + 1;
+                    if ((PART || EXT) && P.piece_recs) r.start += (key >> P.kbits) - cur_q;
                     r.len = pay & 0xffffffu;
                     r.t_pq = (META || ENUM) ? __builtin_amdgcn_readlane(blk_cur.t_pq, l) : 0;
                     r.l_p = (META || ENUM) ? pay >> 24 : 0;
@@ -790,7 +810,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                         // degree bin of the pivot, from the slot of p -> q:
                         // a wave meets its records in increasing slot order
                         // within a tile, so the bin cursor mostly moves forward
-                        const uint64_t s0 = r.start - 1;
+                        const uint64_t s0 = r.k;
                         if (s0 < pb_lo) {
                             pb = 0;
                             pb_lo = 0;
@@ -804,9 +824,9 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                         r.p = pb;
                     }
                     if (kdir) {
-                        // direction of p -> q: the byte at slot start - 1, read
+                        // direction of p -> q: the byte at slot k, read
                         // through the dword that holds it
-                        const uint64_t s0 = r.start - 1;
+                        const uint64_t s0 = r.k;
                         const uint32_t wd = sload(reinterpret_cast<const uint32_t *>(P.edir + (s0 & ~3ull)));
                         r.p |= ((wd >> ((uint32_t)(s0 & 3ull) * 8u)) & 3u) << 8;
                     }
@@ -838,7 +858,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                         ch.l_p = rec.l_p;
                         ch.p = rec.p;
                         ch.base = base;
-                        ch.spq = rec.start - 1;
+                        ch.spq = rec.k;
                         wave_work += ch.n;
                         off += kChunkCand;
                         if (off >= rec.len) {
@@ -1163,7 +1183,6 @@ uint32_t resolve_variant(const tp_graph *g, int c, uint32_t strategy)
     const uint32_t v = g->plan.variant[c];
     if (v != TP_VAR_DEFAULT) return v;
     if (c == kClassTiny) return TP_VAR_WAVE_TABLE;
-    if (c == kClassHuge) return TP_VAR_SEARCH;
     return TP_VAR_GROUP_TABLE;
 }
 
@@ -1174,9 +1193,15 @@ void launch_variant(int c, uint32_t v, const SurveyParams &P0, hipStream_t s, in
     // keeps one copy, since its workgroups merge their counters at every
     // change of graph
     SurveyParams P = P0;
+    if (c == kClassHuge) {
+        // huge targets: tiles over the records cut to each piece
+        P.inkey = P.piece_key;
+        P.inpay = P.piece_pay;
+        P.piece_recs = 1;
+    }
     if (!P.rank_gid) {
         const uint32_t log_slots = v == TP_VAR_WAVE_TABLE ? kTinyLogSlots
-                                   : v == TP_VAR_GROUP_TABLE ? (c == kClassLarge ? kLargeLogSlots : kSmallLogSlots)
+                                   : v == TP_VAR_GROUP_TABLE ? (c >= kClassLarge ? kLargeLogSlots : kSmallLogSlots)
                                                              : 0;
         const bool wave = v == TP_VAR_WAVE_TABLE || v == TP_VAR_WAVE_SEARCH;
         for (P.copies = kMaxCopies; P.copies > 1; P.copies /= 2) {
@@ -1203,9 +1228,10 @@ void launch_variant(int c, uint32_t v, const SurveyParams &P0, hipStream_t s, in
             launch_class<0, kSmallBlock, false, META, ENUM, MULTI, FORM>(P, s, device);
         break;
     case TP_VAR_GROUP_TABLE:
-        if (c == kClassLarge && lds_need<kLargeLogSlots, kLargeBlock, false, META, ENUM, MULTI, FORM>(P) <= kLdsLimit)
+        // large targets and the pieces of huge ones fill the large tables
+        if (c >= kClassLarge && lds_need<kLargeLogSlots, kLargeBlock, false, META, ENUM, MULTI, FORM>(P) <= kLdsLimit)
             launch_class<kLargeLogSlots, kLargeBlock, false, META, ENUM, MULTI, FORM>(P, s, device);
-        else if (c != kClassLarge && lds_need<kSmallLogSlots, kSmallBlock, false, META, ENUM, MULTI, FORM>(P) <= kLdsLimit)
+        else if (c < kClassLarge && lds_need<kSmallLogSlots, kSmallBlock, false, META, ENUM, MULTI, FORM>(P) <= kLdsLimit)
             launch_class<kSmallLogSlots, kSmallBlock, false, META, ENUM, MULTI, FORM>(P, s, device);
         else
             launch_class<0, kSmallBlock, false, META, ENUM, MULTI, FORM>(P, s, device);
@@ -1300,6 +1326,9 @@ SurveyParams make_params(const tp_graph *g, const tp_survey_spec *sp, unsigned l
     P.rlab = g->rlab.get();
     P.inkey = g->inkey.get();
     P.inpay = g->inpay.get();
+    P.piece_key = g->piece_key.get();
+    P.piece_pay = g->piece_pay.get();
+    P.piece_recs = 0;
     P.kbits = g->kbits;
     P.tile_counter = counter;
     P.out = out;
@@ -1819,7 +1848,7 @@ bool variant_allowed(int c, uint32_t v)
     case TP_VAR_WAVE_TABLE:
         return c == kClassTiny;
     case TP_VAR_GROUP_TABLE:
-        return c != kClassHuge;
+        return true;
     default:
         return false;
     }
@@ -1911,7 +1940,7 @@ extern "C" tp_status tripoll_tune(tp_graph *g, const tp_survey_spec *spec, void 
             {TP_VAR_WAVE_TABLE, TP_VAR_GROUP_TABLE, TP_VAR_WAVE_SEARCH},
             {TP_VAR_GROUP_TABLE, TP_VAR_SEARCH, TP_VAR_WAVE_SEARCH},
             {TP_VAR_GROUP_TABLE, TP_VAR_SEARCH},
-            {TP_VAR_SEARCH, TP_VAR_WAVE_SEARCH}};
+            {TP_VAR_GROUP_TABLE, TP_VAR_SEARCH}};
         tp_tune_result r{};
         float best[kNumClasses];
         uint32_t best_v[kNumClasses], best_cap[kNumClasses];

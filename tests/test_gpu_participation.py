@@ -10,6 +10,7 @@ import pytest
 import oracle
 import synth
 from paper_2107_12330_amd import tripoll as tp
+from tests import graphs
 
 pytestmark = pytest.mark.gpu
 
@@ -117,6 +118,15 @@ def test_complete_graph_huge_targets(torch_cuda):
     assert tri == math.comb(n, 3)
     assert (v == math.comb(n - 1, 2)).all()
     assert len(e) == math.comb(n, 2) and set(e.values()) == {n - 2}
+
+
+def test_huge_targets_random_dense(torch_cuda):
+    # huge targets surveyed in pieces: the (q, r) counts of every piece's
+    # table go back to the right CSR slots, the (p, q) counts add up over
+    # the pieces
+    n, src, dst, ts, vlab = graphs.huge_targets(77)
+    say("participation huge targets", n, len(src))
+    check(torch_cuda, n, src, dst, ts, vlab, 5, strategies=(0, 1))
 
 
 def test_degenerate_and_null_outputs(torch_cuda):

@@ -110,8 +110,9 @@ def test_tuner_choice_against_oracle(torch_cuda, mixed):
 
 
 def test_huge_class_variants_closed_form(torch_cuda):
-    """K_3400: targets of d+ > 3276 (the huge class) under both HBM search
-    variants and small tile caps; C(n,3) triangles."""
+    """K_3400: targets of d+ > 3276 (the huge class) in pieces of Adj+(q) in
+    LDS tables (the default), under both HBM search variants and small tile
+    caps; C(n,3) triangles."""
     torch = torch_cuda
     n = 3400
     iu = np.triu_indices(n, 1)
@@ -119,7 +120,8 @@ def test_huge_class_variants_closed_form(torch_cuda):
     stream = torch.cuda.current_stream().cuda_stream
     with tp.build_graph(n, src, dst, stream=stream) as G:
         assert G.stats()["class_tiles"][3] > 0
-        for var, cap in ((V.TP_VAR_SEARCH, 1024), (V.TP_VAR_WAVE_SEARCH, 1024), (V.TP_VAR_WAVE_SEARCH, 16)):
+        for var, cap in ((V.TP_VAR_DEFAULT, 16384), (V.TP_VAR_GROUP_TABLE, 16), (V.TP_VAR_SEARCH, 1024),
+                         (V.TP_VAR_WAVE_SEARCH, 1024), (V.TP_VAR_WAVE_SEARCH, 16)):
             tp.tripoll_set_plan(G.handle, tp.make_plan((0, 0, 0, var), (1024, 1024, 1024, cap)), stream)
             got = tp.survey(G, stream=stream, outputs=("count", "close_hist"))
             assert got["triangles"] == math.comb(n, 3)
@@ -133,7 +135,7 @@ def test_set_plan_rejects_bad_plans(torch_cuda):
     dst = torch.from_numpy(np.array([1, 2, 0], np.uint32)).cuda()
     with tp.build_graph(3, src, dst, stream=stream) as G:
         bad = [((0, V.TP_VAR_WAVE_TABLE, 0, 0), (1024,) * 4),
-               ((0, 0, 0, V.TP_VAR_GROUP_TABLE), (1024,) * 4),
+               ((0, 0, 0, V.TP_VAR_WAVE_TABLE), (1024,) * 4),
                ((0, 0, 0, 9), (1024,) * 4),
                ((0, 0, 0, 0), (1000, 1024, 1024, 1024)),
                ((0, 0, 0, 0), (8, 1024, 1024, 1024)),

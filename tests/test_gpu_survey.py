@@ -13,6 +13,7 @@ import pytest
 import oracle
 import synth
 from paper_2107_12330_amd import tripoll as tp
+from tests import graphs
 
 pytestmark = pytest.mark.gpu
 
@@ -91,7 +92,8 @@ def test_complete_graphs(torch_cuda, n):
 
 
 def test_huge_target_class(torch_cuda):
-    # K_5000: d+ reaches 4999 > 4096, so targets use the HBM binary-search class
+    # K_5000: d+ reaches 4999 > 3276, so the top targets are huge (surveyed
+    # in two pieces of Adj+(q))
     n = 5000
     iu = np.triu_indices(n, 1)
     src, dst = iu[0].astype(np.uint32), iu[1].astype(np.uint32)
@@ -119,6 +121,33 @@ def test_huge_target_class(torch_cuda):
         else:
             e = int(sizes[a]) * int(sizes[b]) * int(sizes[c])
         assert int(got["label_table"][i]) == e
+
+
+def test_huge_targets_random_dense(torch_cuda):
+    # the huge targets' out-lists are surveyed in pieces and every record's
+    # candidates are cut at the pieces' rank bounds, at irregular places:
+    # bit-exact on every output, the extended form too, with the HBM search
+    # beside the default
+    n, src, dst, ts, vlab = graphs.huge_targets(4242)
+    ext = ALL_OUT + ("max_edge", "degree_table")
+    say("huge targets", n, len(src))
+    ref = oracle.survey(n, src, dst, ts, vlab, outputs=ext, n_labels=5, spread_lt=1 << 16, max_edge_shift=12)
+    with gpu_build(torch_cuda, n, src, dst, ts, vlab) as G:
+        st = G.stats()
+        say("d+ max", st["dplus_max"], "huge tiles", st["class_tiles"][3])
+        assert st["dplus_max"] > 3276 and st["class_tiles"][3] > 0
+        for strat in (0, 1):
+            got = gpu_survey(torch_cuda, G, outputs=ALL_OUT, n_labels=5, spread_lt=1 << 16, strategy=strat)
+            assert_same(got, ref)
+            assert got["probes"] == st["probes"]
+        got = gpu_survey(torch_cuda, G, outputs=ext, n_labels=5, spread_lt=1 << 16, max_edge_shift=12)
+        assert_same(got, ref, keys=("triangles", "close_hist", "label_table", "spread_count", "open_close",
+                                    "max_edge", "degree_table"))
+        # tiles of at most 16 records: many more tiles per piece
+        tp.tripoll_set_plan(G.handle, tp.make_plan((0, 0, 0, 0), (1024, 1024, 1024, 16)),
+                            torch_cuda.cuda.current_stream().cuda_stream)
+        got = gpu_survey(torch_cuda, G, outputs=ALL_OUT, n_labels=5, spread_lt=1 << 16)
+        assert_same(got, ref)
 
 
 def test_zero_triangle_and_degenerate_graphs(torch_cuda):
