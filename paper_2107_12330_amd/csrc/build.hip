@@ -603,49 +603,60 @@ __device__ __forceinline__ uint32_t count_below(const uint32_t *a, uint32_t len,
     return lo;
 }
 
-// Cut flags per target: S * (records) for a huge target, else none.
-__global__ void k_piece_slots(const uint64_t *cptr, const uint64_t *rowptr, uint32_t n, uint32_t *slots)
+// Cut flags per target: S * (records) for a huge target with records, else
+// none; the huge targets with records are listed (in no particular order;
+// at most m / (kLargeMaxDeg + 1) targets have d+ above kLargeMaxDeg).
+__global__ void k_piece_slots(const uint64_t *cptr, const uint64_t *rowptr, uint32_t n, uint32_t *slots,
+                              uint32_t *list, unsigned long long *n_list)
 {
     for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
-        const uint64_t dq = rowptr[q + 1] - rowptr[q];
-        slots[q] = class_of(dq) == kClassHuge ? (uint32_t)(piece_count(dq) * (cptr[q + 1] - cptr[q])) : 0u;
+        const uint64_t dq = rowptr[q + 1] - rowptr[q], cnt = cptr[q + 1] - cptr[q];
+        const bool huge = class_of(dq) == kClassHuge && cnt > 0;
+        slots[q] = huge ? (uint32_t)(piece_count(dq) * cnt) : 0u;
+        if (huge) list[atomicAdd(n_list, 1ull)] = (uint32_t)q;
     }
 }
 
-// For every record p -> q of a huge target and every piece j of Adj+(q):
-// the candidates of the record (the rest of p's row, sorted by rank) whose
-// ranks lie in the piece's range [first key of piece j, first key of piece
-// j + 1).  WRITE false: flag[fbase[q] + j cnt + r] = (any candidates), r the
-// record's place among q's records.  WRITE true: the record cut to the
-// piece, at pos[] of its flag.
+// For every record p -> q of a listed huge target (grid row y: targets y,
+// y + gridDim.y, ...) and every piece j of Adj+(q): the candidates of the
+// record (the rest of p's row, sorted by rank) whose ranks lie in the
+// piece's range [first key of piece j, first key of piece j + 1).
+// WRITE false: at f = fbase[q] + j cnt + r (r the record's place among q's
+// records) flag[f] = (any candidates) and cut[f] = the end of the piece's
+// candidates in the record.  WRITE true: the record cut to the piece, from
+// cut[], at pos[f].
 template <bool WRITE>
-__global__ void k_piece_cut(const uint64_t *inkey, const uint32_t *inpay, uint64_t n_in, int kbits,
-                            const uint64_t *cptr, const uint64_t *rowptr, const uint32_t *col, const uint64_t *fbase,
-                            uint32_t *flag, const uint64_t *pos, uint64_t *pkey, uint32_t *ppay)
+__global__ void k_piece_cut(const uint64_t *inkey, const uint32_t *inpay, int kbits, const uint32_t *list,
+                            uint64_t n_list, const uint64_t *cptr, const uint64_t *rowptr, const uint32_t *col,
+                            const uint64_t *fbase, uint32_t *flag, uint32_t *cut, const uint64_t *pos,
+                            uint64_t *pkey, uint32_t *ppay)
 {
     const uint64_t kmask = (1ull << kbits) - 1;
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n_in; e += (size_t)gridDim.x * blockDim.x) {
-        const uint64_t key = inkey[e];
-        const uint64_t q = key >> kbits;
+    for (uint64_t t = blockIdx.y; t < n_list; t += gridDim.y) {
+        const uint64_t q = list[t];
         const uint64_t kq = rowptr[q], dq = rowptr[q + 1] - kq;
-        if (class_of(dq) != kClassHuge) continue;
         const uint32_t S = piece_count(dq), psz = piece_size(dq);
-        const uint64_t cnt = cptr[q + 1] - cptr[q], r = e - cptr[q];
-        const uint64_t k = key & kmask;
-        const uint32_t pay = inpay[e], len = pay & 0xffffffu;
-        const uint32_t *cand = col + k + 1;
-        uint32_t lo = 0;
-        for (uint32_t j = 0; j < S; ++j) {
-            const uint32_t hi = j + 1 < S ? count_below(cand, len, col[kq + (uint64_t)(j + 1) * psz]) : len;
-            const uint64_t f = fbase[q] + j * cnt + r;
-            if (!WRITE) {
-                flag[f] = hi > lo ? 1u : 0u;
-            } else if (hi > lo) {
-                // q + lo < 2n fits above bit kbits, as q <= n does
-                pkey[pos[f]] = ((q + lo) << kbits) | k;
-                ppay[pos[f]] = (pay & 0xff000000u) | (hi - lo);
+        const uint64_t c0 = cptr[q], cnt = cptr[q + 1] - c0;
+        for (uint64_t r = blockIdx.x * (size_t)blockDim.x + threadIdx.x; r < cnt; r += (size_t)gridDim.x * blockDim.x) {
+            const uint64_t key = inkey[c0 + r];
+            const uint64_t k = key & kmask;
+            const uint32_t pay = inpay[c0 + r], len = pay & 0xffffffu;
+            const uint32_t *cand = col + k + 1;
+            uint32_t lo = 0;
+            for (uint32_t j = 0; j < S; ++j) {
+                const uint64_t f = fbase[q] + j * cnt + r;
+                uint32_t hi;
+                if (!WRITE) {
+                    hi = j + 1 < S ? count_below(cand, len, col[kq + (uint64_t)(j + 1) * psz]) : len;
+                    flag[f] = hi > lo ? 1u : 0u;
+                    cut[f] = hi;
+                } else if ((hi = cut[f]) > lo) {
+                    // q + lo < 2n fits above bit kbits, as q <= n does
+                    pkey[pos[f]] = ((q + lo) << kbits) | k;
+                    ppay[pos[f]] = (pay & 0xff000000u) | (hi - lo);
+                }
+                lo = hi;
             }
-            lo = hi;
         }
     }
 }
@@ -773,20 +784,30 @@ void plan_graph(tp_graph *g, const PlanCfg &cfg, hipStream_t s)
     g->n_piece_recs = 0;
     if (g->n_in && g->stats.dplus_max > kLargeMaxDeg) {
         fbase.reset((size_t)n + 1, s);
+        DArray<uint32_t> list(g->m / (kLargeMaxDeg + 1) + 1, s);
+        DArray<unsigned long long> n_list(1, s);
+        TP_HIP(hipMemsetAsync(n_list.get(), 0, sizeof(unsigned long long), s));
         {
             DArray<uint32_t> slots(n, s);
-            k_piece_slots<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), g->rowptr.get(), n, slots.get());
+            k_piece_slots<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), g->rowptr.get(), n, slots.get(), list.get(),
+                                                         n_list.get());
             TP_CHECK_LAUNCH();
             scan_u32_to_u64(slots.get(), fbase.get(), n, s);
         }
         const uint64_t nf = read_scalar(fbase.get() + n, s);
+        const uint64_t nh = read_scalar(n_list.get(), s);
+        // a grid row per listed target (strided), its records across the row
+        const dim3 grid(64, (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(nh, 4096)));
         pos.reset(nf + 1, s);
+        DArray<uint32_t> cut(std::max<uint64_t>(nf, 1), s);
         {
             DArray<uint32_t> flag(std::max<uint64_t>(nf, 1), s);
-            k_piece_cut<false><<<grid_for(g->n_in, kB), kB, 0, s>>>(
-                g->inkey.get(), g->inpay.get(), g->n_in, (int)g->kbits, cptr.get(), g->rowptr.get(), g->col.get(),
-                fbase.get(), flag.get(), nullptr, nullptr, nullptr);
-            TP_CHECK_LAUNCH();
+            if (nh) {
+                k_piece_cut<false><<<grid, kB, 0, s>>>(g->inkey.get(), g->inpay.get(), (int)g->kbits, list.get(), nh,
+                                                       cptr.get(), g->rowptr.get(), g->col.get(), fbase.get(),
+                                                       flag.get(), cut.get(), nullptr, nullptr, nullptr);
+                TP_CHECK_LAUNCH();
+            }
             scan_u32_to_u64(flag.get(), pos.get(), nf, s);
         }
         const uint64_t nr = read_scalar(pos.get() + nf, s);
@@ -794,9 +815,9 @@ void plan_graph(tp_graph *g, const PlanCfg &cfg, hipStream_t s)
         g->piece_key.reset(std::max<uint64_t>(nr, 1), s);
         g->piece_pay.reset(std::max<uint64_t>(nr, 1), s);
         if (nr) {
-            k_piece_cut<true><<<grid_for(g->n_in, kB), kB, 0, s>>>(
-                g->inkey.get(), g->inpay.get(), g->n_in, (int)g->kbits, cptr.get(), g->rowptr.get(), g->col.get(),
-                fbase.get(), nullptr, pos.get(), g->piece_key.get(), g->piece_pay.get());
+            k_piece_cut<true><<<grid, kB, 0, s>>>(g->inkey.get(), g->inpay.get(), (int)g->kbits, list.get(), nh,
+                                                  cptr.get(), g->rowptr.get(), g->col.get(), fbase.get(), nullptr,
+                                                  cut.get(), pos.get(), g->piece_key.get(), g->piece_pay.get());
             TP_CHECK_LAUNCH();
         }
     }

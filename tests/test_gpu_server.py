@@ -11,6 +11,7 @@ import pytest
 import oracle
 import synth
 from paper_2107_12330_amd import tripoll as tp
+from tests import graphs
 
 pytestmark = pytest.mark.gpu
 
@@ -135,6 +136,28 @@ def test_served_results_against_oracle(torch_cuda):
     assert r1["triangles"] == ref1["triangles"] and np.array_equal(r1["close_hist"], ref1["close_hist"])
     assert np.array_equal(r1["label_table"], ref1["label_table"])
     assert r2["triangles"] == ref2["triangles"] and np.array_equal(r2["close_hist"], ref2["close_hist"])
+
+
+def test_served_huge_targets_against_oracle(torch_cuda):
+    """Targets of d+ above 3276, surveyed in pieces of Adj+(q), in shared
+    multi-request passes: each request against the oracle."""
+    torch = torch_cuda
+    n, s, d, t, v = graphs.huge_targets(91)
+    specs = [dict(outputs=("count", "close_hist", "label_table")),
+             dict(outputs=("count", "close_hist"), window=(1 << 20, 3 << 20), label_mask=[0, 7, 19, 33, 64])]
+    with tp.Server(max_slots=4, n_labels=L, step_wedges=1 << 20) as srv:
+        gid = srv.add_graph(n, *[torch.from_numpy(x).cuda() for x in (s, d, t, v)])
+        st = srv.graph_stats(gid)
+        say("served huge targets: d+ max", st["dplus_max"], "huge tiles", st["class_tiles"][3])
+        assert st["class_tiles"][3] > 0
+        tickets = [srv.submit(gid, **sp) for sp in specs]
+        res = [srv.wait(tk, timeout_us=120_000_000)[0] for tk in tickets]
+    for sp, r in zip(specs, res):
+        ref = oracle.survey(n, s, d, t, v, n_labels=L, **sp)
+        assert r["triangles"] == ref["triangles"]
+        assert np.array_equal(r["close_hist"], ref["close_hist"])
+        if "label_table" in sp["outputs"]:
+            assert np.array_equal(r["label_table"], ref["label_table"])
 
 
 def test_concurrent_submitters(torch_cuda):
