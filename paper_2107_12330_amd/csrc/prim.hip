@@ -228,8 +228,10 @@ void scan_u32_to_u64(const uint32_t *in, uint64_t *out, size_t n, hipStream_t s)
 //
 // Reduce-then-scan LSD radix sort, 9-bit digits (52-bit pair keys take 6
 // passes; 8-bit digits took 7 and were slower overall, 10-bit digits write
-// runs too short to coalesce).  A fixed number of blocks each own a
-// contiguous chunk of tiles (4096 keys).  Per pass:
+// runs too short to coalesce), except that a sort takes some 10-bit digits
+// where they save a pass (56-bit keys: 6 passes, two of them 10-bit, not 7).
+// A fixed number of blocks each own a contiguous chunk of tiles (4096
+// keys).  Per pass:
 //   1. upsweep: digit histogram of each block's chunk -> hist[digit][block]
 //   2. exclusive scan of hist (digit-major), giving each (digit, block) its
 //      first output position
@@ -243,40 +245,47 @@ constexpr int kSortBlock = 256;
 constexpr int kSortWaves = kSortBlock / kWave;
 constexpr int kSortRounds = 16;                           // keys per lane
 constexpr int kSortTile = kSortBlock * kSortRounds;       // 4096
-constexpr int kRadixBits = 9;
-constexpr int kRadix = 1 << kRadixBits;
-constexpr int kDigitsPerThread = kRadix / kSortBlock;
+constexpr int kMaxRadixBits = 10;
 constexpr unsigned kMaxSortBlocks = 2048;
 
-__device__ __forceinline__ unsigned digit_of(uint64_t k, int shift) { return (unsigned)(k >> shift) & (kRadix - 1); }
+template <int RB>
+__device__ __forceinline__ unsigned digit_of(uint64_t k, int shift)
+{
+    return (unsigned)(k >> shift) & ((1u << RB) - 1);
+}
 
-template <class K>
+template <class K, int RB>
 __global__ __launch_bounds__(kSortBlock) void radix_upsweep(const K *keys, size_t n, int shift,
                                                             size_t tiles_per_block, uint64_t *hist)
 {
+    constexpr int kRadix = 1 << RB;
     __shared__ unsigned cnt[kRadix];
     for (int d = threadIdx.x; d < kRadix; d += kSortBlock) cnt[d] = 0;
     __syncthreads();
     const size_t t0 = blockIdx.x * tiles_per_block;
     const size_t lo = t0 * kSortTile;
     const size_t hi = std::min(n, (t0 + tiles_per_block) * kSortTile);
-    for (size_t i = lo + threadIdx.x; i < hi; i += kSortBlock) atomicAdd(&cnt[digit_of(keys[i], shift)], 1u);
+    for (size_t i = lo + threadIdx.x; i < hi; i += kSortBlock) atomicAdd(&cnt[digit_of<RB>(keys[i], shift)], 1u);
     __syncthreads();
     for (int d = threadIdx.x; d < kRadix; d += kSortBlock) hist[(size_t)d * gridDim.x + blockIdx.x] = cnt[d];
 }
 
-// K: uint64_t or uint32_t keys; VALS: whether 32-bit values travel with them.
-template <class K, bool VALS>
-__global__ __launch_bounds__(kSortBlock) void radix_downsweep(const K *keys_in, const uint32_t *vals_in,
+// K: uint64_t or uint32_t keys; VALS: whether 32-bit values travel with
+// them; RB: bits of the digit.
+template <class K, bool VALS, int RB>
+// (two blocks of 4 waves per compute unit: 10-bit digits with values need
+// all of 256 registers and 80 KB of LDS for it)
+__global__ __launch_bounds__(kSortBlock, 2) void radix_downsweep(const K *keys_in, const uint32_t *vals_in,
                                                               K *keys_out, uint32_t *vals_out, size_t n,
                                                               int shift, size_t tiles_per_block,
                                                               const uint64_t *offsets)
 {
+    constexpr int kRadix = 1 << RB;
+    constexpr int kDigitsPerThread = kRadix / kSortBlock;
     __shared__ K skey[kSortTile];
     __shared__ uint32_t sval[VALS ? kSortTile : 1];
     __shared__ unsigned wcnt[kSortWaves][kRadix];  // per-wave running count, then per-wave base
     __shared__ unsigned tstart[kRadix];
-    __shared__ unsigned tcount[kRadix];
     __shared__ uint64_t grun[kRadix];              // next output position of each digit
     __shared__ unsigned scan_tmp[kSortWaves];
 
@@ -321,7 +330,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_downsweep(const K *keys_in, 
             ok[r] = i < n;
             k[r] = kn[r];
             v[r] = vn[r];
-            dg[r] = digit_of(k[r], shift);
+            dg[r] = digit_of<RB>(k[r], shift);
         }
         if (t + 1 < t0 + tiles_per_block && (t + 1) * kSortTile < n) load_tile(t + 1);
         // stable rank of every key among equal digits of this wave's quarter
@@ -329,7 +338,7 @@ __global__ __launch_bounds__(kSortBlock) void radix_downsweep(const K *keys_in, 
         for (int r = 0; r < kSortRounds; ++r) {
             uint64_t peers = __ballot(ok[r]);
 #pragma unroll
-            for (int b = 0; b < kRadixBits; ++b) {
+            for (int b = 0; b < RB; ++b) {
                 const bool bit = (dg[r] >> b) & 1u;
                 const uint64_t m = __ballot(bit);
                 peers &= bit ? m : ~m;
@@ -357,7 +366,6 @@ __global__ __launch_bounds__(kSortBlock) void radix_downsweep(const K *keys_in, 
                     wcnt[i][d] = tot;
                     tot += c;
                 }
-                tcount[d] = tot;
                 loc[j] = sum;
                 sum += tot;
             }
@@ -379,18 +387,35 @@ __global__ __launch_bounds__(kSortBlock) void radix_downsweep(const K *keys_in, 
         const unsigned valid = (unsigned)std::min<size_t>(kSortTile, n - tile_lo);
         for (unsigned i = threadIdx.x; i < valid; i += kSortBlock) {
             const K key = skey[i];
-            const unsigned d = digit_of(key, shift);
+            const unsigned d = digit_of<RB>(key, shift);
             const uint64_t dst = grun[d] + (i - tstart[d]);
             keys_out[dst] = key;
             if (VALS) vals_out[dst] = sval[i];
         }
         __syncthreads();
         for (int d = threadIdx.x; d < kRadix; d += kSortBlock) {
-            grun[d] += tcount[d];
+            // the digit's keys in this tile: up to the next digit's start
+            grun[d] += (d + 1 < kRadix ? tstart[d + 1] : valid) - tstart[d];
             for (int i = 0; i < kSortWaves; ++i) wcnt[i][d] = 0;
         }
         __syncthreads();
     }
+}
+
+// One pass over digit [shift, shift + RB): histograms, their scan, the
+// stable scatter (values travel when vi is set).
+template <class K, int RB>
+void sort_pass(const K *ki, const uint32_t *vi, K *ko, uint32_t *vo, size_t n, int shift, unsigned nb, size_t tpb,
+               uint64_t *hist, hipStream_t s)
+{
+    radix_upsweep<K, RB><<<nb, kSortBlock, 0, s>>>(ki, n, shift, tpb, hist);
+    TP_CHECK_LAUNCH();
+    scan_u64(hist, hist, (size_t)(1u << RB) * nb, false, s);
+    if (vi)
+        radix_downsweep<K, true, RB><<<nb, kSortBlock, 0, s>>>(ki, vi, ko, vo, n, shift, tpb, hist);
+    else
+        radix_downsweep<K, false, RB><<<nb, kSortBlock, 0, s>>>(ki, nullptr, ko, nullptr, n, shift, tpb, hist);
+    TP_CHECK_LAUNCH();
 }
 
 template <class K>
@@ -401,21 +426,21 @@ bool radix_sort(K *keys, uint32_t *vals, K *keys_alt, uint32_t *vals_alt, size_t
     const size_t tiles = (n + kSortTile - 1) / kSortTile;
     const unsigned nb = (unsigned)std::min<size_t>(tiles, kMaxSortBlocks);
     const size_t tpb = (tiles + nb - 1) / nb;
-    DArray<uint64_t> hist((size_t)kRadix * nb, s);
+    DArray<uint64_t> hist((size_t)(1u << kMaxRadixBits) * nb, s);
+    // 9-bit digits, or as few 10-bit ones as cover `bits` in one pass less
+    const int p9 = (bits + 8) / 9, p10 = (bits + 9) / 10;
+    const int passes = std::min(p9, p10);
+    const int n10 = passes < p9 ? bits - 9 * passes : 0;
     bool in_alt = false;
-    for (int shift = begin_bit; shift < begin_bit + bits; shift += kRadixBits) {
+    int shift = begin_bit;
+    for (int pass = 0; pass < passes; ++pass) {
         const K *ki = in_alt ? keys_alt : keys;
         const uint32_t *vi = in_alt ? vals_alt : vals;
         K *ko = in_alt ? keys : keys_alt;
         uint32_t *vo = in_alt ? vals : vals_alt;
-        radix_upsweep<K><<<nb, kSortBlock, 0, s>>>(ki, n, shift, tpb, hist.get());
-        TP_CHECK_LAUNCH();
-        scan_u64(hist.get(), hist.get(), (size_t)kRadix * nb, false, s);
-        if (vals)
-            radix_downsweep<K, true><<<nb, kSortBlock, 0, s>>>(ki, vi, ko, vo, n, shift, tpb, hist.get());
-        else
-            radix_downsweep<K, false><<<nb, kSortBlock, 0, s>>>(ki, nullptr, ko, nullptr, n, shift, tpb, hist.get());
-        TP_CHECK_LAUNCH();
+        if (pass < n10) sort_pass<K, 10>(ki, vi, ko, vo, n, shift, nb, tpb, hist.get(), s);
+        else sort_pass<K, 9>(ki, vi, ko, vo, n, shift, nb, tpb, hist.get(), s);
+        shift += pass < n10 ? 10 : 9;
         in_alt = !in_alt;
     }
     return in_alt;
