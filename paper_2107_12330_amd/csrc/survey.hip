@@ -85,11 +85,10 @@ struct SurveyParams {
     // the records of the huge class's tiles, one per (record, piece) with
     // candidates in the piece: key ((q + skip) << kbits) | k (skip: the
     // candidates of the rest of p's row below the piece's ranks), payload as
-    // inpay with the candidates in the piece; inkey and inpay while
-    // piece_recs is set
+    // inpay with the candidates in the piece; inkey and inpay for that
+    // class's launches
     const uint64_t *piece_key;
     const uint32_t *piece_pay;
-    uint32_t piece_recs;
     uint32_t kbits;
     const TileDesc *tiles;
     uint64_t n_tiles;
@@ -405,7 +404,9 @@ struct RecBlock {
 // reductions (max-edge bins, degree table), compiled into their own kernels
 // so that the others keep their register budget; kFormPart counts the
 // triangles at every edge (local participation) instead of reducing them.
-template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM>
+// PIECES: the huge class, whose tiles each hold one piece of Adj+(q) and
+// walk records cut to it (the other classes compile without this).
+template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM, bool PIECES>
 __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
 {
     constexpr int kSub = Depth<WAVE>::kSub;
@@ -670,7 +671,7 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 kb0 = load_keys(0);
                 kb1 = load_keys(1);
             }
-            if (d.q != cur_q || d.piece != cur_piece) {
+            if (d.q != cur_q || (PIECES && d.piece != cur_piece)) {
                 // a new target (or piece): reduce the hits still queued
                 // against the old table, then rebuild it once every wave is
                 // done with it
@@ -693,8 +694,8 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                 dq = (uint32_t)(sload(P.rowptr + cur_q + 1) - kq);
                 l_q = META ? __builtin_amdgcn_readfirstlane(P.rlab[cur_q]) : 0u;
                 if (ENUM) id_q = sload(P.perm + cur_q);
-                pk0 = min(cur_piece, piece_count(dq)) * piece_size(dq);
-                pn = pk0 < dq ? min(dq - pk0, piece_size(dq)) : 0u;
+                pk0 = PIECES ? min(cur_piece, piece_count(dq)) * piece_size(dq) : 0u;
+                pn = PIECES ? (pk0 < dq ? min(dq - pk0, piece_size(dq)) : 0u) : dq;
                 log_s = 5;
                 while ((1u << log_s) < pn + pn / 4) ++log_s;
                 // a target too large for this kernel's tables (the planner's
@@ -776,11 +777,12 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                     r.pay = kb.pay;
                     r.t_pq = (META || ENUM) ? P.ets[kb.key & kmask] : 0u;
                     r.p = ENUM ? P.enum_srow[kb.key & kmask] : 0u;
-                    if (!PART && !EXT && P.piece_recs) {
+                    if (PIECES && !PART && !kdir) {
                         // a record cut to a piece: once its slot's gathers
                         // are issued, the slot moves past the skipped
-                        // candidates (the forms that need the slot of p -> q
-                        // later skip them record by record)
+                        // candidates, still in p's row (participation and the
+                        // directed census, which need the slot of p -> q
+                        // later, skip them record by record)
                         r.key = (kb.key & kmask) + ((kb.key >> P.kbits) - cur_q);
                     }
                     return r;
@@ -799,15 +801,16 @@ __global__ __launch_bounds__(BLOCK) void survey_kernel(SurveyParams P)
                                          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(blk_cur.key >> 32), l)
                                           << 32);
                     const uint32_t pay = __builtin_amdgcn_readlane(blk_cur.pay, l);
-                    r.k = key & kmask;
-                    r.start = r.k + 1;
-                    if ((PART || EXT) && P.piece_recs) r.start += (key >> P.kbits) - cur_q;
+                    r.start = (key & kmask) + 1;
+                    r.k = r.start - 1;
+                    if (PIECES && (PART || kdir)) r.start += (key >> P.kbits) - cur_q;
                     r.len = pay & 0xffffffu;
                     r.t_pq = (META || ENUM) ? __builtin_amdgcn_readlane(blk_cur.t_pq, l) : 0;
                     r.l_p = (META || ENUM) ? pay >> 24 : 0;
                     r.p = 0;
                     if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE)) {
-                        // degree bin of the pivot, from the slot of p -> q:
+                        // degree bin of the pivot, from a slot of p's row (that
+                        // of p -> q, or past it for a record cut to a piece):
                         // a wave meets its records in increasing slot order
                         // within a tile, so the bin cursor mostly moves forward
                         const uint64_t s0 = r.k;
@@ -1132,7 +1135,7 @@ size_t lds_need(const SurveyParams &P)
         .total;
 }
 
-template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM>
+template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM, bool PIECES = false>
 void launch_class(const SurveyParams &P, hipStream_t s, int device)
 {
     if (P.n_tiles == 0) return;
@@ -1143,7 +1146,7 @@ void launch_class(const SurveyParams &P, hipStream_t s, int device)
                                    FORM == kFormPart, FORM == kFormExt && P.dir_words, ENUM);
     if (L.total > kLdsLimit)
         fail(TP_ERR_UNSUPPORTED, "tripoll_survey: the requested outputs need more LDS than a workgroup may hold");
-    auto kern = survey_kernel<LOG_SLOTS, BLOCK, WAVE, META, ENUM, MULTI, FORM>;
+    auto kern = survey_kernel<LOG_SLOTS, BLOCK, WAVE, META, ENUM, MULTI, FORM, PIECES>;
     // attribute and occupancy queries run once per kernel, device and LDS
     // size, so that a survey recorded into a HIP graph issues launches only
     static std::mutex mu;
@@ -1197,7 +1200,6 @@ void launch_variant(int c, uint32_t v, const SurveyParams &P0, hipStream_t s, in
         // huge targets: tiles over the records cut to each piece
         P.inkey = P.piece_key;
         P.inpay = P.piece_pay;
-        P.piece_recs = 1;
     }
     if (!P.rank_gid) {
         const uint32_t log_slots = v == TP_VAR_WAVE_TABLE ? kTinyLogSlots
@@ -1218,6 +1220,17 @@ void launch_variant(int c, uint32_t v, const SurveyParams &P0, hipStream_t s, in
     // degree tables) searches Adj+(q) in HBM instead
     // (per-wave forms hold counters per wave, so they overflow first)
     const bool wave_search_fits = lds_need<0, kSmallBlock, true, META, ENUM, MULTI, FORM>(P) <= kLdsLimit;
+    if (c == kClassHuge) {
+        // the kernels that walk pieces: the large tables, or the HBM search
+        // by workgroups or by waves
+        if (v == TP_VAR_GROUP_TABLE && lds_need<kLargeLogSlots, kLargeBlock, false, META, ENUM, MULTI, FORM>(P) <= kLdsLimit)
+            launch_class<kLargeLogSlots, kLargeBlock, false, META, ENUM, MULTI, FORM, true>(P, s, device);
+        else if (v == TP_VAR_WAVE_SEARCH && wave_search_fits)
+            launch_class<0, kSmallBlock, true, META, ENUM, MULTI, FORM, true>(P, s, device);
+        else
+            launch_class<0, kSmallBlock, false, META, ENUM, MULTI, FORM, true>(P, s, device);
+        return;
+    }
     switch (v) {
     case TP_VAR_WAVE_TABLE:
         if (lds_need<kTinyLogSlots, kSmallBlock, true, META, ENUM, MULTI, FORM>(P) <= kLdsLimit)
@@ -1228,10 +1241,9 @@ void launch_variant(int c, uint32_t v, const SurveyParams &P0, hipStream_t s, in
             launch_class<0, kSmallBlock, false, META, ENUM, MULTI, FORM>(P, s, device);
         break;
     case TP_VAR_GROUP_TABLE:
-        // large targets and the pieces of huge ones fill the large tables
-        if (c >= kClassLarge && lds_need<kLargeLogSlots, kLargeBlock, false, META, ENUM, MULTI, FORM>(P) <= kLdsLimit)
+        if (c == kClassLarge && lds_need<kLargeLogSlots, kLargeBlock, false, META, ENUM, MULTI, FORM>(P) <= kLdsLimit)
             launch_class<kLargeLogSlots, kLargeBlock, false, META, ENUM, MULTI, FORM>(P, s, device);
-        else if (c < kClassLarge && lds_need<kSmallLogSlots, kSmallBlock, false, META, ENUM, MULTI, FORM>(P) <= kLdsLimit)
+        else if (c != kClassLarge && lds_need<kSmallLogSlots, kSmallBlock, false, META, ENUM, MULTI, FORM>(P) <= kLdsLimit)
             launch_class<kSmallLogSlots, kSmallBlock, false, META, ENUM, MULTI, FORM>(P, s, device);
         else
             launch_class<0, kSmallBlock, false, META, ENUM, MULTI, FORM>(P, s, device);
@@ -1328,7 +1340,6 @@ SurveyParams make_params(const tp_graph *g, const tp_survey_spec *sp, unsigned l
     P.inpay = g->inpay.get();
     P.piece_key = g->piece_key.get();
     P.piece_pay = g->piece_pay.get();
-    P.piece_recs = 0;
     P.kbits = g->kbits;
     P.tile_counter = counter;
     P.out = out;
