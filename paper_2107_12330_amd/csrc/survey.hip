@@ -44,10 +44,12 @@ constexpr int kSmallBlock = 256;   // 4 waves share a small target's tables
 constexpr int kLargeBlock = 1024;  // 16 waves share a large target's tables
 // Candidate loads in flight per wave: a chunk is kSub sub-rows of 64
 // candidates of one record, a batch is kBatch chunks, and two batches are in
-// flight.  The per-wave form serves short rows (tiny targets, small graphs):
-// shorter chunks, more of them.
+// flight.  The per-wave form serves short rows (tiny targets, small graphs;
+// on the scale-26 workload 13.5 candidates per record): chunks of one
+// sub-row, two of them per batch (2 sub-rows per chunk: 20,000-graph batch
+// survey 572.6 against 540.0 ms).
 template <bool WAVE> struct Depth {
-    static constexpr int kSub = WAVE ? 2 : 4;
+    static constexpr int kSub = WAVE ? 1 : 4;
     static constexpr int kBatch = WAVE ? 2 : 1;
     static constexpr uint32_t kChunkCand = kSub * 64;
 };
