@@ -9,6 +9,7 @@ import pytest
 import oracle
 import synth
 from paper_2107_12330_amd import tripoll as tp
+from tests import graphs
 
 pytestmark = pytest.mark.gpu
 
@@ -49,8 +50,8 @@ def canon(recs):
     return out
 
 
-def oracle_records(n, src, dst, ts, vlab, window=None, label_mask=None):
-    r = oracle.survey(n, src, dst, ts, vlab, outputs=("count",), n_labels=4, records=True)["records"]
+def oracle_records(n, src, dst, ts, vlab, window=None, label_mask=None, n_labels=4):
+    r = oracle.survey(n, src, dst, ts, vlab, outputs=("count",), n_labels=n_labels, records=True)["records"]
     want = set()
     for x in zip(*(r[f].tolist() for f in ("a", "b", "c", "t_ab", "t_ac", "t_bc", "l_a", "l_b", "l_c"))):
         if window is not None and not all(window[0] <= t <= window[1] for t in x[3:6]):
@@ -143,6 +144,20 @@ def test_small_capacity_refused_then_resumed(torch_cuda):
             assert set(got) == want and len(got) == total
         finally:
             tp.tripoll_enum_close(e)
+
+
+def test_stream_huge_targets_random(torch_cuda):
+    # targets of d+ above 3276 whose records straddle the pieces of Adj+(q)
+    # at irregular places; a label mask keeps the triangles labelled (0, 0, x)
+    T = torch_cuda
+    n, src, dst, ts, vlab = graphs.huge_targets(808)
+    mask = [oracle.msidx(0, 0, c) for c in range(5)]
+    want = oracle_records(n, src, dst, ts, vlab, label_mask=set(mask), n_labels=5)
+    say("enum stream huge targets", len(want))
+    with gpu_build(T, n, src, dst, ts, vlab) as G:
+        assert G.stats()["class_tiles"][3] > 0
+        got, total, _, chunks = stream_all(T, G, max(1, len(want) // 4 + 1), n_labels=5, label_mask=mask)
+    assert total == len(want) and len(got) == len(set(got)) and set(got) == want and chunks >= 4
 
 
 def test_stream_huge_targets_and_empty(torch_cuda):
