@@ -620,8 +620,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(the survey shards by splitting the work prefix, see the design notes)" % args.gpus,
+        print("bench.py: the survey runs on one GPU; --gpus %d is not supported "
+              "(across GPUs it would shard by splitting the work prefix of the targets)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
