@@ -13,6 +13,7 @@ import pytest
 import oracle
 import synth
 from paper_2107_12330_amd import tripoll as tp
+from tests import graphs as shaped
 
 pytestmark = pytest.mark.gpu
 
@@ -148,6 +149,35 @@ def test_batch_kinds_and_strategies(torch_cuda, outputs, strategy):
                 assert np.array_equal(got[i]["close_hist"], ref["close_hist"]), i
             if "label_table" in outputs:
                 assert np.array_equal(got[i]["label_table"], ref["label_table"]), i
+
+
+def test_batch_with_huge_targets(torch_cuda):
+    """A batch holding a graph with targets of d+ above 3276 (surveyed in
+    pieces of Adj+(q)) beside small ones: every block equals the graph's
+    survey alone, eager and from a recorded launch."""
+    torch = torch_cuda
+    n, s, t, ts, vl = shaped.huge_targets(515)
+    batch = small_batch()[:5] + [(n, s, t, ts, vl)] + small_batch()[5:9]
+    stream = torch.cuda.current_stream().cuda_stream
+    spec = tp.make_spec(outputs=("count", "close_hist", "label_table"), n_labels=8)
+    G, out, got = run_batch(torch, batch, spec, 8)
+    with G:
+        assert G.stats()["class_tiles"][3] > 0
+        rec = torch.zeros_like(out)
+        with tp.Launch(tp.tripoll_survey_capture(G.handle, spec, rec.data_ptr())) as L:
+            L.replay(stream)
+            torch.cuda.synchronize()
+        replayed = tp.batch_dicts(rec.cpu().numpy().view(np.uint64), len(batch), spec, 8)
+        for i, (gn, gs, gt, gts, gvl) in enumerate(batch):
+            if gn == 0:
+                continue
+            dev = [upload(torch, x) for x in (gs, gt, gts, gvl)]
+            with tp.build_graph(gn, *dev, stream=stream) as H:
+                one = tp.survey(H, stream=stream, outputs=("count", "close_hist", "label_table"), n_labels=8)
+            say("graph %d: %d triangles" % (i, one["triangles"]))
+            for k in ("triangles", "close_hist", "label_table"):
+                assert np.array_equal(np.asarray(got[i][k]), np.asarray(one[k])), (i, k)
+                assert np.array_equal(np.asarray(replayed[i][k]), np.asarray(one[k])), (i, k)
 
 
 def test_recorded_launch_replays(torch_cuda):
