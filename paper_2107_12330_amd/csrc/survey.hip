@@ -146,16 +146,17 @@ struct SurveyParams {
 // and slot counts exist in the participation form only, which has no rings.
 struct LdsLayout {
     uint32_t slots;
-    size_t off_hts, off_hlab, off_hdir, off_hpos, off_hcnt, off_ring, off_cnt, off_lut, total;
+    size_t off_hts, off_hlab, off_hdir, off_hbin, off_hpos, off_hcnt, off_ring, off_cnt, off_lut, total;
 };
 // (the enumeration form keeps each key's original id where participation
 // keeps row positions)
 
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// bins: the degree bin of each key (extended form with the degree table)
 __host__ __device__ inline LdsLayout lds_layout(uint32_t slots, bool meta, uint32_t counter_words, int waves,
                                                 uint32_t lut_shift, bool part = false, bool dir = false,
-                                                bool ids = false)
+                                                bool ids = false, bool bins = false)
 {
     LdsLayout L;
     L.slots = slots;
@@ -166,6 +167,8 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t slots, bool meta, uint3
     if (meta) o += slots;
     L.off_hdir = o;
     if (dir) o += slots;
+    L.off_hbin = o;
+    if (bins) o += slots;
     o = align_up(o, 16);
     L.off_hpos = o;
     if (part || ids) o += (size_t)slots * 4;
@@ -430,7 +433,9 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     static_assert(!(EXT || PART) || (META && !ENUM && !MULTI), "extended forms are single-request metadata surveys");
     const uint32_t nc = counter_words<MULTI, FORM>(P);
     const bool kdir = EXT && P.dir_words;  // the directed census
-    const LdsLayout L = lds_layout(kSlots * kGroups, META || ENUM, nc * kGroups, kWaves, P.lut_shift, PART, kdir, ENUM);
+    const bool kbins = EXT && (P.outputs & TP_OUT_DEGREE_TABLE);  // the degree table
+    const LdsLayout L =
+        lds_layout(kSlots * kGroups, META || ENUM, nc * kGroups, kWaves, P.lut_shift, PART, kdir, ENUM, kbins);
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
     const int grp = WAVE ? w : 0;     // this thread's group
@@ -440,6 +445,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     uint32_t *hts = reinterpret_cast<uint32_t *>(lds + L.off_hts) + (size_t)grp * kSlots;
     uint8_t *hlab = lds + L.off_hlab + (size_t)grp * kSlots;
     uint8_t *hdir = lds + L.off_hdir + (size_t)grp * kSlots;  // EXT, directed census
+    uint8_t *hbin = lds + L.off_hbin + (size_t)grp * kSlots;  // EXT, degree table: bin of each key
     uint32_t *hpos = reinterpret_cast<uint32_t *>(lds + L.off_hpos) + (size_t)grp * kSlots;  // PART; ENUM: ids
     uint32_t *hcnt = reinterpret_cast<uint32_t *>(lds + L.off_hcnt) + (size_t)grp * kSlots;  // PART
     unsigned long long *cnt_all = reinterpret_cast<unsigned long long *>(lds + L.off_cnt);
@@ -527,6 +533,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
 
     // the target whose out-list is in the LDS table, and its geometry
     uint32_t cur_q = 0xffffffffu, cur_piece = 0;
+    uint32_t bin_q = 0;  // degree bin of cur_q (extended form, degree table)
     uint32_t id_q = 0;  // original id of cur_q (enumeration)
     uint64_t kq = 0;
     uint32_t dq = 0, l_q = 0, log_s = 0;
@@ -562,11 +569,11 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                 h.l_r = P.tlab[kq + where];
             }
             if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE)) {
-                // the ring's last word holds the pivot's degree bin
-                const uint32_t r = !G ? hkey[where] : P.col[kq + where];
+                // the ring's last word holds the pivot's degree bin; the
+                // table keeps that of every key
                 h.b_p = e.w & 0xffu;
-                h.b_q = degree_bin_of(dbin_lds, cur_q);
-                h.b_r = degree_bin_of(dbin_lds, r);
+                h.b_q = bin_q;
+                h.b_r = !G ? hbin[where] : degree_bin_of(dbin_lds, P.col[kq + where]);
             }
             if (kdir) {
                 // ... and the directions of (p, q) and (p, r) above it
@@ -699,6 +706,8 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                 dq = (uint32_t)(sload(P.rowptr + cur_q + 1) - kq);
                 l_q = META ? __builtin_amdgcn_readfirstlane(P.rlab[cur_q]) : 0u;
                 if (ENUM) id_q = sload(P.perm + cur_q);
+                if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE))
+                    bin_q = __builtin_amdgcn_readfirstlane(degree_bin_of(dbin_lds, cur_q));
                 pk0 = PIECES ? min(cur_piece, piece_count(dq)) * piece_size(dq) : 0u;
                 pn = PIECES ? (pk0 < dq ? min(dq - pk0, piece_size(dq)) : 0u) : dq;
                 log_s = 5;
@@ -755,6 +764,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                                 hcnt[h] = 0;
                             }
                             if (kdir) hdir[h] = P.edir[kq + pk0 + i];
+                            if (kbins) hbin[h] = (uint8_t)degree_bin_of(dbin_lds, r);
                             if (ENUM) hpos[h] = P.perm[r];
                         }
                     }
@@ -1136,7 +1146,8 @@ size_t lds_need(const SurveyParams &P)
     const uint32_t slots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
     const uint32_t nc = counter_words<MULTI, FORM>(P);
     return lds_layout(slots * groups, META || ENUM, nc * groups, BLOCK / kWave, P.lut_shift, FORM == kFormPart,
-                      FORM == kFormExt && P.dir_words, ENUM)
+                      FORM == kFormExt && P.dir_words, ENUM,
+                      FORM == kFormExt && (P.outputs & TP_OUT_DEGREE_TABLE))
         .total;
 }
 
@@ -1148,7 +1159,8 @@ void launch_class(const SurveyParams &P, hipStream_t s, int device)
     const uint32_t slots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
     const uint32_t nc = counter_words<MULTI, FORM>(P);
     const LdsLayout L = lds_layout(slots * groups, META || ENUM, nc * groups, BLOCK / kWave, P.lut_shift,
-                                   FORM == kFormPart, FORM == kFormExt && P.dir_words, ENUM);
+                                   FORM == kFormPart, FORM == kFormExt && P.dir_words, ENUM,
+                                   FORM == kFormExt && (P.outputs & TP_OUT_DEGREE_TABLE));
     if (L.total > kLdsLimit)
         fail(TP_ERR_UNSUPPORTED, "tripoll_survey: the requested outputs need more LDS than a workgroup may hold");
     auto kern = survey_kernel<LOG_SLOTS, BLOCK, WAVE, META, ENUM, MULTI, FORM, PIECES>;
