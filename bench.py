@@ -66,13 +66,23 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(st: dict, c: int, meta: bool) -> int:
-    """Bytes the survey of class c must move, per launch.
-    Per wedge check: the candidate r (4 B) and, for metadata surveys, the
-    time of edge (p, r) that travels with it (4 B) -- the payload of a push in
-    Algorithm 1.  Per staged out-list entry of a target: id, and for metadata
-    surveys its edge time and target label (4 or 9 B).  Per in-edge record
-    16 B, per tile 16 B descriptor + 16 B of row pointers."""
+def algorithmic_bytes(st: dict, c: int, meta: bool, hits: int) -> int:
+    """Bytes the survey of target class c must move, per launch, by the
+    work model of the q-centric survey: per wedge check the candidate r
+    (4 B); per hit the time of edge (p, r) (4 B, metadata surveys only); per
+    staged out-list entry of a target its rank, and for metadata surveys its
+    edge time and label (4 or 9 B); per in-edge record 8 B; per tile its two
+    row pointers (16 B)."""
+    per_staged = 9 if meta else 4
+    return (4 * st["class_probes"][c] + (4 * hits if meta else 0) + per_staged * st["class_staged"][c]
+            + 8 * st["class_records"][c] + 16 * st["class_tiles"][c])
+
+
+def loaded_bytes(st: dict, c: int, meta: bool) -> int:
+    """Bytes the kernel of class c loads by design: every candidate's rank
+    and, for metadata surveys, its edge time (a hit rate near one in five
+    touches nearly every line of times anyway), each staged entry, the
+    in-edge records with their time(p, q) gather, and the tiles."""
     per_probe = 8 if meta else 4
     per_staged = 9 if meta else 4
     return (per_probe * st["class_probes"][c] + per_staged * st["class_staged"][c] + 16 * st["class_records"][c]
@@ -93,6 +103,13 @@ def load_traffic(key: str, workload_name: str):
     return None if v is None else int(v["hbm_bytes_per_launch"])
 
 
+# The oracle's own run of the full scale-26 workload (single-threaded clean,
+# then the survey on 8 threads), as stored beside its result by
+# tests/golden/make_golden.py on the 8-core build host.
+FULL_C3_ORACLE = {"triangles": 49164311615, "clean_s": 297.47, "survey_s": 1968.17, "threads": 8,
+                  "host": "8-core Intel Xeon Processor @ 2.70GHz"}
+
+
 def cpu_baseline(scale: int, threads: int) -> dict:
     """The oracle (clean + survey) on a bounded sample: the same recipe at a
     smaller R-MAT scale, timed on this host's cores."""
@@ -105,10 +122,15 @@ def cpu_baseline(scale: int, threads: int) -> dict:
     r = oracle.survey_clean(g["n"], u, v, t, g["vlab"], outputs=w.outputs, n_labels=4, spread_lt=w.spread_lt,
                             threads=threads)
     dt = time.perf_counter() - t0
+    full = FULL_C3_ORACLE
     return {"value": r["triangles"] / dt, "unit": "triangles/s", "cores": threads, "kind": "oracle",
-            "sample": "full oracle pipeline (single-threaded clean, then orient + survey on %d threads, same "
-                      "outputs) on R-MAT scale %d of the same recipe: %d triangles in %.2f s"
-                      % (threads, scale, r["triangles"], dt)}
+            "sample": "R-MAT scale %d of the scale-26 recipe (%s: bursty times, labels 0..3, same outputs), not "
+                      "the scale-26 input itself: full oracle pipeline (single-threaded clean, then orient + "
+                      "survey on %d threads), %d triangles in %.2f s"
+                      % (scale, w.name, threads, r["triangles"], dt),
+            "full_config_oracle": dict(full, triangles_per_s=round(full["triangles"] /
+                                                                   (full["clean_s"] + full["survey_s"]), 1),
+                                       input="rmat-s26-bursty (the bench workload itself)")}
 
 
 def oracle_table(threads: int, workloads=(1, 2), sample_scale: int | None = None) -> dict:
@@ -173,25 +195,13 @@ def batch_bench(args, torch, synth, tp) -> dict:
     M, N = int(eoff[-1]), int(vcnt.sum())
     stream = torch.cuda.current_stream()
     sptr = stream.cuda_stream
-    log("batch of %d graphs: %d vertices, %d raw edges; generating" % (G, N, M))
+    log("batch of %d graphs: %d vertices, %d raw edges; generating on the device" % (G, N, M))
     t0 = time.perf_counter()
-    src = torch.empty(M, dtype=torch.int32, device="cuda")
-    dst = torch.empty_like(src)
-    ts = torch.empty_like(src)
-    vlab = torch.empty(N, dtype=torch.uint8, device="cuda")
-    v0 = 0
-    chunk = 1000
-    for lo in range(0, G, chunk):
-        hi = min(G, lo + chunk)
-        d = synth.generate_batch(specs[lo:hi])
-        e0, e1 = int(eoff[lo]), int(eoff[hi])
-        for dev, k in ((src, "src"), (dst, "dst"), (ts, "ts")):
-            dev[e0:e1].copy_(torch.from_numpy(d[k].view(np.int32)))
-        vlab[v0:v0 + len(d["vlab"])].copy_(torch.from_numpy(d["vlab"]))
-        v0 += len(d["vlab"])
-        del d
-        log("  graphs %d..%d generated (%.1f s)" % (lo, hi, time.perf_counter() - t0))
+    d = synth.generate_batch_device(specs, torch)
+    src, dst, ts, vlab = d["src"], d["dst"], d["ts"], d["vlab"]
+    del d
     torch.cuda.synchronize()
+    log("  generated in %.1f s" % (time.perf_counter() - t0))
     outputs = w.outputs
     spec = tp.make_spec(outputs=outputs, n_labels=w.n_labels)
     bw = tp.tripoll_batch_words(spec)
@@ -561,7 +571,8 @@ def kind_bench(args, torch, synth, tp) -> dict:
     ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
     st, tri, written, _, r = per[-1]
     kind_ms = statistics.median(x[3] for x in per)
-    alg = sum(algorithmic_bytes(st, c, True) for c in range(4)) + written
+    hits = r["class_triangles"] if r is not None else [0] * 4
+    alg = sum(algorithmic_bytes(st, c, True, hits[c]) for c in range(4)) + written
     achieved = alg / (kind_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC, "value": tri / (ms_per_step * 1e-3), "unit": "triangles/s", "n_gpus": 1,
@@ -732,18 +743,31 @@ def main():
 
     # dominant survey kernel
     cls_ms = [statistics.mean(rr["class_ms"][c] for _, _, rr in per) for c in range(4)]
+    hits = r["class_triangles"]
     c = int(np.argmax(cls_ms))
-    alg = algorithmic_bytes(st, c, meta)
+    alg = algorithmic_bytes(st, c, meta, hits[c])
+    loaded = loaded_bytes(st, c, meta)
     achieved = alg / (cls_ms[c] * 1e-3) / 1e9
     var = st["plan"]["variant"][c]
     key = kernel_key(c, var, meta)
     traffic = load_traffic(key, w.name)
+    survey_alg = sum(algorithmic_bytes(st, k, meta, hits[k]) for k in range(4))
+    survey_t = statistics.median(kernel_ms) * 1e-3
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "%s: class %s, %s" % (key, CLASS_NAMES[c], VARIANT_NAMES[resolve_variant(c, var)]),
-                "traffic_per_algorithmic_byte": None if traffic is None else round(traffic / alg, 3),
                 "kernel_ms": round(cls_ms[c], 3), "algorithmic_bytes": int(alg),
-                "wedge_checks": int(st["class_probes"][c])}
+                "algorithmic_model": "4 B per wedge check + 4 B per hit + %d B per staged out-list entry + 8 B per "
+                                     "in-edge record + 16 B per tile" % (9 if meta else 4),
+                "wedge_checks": int(st["class_probes"][c]), "hits": int(hits[c]),
+                "staged": int(st["class_staged"][c]), "records": int(st["class_records"][c]),
+                "tiles": int(st["class_tiles"][c]),
+                "traffic_frac": None if traffic is None else round(traffic / (cls_ms[c] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic_per_algorithmic_byte": None if traffic is None else round(traffic / alg, 3),
+                "loaded_bytes": int(loaded),
+                "loaded_frac": round(loaded / (cls_ms[c] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "survey_algorithmic_bytes": int(survey_alg),
+                "survey_frac": round(survey_alg / survey_t / 1e9 / HBM_PEAK_GBS, 4)}
 
     out = {
         "metric": METRIC,

@@ -264,11 +264,15 @@ typedef struct {
     float kernel_ms;         /* device time of the intersection kernels */
     float total_ms;          /* device time of the whole survey call */
     float class_ms[TP_NUM_CLASSES]; /* device time of the kernel of each target class */
+    uint64_t class_triangles[TP_NUM_CLASSES]; /* triangles counted by each target class's kernel
+                                                 (their sum is `triangles`) */
 } tp_survey_result;
 
 /* Word layout of a device result buffer (uint64[TP_RESULT_WORDS]).  The
- * last TP_RW_SCRATCH_WORDS words are work counters used by the survey
- * itself; their content is unspecified. */
+ * last TP_RW_SCRATCH_WORDS words are used by the survey itself: the first
+ * four are work counters whose content is unspecified; then, at
+ * TP_RW_CLASS_TRI + c, the triangles counted by target classes 0..c (a
+ * running sum, taken after each class's kernel). */
 #define TP_RW_TRIANGLES 0u
 #define TP_RW_SPREAD 1u
 #define TP_RW_PROBES 2u
@@ -279,7 +283,8 @@ typedef struct {
 #define TP_RW_DEGREE (TP_RW_MAX_EDGE + TP_MAX_EDGE_BINS)
 #define TP_RW_DIRECTED (TP_RW_DEGREE + TP_DEGREE_MAX)
 #define TP_RW_SCRATCH (TP_RW_DIRECTED + 8u)
-#define TP_RW_SCRATCH_WORDS 4u
+#define TP_RW_SCRATCH_WORDS 8u
+#define TP_RW_CLASS_TRI (TP_RW_SCRATCH + 4u)
 #define TP_RESULT_WORDS (TP_RW_SCRATCH + TP_RW_SCRATCH_WORDS)
 
 /*
@@ -440,7 +445,11 @@ tp_status tripoll_survey_batch(const tp_graph *g, const tp_survey_spec *spec, ui
  * tripoll_survey_batch for one graph, spec and output buffer, captured once
  * into an executable HIP graph and replayed with one launch call.
  *   tripoll_survey_capture  records it (synchronous); `dev_out` as for
- *                           tripoll_survey_batch and bound to the launch
+ *                           tripoll_survey_batch and bound to the launch.
+ *                           Recording runs one survey first, on a private
+ *                           stream into a temporary buffer of its own (so
+ *                           that every kernel is set up before the capture);
+ *                           it does not write dev_out, which only replays do
  *   tripoll_launch_replay   enqueues one replay on `stream`; replays on one
  *                           launch must not overlap (they share dev_out)
  *   tripoll_launch_free     releases it (NULL accepted); the graph must
@@ -622,6 +631,18 @@ tp_status tripoll_trim(void);
 
 /* Bytes currently cached by the allocator on the current device. */
 tp_status tripoll_cached_bytes(uint64_t *out);
+
+/* Device bytes the library's allocator has handed out on the current device
+ * and not yet released (graphs, servers, temporaries of calls in progress;
+ * the cache of released blocks is not counted). */
+tp_status tripoll_live_bytes(uint64_t *out);
+
+/* Fault injection for tests of the error paths: the n-th device allocation
+ * the library makes from now on (n >= 1, counted over all threads and
+ * devices) fails once, as if the device were out of memory, so the call
+ * making it returns TP_ERR_OOM and must release everything it took; n = 0
+ * switches the injection off. */
+tp_status tripoll_fail_alloc_after(uint64_t n);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *tripoll_last_error(void);

@@ -69,3 +69,16 @@ extern "C" tp_status tripoll_cached_bytes(uint64_t *out)
         *out = dev_cached_bytes();
     });
 }
+
+extern "C" tp_status tripoll_live_bytes(uint64_t *out)
+{
+    return guard([&] {
+        if (!out) fail(TP_ERR_INVALID, "tripoll_live_bytes: NULL");
+        *out = dev_live_bytes();
+    });
+}
+
+extern "C" tp_status tripoll_fail_alloc_after(uint64_t n)
+{
+    return guard([&] { dev_fail_after(n); });
+}

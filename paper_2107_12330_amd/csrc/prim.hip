@@ -2,6 +2,7 @@
 // per-thread error state, the caching device allocator, exclusive scans and
 // a stable LSD radix sort of (uint64 key, uint32 value) pairs.
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -55,10 +56,22 @@ void trim_locked(Pool &p)
     p.cached = 0;
 }
 
+// Fault injection: when non-zero, the allocation that brings it to zero
+// fails as if the device were out of memory.
+std::atomic<uint64_t> g_fail_countdown{0};
+
 }  // namespace
+
+void dev_fail_after(uint64_t n) { g_fail_countdown.store(n); }
 
 void *dev_alloc(size_t bytes)
 {
+    for (uint64_t c = g_fail_countdown.load(); c;) {
+        if (g_fail_countdown.compare_exchange_weak(c, c - 1)) {
+            if (c == 1) fail(TP_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed (injected)");
+            break;
+        }
+    }
     Pool &p = pool_for_current_device();
     const size_t sz = round_size(bytes ? bytes : 1);
     std::lock_guard<std::mutex> lk(p.mu);
@@ -113,6 +126,15 @@ size_t dev_cached_bytes()
     Pool &p = pool_for_current_device();
     std::lock_guard<std::mutex> lk(p.mu);
     return p.cached;
+}
+
+size_t dev_live_bytes()
+{
+    Pool &p = pool_for_current_device();
+    std::lock_guard<std::mutex> lk(p.mu);
+    size_t b = 0;
+    for (const auto &kv : p.live) b += kv.second;
+    return b;
 }
 
 // ================================================================ fill

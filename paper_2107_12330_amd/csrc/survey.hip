@@ -139,6 +139,9 @@ struct SurveyParams {
     const SlotSpec *slots;
     uint32_t n_slots, slot_words, slot_labels;
     uint32_t grid_eighths;    // share of the device the persistent grid may fill (0 or 8: all)
+    // single-graph surveys: after class c, the running triangle count is
+    // copied to class_tri[c] (so that each class's triangles are known)
+    unsigned long long *class_tri;
 };
 
 // LDS layout (dynamic): [hash keys][hash times][hash labels]
@@ -1054,6 +1057,12 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     flush(cur_g);
 }
 
+// dst = *src, by one thread (a snapshot of a counter between launches)
+__global__ void k_copy_word(const unsigned long long *src, unsigned long long *dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
 __global__ void zero_u64(unsigned long long *p, size_t n)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
@@ -1288,6 +1297,10 @@ void launch_all(const tp_graph *g, SurveyParams P, uint32_t strategy, hipStream_
         if (timers) timers[c].start();
         launch_variant<META, ENUM, false, FORM>(c, resolve_variant(g, c, strategy), P, s, g->device);
         if (timers) timers[c].stop();
+        if (P.class_tri) {
+            k_copy_word<<<1, 64, 0, s>>>(P.out + P.o_tri, P.class_tri + c);
+            TP_CHECK_LAUNCH();
+        }
     }
 }
 
@@ -1426,6 +1439,7 @@ void survey_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned long l
     TP_CHECK_LAUNCH();
     SurveyParams P = make_params(g, sp, dev_out, dev_out + TP_RW_SCRATCH);
     if (g->m == 0 || g->n_in == 0) return;
+    if (!ENUM) P.class_tri = dev_out + TP_RW_CLASS_TRI;
     if (ENUM) {
         P.enum_out = enum_out;
         P.enum_cap = enum_cap;
@@ -1489,6 +1503,8 @@ void copy_result(const std::vector<unsigned long long> &h, tp_survey_result *out
     for (uint32_t i = 0; i < TP_MAX_EDGE_BINS; ++i) out->max_edge[i] = h[TP_RW_MAX_EDGE + i];
     for (uint32_t i = 0; i < TP_DEGREE_MAX; ++i) out->degree_table[i] = h[TP_RW_DEGREE + i];
     for (uint32_t i = 0; i < 7; ++i) out->directed[i] = h[TP_RW_DIRECTED + i];
+    for (int c = 0; c < kNumClasses; ++c)
+        out->class_triangles[c] = h[TP_RW_CLASS_TRI + c] - (c ? h[TP_RW_CLASS_TRI + c - 1] : 0ull);
 }
 
 }  // namespace
@@ -1767,15 +1783,21 @@ extern "C" tp_status tripoll_survey_capture(const tp_graph *g, const tp_survey_s
         if (!dev_out || !out) fail(TP_ERR_INVALID, "tripoll_survey_capture: NULL argument");
         validate_spec(g, spec);
         // the kernels' attributes are set outside the capture: one eager
-        // survey on a private stream prepares every launch
+        // survey on a private stream prepares every launch.  It writes a
+        // temporary buffer of the same size, never dev_out, which work on
+        // the caller's streams may still be using.
         hipStream_t cs = nullptr;
         TP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         struct StreamGuard {
             hipStream_t s;
             ~StreamGuard() { (void)hipStreamDestroy(s); }
         } sg{cs};
-        survey_batch_enqueue(g, spec, reinterpret_cast<unsigned long long *>(dev_out), cs);
-        TP_HIP(hipStreamSynchronize(cs));
+        {
+            const uint64_t words = (uint64_t)graph_count(g) * batch_words(spec) + TP_BATCH_SCRATCH_WORDS;
+            DArray<unsigned long long> prep(words, cs);
+            survey_batch_enqueue(g, spec, prep.get(), cs);
+            TP_HIP(hipStreamSynchronize(cs));
+        }
         auto L = std::make_unique<tp_launch>();
         TP_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         try {

@@ -68,6 +68,8 @@ void *dev_alloc(size_t bytes);
 void dev_release(void *p, hipStream_t stream);
 void dev_trim();
 size_t dev_cached_bytes();
+size_t dev_live_bytes();   // bytes handed out and not yet released
+void dev_fail_after(uint64_t n);  // fault injection: the n-th allocation from now fails (0: off)
 
 // Owning device array, released into the cache.
 template <class T>

@@ -40,7 +40,8 @@ TP_RW_MAX_EDGE = TP_RW_OPEN_CLOSE + 1024
 TP_RW_DEGREE = TP_RW_MAX_EDGE + TP_MAX_EDGE_BINS
 TP_RW_DIRECTED = TP_RW_DEGREE + TP_DEGREE_MAX
 TP_RW_SCRATCH = TP_RW_DIRECTED + 8
-TP_RESULT_WORDS = TP_RW_SCRATCH + 4
+TP_RW_CLASS_TRI = TP_RW_SCRATCH + 4
+TP_RESULT_WORDS = TP_RW_SCRATCH + 8
 TP_BW_TRIANGLES, TP_BW_SPREAD, TP_BW_PROBES, TP_BW_HIST, TP_BW_TABLE = 0, 1, 2, 3, 35
 TP_BATCH_SCRATCH_WORDS = 4
 
@@ -86,7 +87,8 @@ class tp_survey_result(ctypes.Structure):
                 ("open_close", ctypes.c_uint64 * 1024), ("max_edge", ctypes.c_uint64 * TP_MAX_EDGE_BINS),
                 ("degree_table", ctypes.c_uint64 * TP_DEGREE_MAX), ("directed", ctypes.c_uint64 * 8),
                 ("kernel_ms", ctypes.c_float),
-                ("total_ms", ctypes.c_float), ("class_ms", ctypes.c_float * TP_NUM_CLASSES)]
+                ("total_ms", ctypes.c_float), ("class_ms", ctypes.c_float * TP_NUM_CLASSES),
+                ("class_triangles", ctypes.c_uint64 * TP_NUM_CLASSES)]
 
 
 class tp_plan(ctypes.Structure):
@@ -168,6 +170,8 @@ SIGNATURES = {
     "tripoll_msidx": (ctypes.c_uint32, [ctypes.c_uint32] * 3),
     "tripoll_trim": (ctypes.c_int, []),
     "tripoll_cached_bytes": (ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64)]),
+    "tripoll_live_bytes": (ctypes.c_int, [ctypes.POINTER(ctypes.c_uint64)]),
+    "tripoll_fail_alloc_after": (ctypes.c_int, [ctypes.c_uint64]),
     "tripoll_last_error": (ctypes.c_char_p, []),
     "tripoll_version": (ctypes.c_char_p, []),
 }
@@ -378,6 +382,16 @@ def tripoll_cached_bytes() -> int:
     return v.value
 
 
+def tripoll_live_bytes() -> int:
+    v = ctypes.c_uint64(0)
+    _check(load().tripoll_live_bytes(ctypes.byref(v)))
+    return v.value
+
+
+def tripoll_fail_alloc_after(n: int) -> None:
+    _check(load().tripoll_fail_alloc_after(n))
+
+
 def tripoll_version() -> str:
     return load().tripoll_version().decode()
 
@@ -415,7 +429,8 @@ def result_dict(res: tp_survey_result, n_labels: int = 16) -> dict:
                 degree_table=np.frombuffer(bytes(res.degree_table), np.uint64).copy(),
                 directed=np.frombuffer(bytes(res.directed), np.uint64)[:7].copy(),
                 kernel_ms=float(res.kernel_ms), total_ms=float(res.total_ms),
-                class_ms=[float(x) for x in res.class_ms])
+                class_ms=[float(x) for x in res.class_ms],
+                class_triangles=[int(x) for x in res.class_triangles])
 
 
 def words_dict(words: np.ndarray, n_labels: int = 16) -> dict:

@@ -25,6 +25,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tpgen.c")
 _LIB = os.path.join(_HERE, "libtpgen.so")
+_DEV_SRC = os.path.join(_HERE, "tpgen_dev.hip")
+_DEV_LIB = os.path.join(_HERE, "libtpgen_dev.so")
 
 # R-MAT quadrant thresholds floor(p * 2^32) for a=0.57, a+b=0.76, a+b+c=0.95.
 RMAT_THR = ((57 << 32) // 100, (76 << 32) // 100, (95 << 32) // 100)
@@ -38,13 +40,21 @@ _lib = None
 
 
 def build(verbose: bool = False) -> str:
-    """Compile libtpgen.so with gcc (OpenMP)."""
+    """Compile libtpgen.so with gcc (OpenMP) and the device batch generator
+    libtpgen_dev.so with hipcc for gfx950."""
     cmd = ["gcc", "-O3", "-march=x86-64-v2", "-fopenmp", "-fPIC", "-shared",
            "-std=c11", "-Wall", "-o", _LIB + ".tmp", _SRC]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
     os.replace(_LIB + ".tmp", _LIB)
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    cmd = [hipcc, "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950", "-Wall",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-o", _DEV_LIB + ".tmp", _DEV_SRC]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(_DEV_LIB + ".tmp", _DEV_LIB)
     return _LIB
 
 
@@ -242,3 +252,73 @@ def generate_batch(specs: list) -> dict:
         fill_labels(s, vlab[v0:v0 + s.n])
         v0 += s.n
     return dict(src=src, dst=dst, ts=ts, vlab=vlab, edge_offsets=eoff, vertex_counts=vcnt)
+
+
+# --------------------------------------------------------------------------
+# Device generation of a batch (tpgen_dev.hip): the same values as
+# generate_batch, written straight into device memory.
+# --------------------------------------------------------------------------
+
+_dev_lib = None
+_DEV_GRAPH = np.dtype([("seed", np.uint64), ("edge_offset", np.uint64), ("n_edges", np.uint64),
+                       ("vertex_offset", np.uint64), ("kind", np.uint32), ("scale", np.uint32),
+                       ("ts_bits", np.uint32), ("n_labels", np.uint32)])
+_DEV_CHUNK = np.dtype([("graph", np.uint32), ("count", np.uint32), ("first", np.uint64)])
+_CHUNK_EDGES = 1 << 16
+
+
+def _load_dev():
+    global _dev_lib
+    if _dev_lib is not None:
+        return _dev_lib
+    if not os.path.exists(_DEV_LIB):
+        raise ImportError("libtpgen_dev.so is not built (run synth.build())")
+    lib = ctypes.CDLL(_DEV_LIB)
+    p, u32 = ctypes.c_void_p, ctypes.c_uint32
+    lib.tpgen_dev_batch.restype = ctypes.c_int
+    lib.tpgen_dev_batch.argtypes = [p, u32, p, u32, u32, u32, u32, p, p, p, p, p]
+    _dev_lib = lib
+    return lib
+
+
+def generate_batch_device(specs: list, torch, stream=None) -> dict:
+    """Raw inputs of a batch of uniform-time, uniform-label graphs generated
+    on the current device: int32 tensors src, dst, ts (uint32 values, local
+    ids) and a uint8 tensor vlab, with host arrays edge_offsets and
+    vertex_counts.  Byte for byte the arrays of generate_batch(specs)."""
+    eoff, vcnt = batch_offsets(specs)
+    G = len(specs)
+    recs = np.zeros(G, _DEV_GRAPH)
+    voff = 0
+    chunks = []
+    for i, s in enumerate(specs):
+        if s.ts[0] != "uniform" or s.labels[0] != "uniform":
+            raise ValueError("device batches take uniform times and labels")
+        recs[i] = (s.seed, int(eoff[i]), s.n_edges, voff, 0 if s.kind == "rmat" else 1, s.scale, s.ts[1],
+                   s.labels[1])
+        voff += s.n
+        nch = -(-s.n_edges // _CHUNK_EDGES)
+        if nch:
+            first = np.arange(nch, dtype=np.uint64) * _CHUNK_EDGES
+            cnt = np.minimum(np.uint64(s.n_edges) - first, _CHUNK_EDGES).astype(np.uint32)
+            ch = np.zeros(nch, _DEV_CHUNK)
+            ch["graph"], ch["count"], ch["first"] = i, cnt, first
+            chunks.append(ch)
+    chunks = np.concatenate(chunks) if chunks else np.zeros(0, _DEV_CHUNK)
+    M, N = int(eoff[-1]), int(vcnt.sum())
+    dev = "cuda"
+    d_recs = torch.from_numpy(recs.view(np.uint8)).to(dev)
+    d_chunks = torch.from_numpy(chunks.view(np.uint8)).to(dev)
+    src = torch.empty(max(M, 1), dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    ts = torch.empty_like(src)
+    vlab = torch.empty(max(N, 1), dtype=torch.uint8, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    st = _load_dev().tpgen_dev_batch(d_recs.data_ptr(), G, d_chunks.data_ptr(), len(chunks), *RMAT_THR,
+                                     src.data_ptr(), dst.data_ptr(), ts.data_ptr(), vlab.data_ptr(), stream)
+    if st != 0:
+        raise RuntimeError("tpgen_dev_batch: hip error %d" % st)
+    torch.cuda.synchronize()
+    del d_recs, d_chunks
+    return dict(src=src[:M], dst=dst[:M], ts=ts[:M], vlab=vlab[:N], edge_offsets=eoff, vertex_counts=vcnt)

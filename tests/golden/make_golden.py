@@ -13,6 +13,16 @@ tests regenerate the same inputs and compare against these files.
 the degree-log table and the directed census (the raw edges read as arcs
 src -> dst), and checksums of the per-vertex and per-edge participation
 counts (see participation_checksums).
+
+    python tests/golden/make_golden.py 4 --batch      # golden_batch_w4.json
+    python tests/golden/make_golden.py 5 --served     # golden_served_pool.json
+
+--batch surveys every graph of the 20,000-graph batch on its own (one oracle
+process per graph, in a pool) and stores every graph's triangle count, the
+sum of all closure histograms, and the full histogram of every 50th graph
+and of every scale-16 member.  --served stores, for each graph of the served
+pool (R-MAT scales 16..20), the oracle's answers to seeded requests of the
+served kinds: a full survey, a time window and a label predicate.
 """
 import argparse
 import gc
@@ -87,14 +97,135 @@ def extended(w, threads):
     }
 
 
+BATCH_STRIDE = 50
+
+
+def batch_sample(specs) -> list:
+    """Graphs whose full histograms are stored: every BATCH_STRIDE-th graph
+    and every member of the largest scale."""
+    top = max(s.scale for s in specs)
+    return sorted({g for g in range(0, len(specs), BATCH_STRIDE)} |
+                  {g for g, s in enumerate(specs) if s.scale == top})
+
+
+def _batch_member(arg):
+    g, spec = arg
+    d = synth.generate(spec)
+    r = oracle.survey(spec.n, d["src"], d["dst"], d["ts"], d["vlab"], outputs=("count", "close_hist"),
+                      n_labels=int(spec.labels[1]), threads=1)
+    return g, int(r["triangles"]), [int(x) for x in r["close_hist"]], int(r["m"])
+
+
+def batch(w, procs):
+    """Oracle survey of every graph of the batched workload, each alone."""
+    import multiprocessing as mp
+    ex = w.extra
+    specs = synth.batch_specs(ex["n_graphs"], scale_lo=ex["scale_lo"], scale_hi=ex["scale_hi"],
+                              ef_lo=ex["ef_lo"], ef_hi=ex["ef_hi"])
+    order = sorted(range(len(specs)), key=lambda g: -specs[g].n_edges)
+    tri = [0] * len(specs)
+    edges = [0] * len(specs)
+    hist = {}
+    total = np.zeros(32, np.uint64)
+    t0 = time.time()
+    # one thread per worker process: the generator's and the oracle's
+    # OpenMP runtimes read this when they start in the (spawned) workers
+    os.environ["OMP_NUM_THREADS"] = "1"
+    with mp.get_context("spawn").Pool(procs or os.cpu_count()) as pool:
+        for k, (g, t, h, m) in enumerate(pool.imap_unordered(_batch_member, [(g, specs[g]) for g in order],
+                                                             chunksize=4)):
+            tri[g], edges[g] = t, m
+            hist[g] = h
+            total += np.array(h, np.uint64)
+            if k % 1000 == 0:
+                print("  %d graphs surveyed (%.0f s)" % (k, time.time() - t0), flush=True)
+    sample = batch_sample(specs)
+    return {
+        "about": "Oracle survey of every graph of the seeded batched workload %d (%s), each graph alone; written "
+                 "by tests/golden/make_golden.py --batch, which calls only the oracle and the input generator."
+                 % (w.number, w.name),
+        "workload": w.number, "name": w.name, "n_graphs": len(specs), "outputs": ["count", "close_hist"],
+        "n_labels": w.n_labels, "scale_range": [ex["scale_lo"], ex["scale_hi"]],
+        "edge_factor_range": [ex["ef_lo"], ex["ef_hi"]],
+        "raw_edges": int(sum(s.n_edges for s in specs)), "edges": int(sum(edges)),
+        "triangles_total": int(sum(tri)), "triangles": tri,
+        "close_hist_total": [int(x) for x in total],
+        "close_hist_sample": {str(g): hist[g] for g in sample},
+        "oracle_seconds": round(time.time() - t0, 1), "host_processes": procs or os.cpu_count(),
+    }
+
+
+def served_pool_specs(w):
+    """The served pool graphs (R-MAT scales lo..hi, times uniform on
+    [0, 2^31), labels uniform on 0..L-1) as the benchmark builds them."""
+    ex = w.extra
+    return [synth.GraphSpec("rmat", sc, 16, synth.MASTER_SEED + 50 + k, ("uniform", 31), ("uniform", w.n_labels))
+            for k, sc in enumerate(range(ex["pool_scale_lo"], ex["pool_scale_hi"] + 1))]
+
+
+def served_requests(L, seed):
+    """Seeded requests of the served kinds on one graph: a full survey
+    (closure histogram, label table, spread count), a closed time window of
+    log-uniform width in [2^12, 2^31], and a label predicate (each multiset
+    bit set with probability 1/2)."""
+    rng = np.random.default_rng(seed)
+    n_tab = (L + 2) * (L + 1) * L // 6
+    width = int(2 ** (12 + 19 * rng.random()))
+    lo = int(rng.integers(0, 1 << 31))
+    mask = [int(i) for i in np.nonzero(rng.random(n_tab) < 0.5)[0]]
+    return [dict(outputs=["count", "close_hist", "label_table", "spread_count"],
+                 spread_lt=int(1 << int(rng.integers(16, 28)))),
+            dict(outputs=["count", "close_hist"], window=[lo, min(lo + width, (1 << 32) - 1)]),
+            dict(outputs=["count"], label_mask=mask)]
+
+
+def served(w, threads):
+    out = []
+    for k, spec in enumerate(served_pool_specs(w)):
+        d = synth.generate(spec)
+        u, v, t = oracle.clean(spec.n, d["src"], d["dst"], d["ts"])
+        reqs = []
+        for rq in served_requests(w.n_labels, synth.MASTER_SEED + 500 + k):
+            kw = dict(rq)
+            kw["outputs"] = tuple(kw["outputs"])
+            r = oracle.survey_clean(spec.n, u, v, t, d["vlab"], n_labels=w.n_labels, threads=threads, **kw)
+            res = {"triangles": int(r["triangles"])}
+            if "close_hist" in rq["outputs"]:
+                res["close_hist"] = [int(x) for x in r["close_hist"]]
+            if "label_table" in rq["outputs"]:
+                res["label_table"] = [int(x) for x in r["label_table"]]
+            if "spread_count" in rq["outputs"]:
+                res["spread_count"] = int(r["spread_count"])
+            reqs.append({"request": rq, "result": res})
+        print("  pool graph %d (scale %d): %d triangles" % (k, spec.scale, reqs[0]["result"]["triangles"]),
+              flush=True)
+        out.append({"scale": spec.scale, "edge_factor": spec.edge_factor, "seed": spec.seed, "ts": list(spec.ts),
+                    "labels": list(spec.labels), "m": int(len(u)), "requests": reqs})
+    return {
+        "about": "Oracle answers to seeded served requests on the pool graphs of workload %d (%s); written by "
+                 "tests/golden/make_golden.py --served, which calls only the oracle and the input generator."
+                 % (w.number, w.name),
+        "workload": w.number, "n_labels": w.n_labels, "graphs": out,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("workload", type=int)
     ap.add_argument("--scale", type=int, default=None)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--extended", action="store_true")
+    ap.add_argument("--batch", action="store_true")
+    ap.add_argument("--served", action="store_true")
     a = ap.parse_args()
     w = synth.workload(a.workload, scale=a.scale)
+    if a.batch or a.served:
+        out = batch(w, a.threads) if a.batch else served(w, a.threads)
+        path = os.path.join(HERE, "golden_batch_w4.json" if a.batch else "golden_served_pool.json")
+        with open(path, "w") as f:
+            json.dump(out, f, separators=(",", ":") if a.batch else (", ", ": "), indent=None if a.batch else 1)
+        print("wrote", path)
+        return
     if a.extended:
         out = extended(w, a.threads)
         path = golden_path(w.number, w.graph.scale, extended=True)

@@ -1,8 +1,13 @@
 // Host-only checks of the survey server's scheduling policy (sched.hpp).
 // Prints one line per check: "ok <name>" or "FAIL <name>: <detail>".
+#include <chrono>
+#include <condition_variable>
 #include <cstdio>
+#include <map>
+#include <mutex>
 #include <set>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "sched.hpp"
@@ -46,8 +51,95 @@ static std::vector<std::vector<uint32_t>> simulate(uint32_t slots, uint32_t n_se
     return seen;
 }
 
+// The server's threading discipline on the host alone: client threads
+// submit under one mutex and wait on a condition variable; one worker thread
+// admits (slot and budget), begins a step, runs the "device" part without
+// the lock, then ends the step and wakes the clients -- as the server does
+// around its device calls.  Built under ThreadSanitizer this checks that the
+// policy objects are only ever touched under the lock.
+static void threaded_serving()
+{
+    const uint32_t n_seg = 5, clients = 6, per_client = 40;
+    std::mutex mu;
+    std::condition_variable cv;
+    Engine eng(3, n_seg);
+    Queue queue(8);
+    Budget budget(3 * 100);
+    std::map<uint64_t, std::vector<uint32_t>> seen;  // ticket -> segments
+    std::set<uint64_t> done;
+    uint64_t next_ticket = 0, rejected = 0;
+    bool stop = false;
+    std::thread worker([&] {
+        std::vector<uint32_t> part, fin;
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            queue.admit([&](uint64_t t) {
+                if (!budget.take(100)) return false;
+                if (eng.admit(t) < 0) {
+                    budget.give(100);
+                    return false;
+                }
+                return true;
+            });
+            (void)eng.take_fresh();
+            if (!eng.begin_step(part, fin)) {
+                if (stop) break;
+                // nothing runs: sleep until a request arrives or the clients
+                // are done (an untimed wait: ThreadSanitizer of this toolchain
+                // does not see the timed wait's unlock)
+                cv.wait(lk, [&] { return stop || queue.size() > 0; });
+                continue;
+            }
+            const uint32_t seg = eng.cursor();
+            std::vector<uint64_t> tickets;
+            for (uint32_t s : part) tickets.push_back(eng.slot(s).ticket);
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(50));  // the device step
+            lk.lock();
+            for (uint64_t t : tickets) seen[t].push_back(seg);
+            std::vector<uint64_t> finished;
+            eng.end_step(finished);
+            for (uint64_t t : finished) {
+                done.insert(t);
+                budget.give(100);
+            }
+            if (!finished.empty()) cv.notify_all();
+        }
+    });
+    std::vector<std::thread> cl;
+    for (uint32_t c = 0; c < clients; ++c)
+        cl.emplace_back([&] {
+            for (uint32_t i = 0; i < per_client; ++i) {
+                std::unique_lock<std::mutex> lk(mu);
+                const uint64_t t = next_ticket++;
+                if (!queue.push(t)) {  // queue full: counted, not kept
+                    ++rejected;
+                    continue;
+                }
+                cv.notify_all();
+                cv.wait(lk, [&] { return done.count(t) != 0; });
+            }
+        });
+    for (auto &t : cl) t.join();
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        stop = true;
+    }
+    cv.notify_all();
+    worker.join();
+    bool ok = done.size() + rejected == (size_t)clients * per_client && budget.used() == 0;
+    for (uint64_t t : done) {
+        const auto &v = seen[t];
+        std::set<uint32_t> u(v.begin(), v.end());
+        ok = ok && v.size() == n_seg && u.size() == n_seg;
+    }
+    check(ok, "threaded clients and worker: every admitted request sees each segment once",
+          std::to_string(done.size()) + " done, " + std::to_string(rejected) + " rejected");
+}
+
 int main()
 {
+    threaded_serving();
     // every request sees every segment exactly once, whenever it arrives
     {
         std::vector<uint32_t> arrive = {0, 0, 3, 5, 5, 5, 9, 14, 14, 20};

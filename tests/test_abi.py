@@ -58,12 +58,13 @@ int main(void) {
          offsetof(tp_tune_result, trials), TP_BW_TABLE, TP_BATCH_SCRATCH_WORDS, TP_NUM_CLASSES);
   printf("%zu %zu %zu %zu %zu\\n", sizeof(tp_server_config), sizeof(tp_request_info), sizeof(tp_server_stats),
          offsetof(tp_server_stats, p50_ms), offsetof(tp_server_stats, elapsed_s));
+  printf("%zu %u %u\\n", offsetof(tp_survey_result, class_triangles), TP_RW_CLASS_TRI, TP_RW_SCRATCH_WORDS);
   return 0;
 }
 """)
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-std=c11", "-I", INCLUDE, str(src), "-o", str(exe)])
-    l1, l2, l3, l3b, l4, l5 = subprocess.check_output([str(exe)]).decode().split("\n")[:6]
+    l1, l2, l3, l3b, l4, l5, l6 = subprocess.check_output([str(exe)]).decode().split("\n")[:7]
     assert list(map(int, l1.split())) == [ctypes.sizeof(tp.tp_edge_list), ctypes.sizeof(tp.tp_graph_stats),
                                           ctypes.sizeof(tp.tp_survey_spec), ctypes.sizeof(tp.tp_survey_result)]
     assert list(map(int, l2.split())) == [tp.tp_graph_stats.phase_ms.offset, tp.tp_survey_spec.label_mask.offset,
@@ -80,6 +81,8 @@ int main(void) {
     assert list(map(int, l5.split())) == [ctypes.sizeof(tp.tp_server_config), ctypes.sizeof(tp.tp_request_info),
                                           ctypes.sizeof(tp.tp_server_stats), tp.tp_server_stats.p50_ms.offset,
                                           tp.tp_server_stats.elapsed_s.offset]
+    assert list(map(int, l6.split())) == [tp.tp_survey_result.class_triangles.offset, tp.TP_RW_CLASS_TRI,
+                                          tp.TP_RESULT_WORDS - tp.TP_RW_SCRATCH]
 
 
 def test_msidx_is_colex_rank():

@@ -64,6 +64,8 @@ def test_full_size_against_oracle(workload, scale):
         got = tp.survey(G, stream=stream, outputs=ALL_OUT, n_labels=gold["n_labels"], spread_lt=gold["spread_lt"])
         check_against_golden(got, gold)
         assert got["probes"] == st["probes"] == sum(st["class_probes"])
+        assert sum(got["class_triangles"]) == gold["triangles"]
+        assert all(t == 0 for t, k in zip(got["class_triangles"], st["class_tiles"]) if k == 0)
         # the count-only kernels find the same triangles
         c = tp.survey(G, stream=stream, outputs=("count",), n_labels=gold["n_labels"])
         assert c["triangles"] == gold["triangles"]

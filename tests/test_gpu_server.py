@@ -160,6 +160,71 @@ def test_served_huge_targets_against_oracle(torch_cuda):
             assert np.array_equal(r["label_table"], ref["label_table"])
 
 
+def test_served_config_graphs_against_oracle(torch_cuda):
+    """The served configuration's graph kinds in one server: the R-MAT
+    scale-22 graph of workload 2 (many segments per pass) and the pool of
+    R-MAT scales 16..20 (one segment each, on the second stream).  Requests
+    of every served kind arrive while the large graph's pass is on the
+    device; each result equals the oracle's stored answer
+    (tests/golden/make_golden.py 2 and --served)."""
+    import json
+    import os
+    torch = torch_cuda
+    gdir = os.path.join(os.path.dirname(__file__), "golden")
+    pool_path = os.path.join(gdir, "golden_served_pool.json")
+    big_path = os.path.join(gdir, "golden_w2_s22.json")
+    if not (os.path.exists(pool_path) and os.path.exists(big_path)):
+        pytest.skip("no stored oracle results for the served graphs")
+    pool_gold = json.load(open(pool_path))
+    big_gold = json.load(open(big_path))
+    assert pool_gold["n_labels"] == L == big_gold["n_labels"]
+    w2 = synth.workload(2)
+    with tp.Server(max_slots=8, n_labels=L, step_wedges=1 << 30) as srv:
+        say("resident: workload 2 at scale 22")
+        g = synth.generate(w2.graph)
+        big = srv.add_graph(w2.graph.n, *[torch.from_numpy(g[k]).cuda() for k in ("src", "dst", "ts", "vlab")])
+        del g
+        st = srv.graph_stats(big)
+        assert st["n_edges"] == big_gold["m"] and st["probes"] > 4 * (1 << 30)
+        pool = []
+        for pg in pool_gold["graphs"]:
+            spec = synth.GraphSpec("rmat", pg["scale"], pg["edge_factor"], pg["seed"], tuple(pg["ts"]),
+                                   tuple(pg["labels"]))
+            say("resident: pool graph of scale %d" % spec.scale)
+            g = synth.generate(spec)
+            gid = srv.add_graph(spec.n, *[torch.from_numpy(g[k]).cuda() for k in ("src", "dst", "ts", "vlab")])
+            assert srv.graph_stats(gid)["n_edges"] == pg["m"]
+            pool.append(gid)
+            del g
+        torch.cuda.synchronize()
+        big_spec = dict(outputs=("count", "close_hist", "label_table", "spread_count"),
+                        spread_lt=big_gold["spread_lt"])
+        jobs = [(srv.submit(big, tag=0, **big_spec), None)]
+        time.sleep(0.01)  # the pool requests join while the large pass runs
+        for gid, pg in zip(pool, pool_gold["graphs"]):
+            for rq in pg["requests"]:
+                kw = {k: (tuple(v) if k in ("outputs", "window") else v) for k, v in rq["request"].items()}
+                jobs.append((srv.submit(gid, tag=3, **kw), rq))
+        jobs.append((srv.submit(big, tag=0, **big_spec), None))
+        results = [srv.wait(t, timeout_us=120_000_000)[0] for t, _ in jobs]
+    for (t, rq), r in zip(jobs, results):
+        if rq is None:
+            assert r["triangles"] == big_gold["triangles"]
+            assert r["spread_count"] == big_gold["spread_count"]
+            assert np.array_equal(r["close_hist"], np.array(big_gold["close_hist"], np.uint64))
+            assert np.array_equal(r["label_table"], np.array(big_gold["label_table"], np.uint64))
+            continue
+        want = rq["result"]
+        say("pool request %s: %d triangles" % (sorted(rq["request"]), r["triangles"]))
+        assert r["triangles"] == want["triangles"]
+        if "close_hist" in want:
+            assert np.array_equal(r["close_hist"], np.array(want["close_hist"], np.uint64))
+        if "label_table" in want:
+            assert np.array_equal(r["label_table"], np.array(want["label_table"], np.uint64))
+        if "spread_count" in want:
+            assert r["spread_count"] == want["spread_count"]
+
+
 def test_concurrent_submitters(torch_cuda):
     """Several host threads submit and wait at once."""
     torch = torch_cuda
