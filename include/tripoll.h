@@ -309,6 +309,25 @@ tp_status tripoll_survey_async(const tp_graph *g, const tp_survey_spec *spec, ui
                                void *stream);
 
 /*
+ * As tripoll_survey, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the survey's device result words and work counters live in a
+ * static device array of TP_RESULT_WORDS uint64 (about 71 KB) that each GPU
+ * holds from the first call on it until the process ends, so the call makes
+ * no device allocation and releases nothing.  The result size does not
+ * depend on the graph or the spec, so every survey fits that array.
+ * Synchronous; kernel_ms, total_ms and class_ms are 0 (no timers).
+ *   The graph's device must be the current device.
+ *   All calls on one GPU share its array, which keeps the last call's
+ *   contents (each call clears it first): calls that overlap on one GPU,
+ *   from several threads or streams, race and must not be made.
+ * Errors: as tripoll_survey; TP_ERR_INVALID also when the current device is
+ * not the graph's.  On TP_ERR_DEVICE *out may have been partly written.
+ */
+tp_status tripoll_survey_noalloc(const tp_graph *g, const tp_survey_spec *spec, tp_survey_result *out,
+                                 void *stream);
+
+/*
  * Enumerate every triangle (the full-enumeration use of the callback,
  * Introduction).  Writes up to `capacity` records of 9 uint32 each into the
  * device buffer `dev_records`: original ids a, b, c (the triangle's pivot,

@@ -27,6 +27,7 @@
 // records cut to each piece's candidates by the planner; any class may be
 // switched to binary search of Adj+(q) in HBM.
 #include <algorithm>
+#include <cstddef>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -1542,6 +1543,69 @@ extern "C" tp_status tripoll_survey_async(const tp_graph *g, const tp_survey_spe
         if (!dev_out) fail(TP_ERR_INVALID, "tripoll_survey_async: NULL output");
         validate_spec(g, spec);
         survey_enqueue<false>(g, spec, reinterpret_cast<unsigned long long *>(dev_out), (hipStream_t)stream);
+    });
+}
+
+// ---------------------------------------------------------------- survey without allocation
+// The result words of tripoll_survey_noalloc live in one file-scope device
+// array (each GPU holds its own copy until the process ends) instead of a
+// buffer taken from the allocator.  Its name is a host-side stand-in in host
+// code: the device address of each GPU's copy comes from
+// hipGetSymbolAddress, called once per device with that device current, and
+// only that address is handed to kernels and copies.
+constexpr size_t kStaticResultWords = TP_RESULT_WORDS;
+static __device__ __align__(256) unsigned long long scratch[kStaticResultWords];
+
+namespace {
+
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_static_mu;
+unsigned long long *g_static_ptr[kMaxStaticDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current.
+unsigned long long *static_result_words(int device)
+{
+    if (device < 0 || device >= kMaxStaticDevices)
+        fail(TP_ERR_UNSUPPORTED, "tripoll_survey_noalloc: device index beyond " + std::to_string(kMaxStaticDevices));
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[device]) {
+        void *p = nullptr;
+        TP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) fail(TP_ERR_DEVICE, "tripoll_survey_noalloc: no device address for the result words");
+        g_static_ptr[device] = static_cast<unsigned long long *>(p);
+    }
+    return g_static_ptr[device];
+}
+
+}  // namespace
+
+extern "C" tp_status tripoll_survey_noalloc(const tp_graph *g, const tp_survey_spec *spec, tp_survey_result *out,
+                                            void *stream)
+{
+    static_assert(TP_RESULT_WORDS <= kStaticResultWords, "the static result words hold a whole result");
+    static_assert(offsetof(tp_survey_result, directed) == TP_RW_DIRECTED * 8,
+                  "the result struct starts with the device result words");
+    return guard([&] {
+        if (!out) fail(TP_ERR_INVALID, "tripoll_survey_noalloc: NULL result");
+        validate_spec(g, spec);
+        int dev = 0;
+        TP_HIP(hipGetDevice(&dev));
+        if (dev != g->device) fail(TP_ERR_INVALID, "tripoll_survey_noalloc: the graph's device must be current");
+        unsigned long long *words = static_result_words(dev);
+        hipStream_t s = (hipStream_t)stream;
+        // survey_enqueue clears the words with a fill kernel, then surveys
+        survey_enqueue<false>(g, spec, words, s);
+        unsigned long long snap[kNumClasses];
+        TP_HIP(hipMemcpyAsync(out, words, TP_RW_SCRATCH * 8, hipMemcpyDeviceToHost, s));
+        TP_HIP(hipMemcpyAsync(snap, words + TP_RW_CLASS_TRI, sizeof(snap), hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+        out->directed[7] = 0;
+        out->kernel_ms = 0.f;
+        out->total_ms = 0.f;
+        for (int c = 0; c < kNumClasses; ++c) {
+            out->class_ms[c] = 0.f;
+            out->class_triangles[c] = snap[c] - (c ? snap[c - 1] : 0ull);
+        }
     });
 }
 

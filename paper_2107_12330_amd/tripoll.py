@@ -139,6 +139,8 @@ SIGNATURES = {
     "tripoll_graph_export": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "tripoll_survey": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), ctypes.POINTER(tp_survey_result), _P]),
     "tripoll_survey_async": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, _P]),
+    "tripoll_survey_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), ctypes.POINTER(tp_survey_result),
+                                              _P]),
     "tripoll_enumerate": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64), _P]),
     "tripoll_participation": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, _P,
                                              ctypes.POINTER(ctypes.c_uint64), _P]),
@@ -225,6 +227,12 @@ def tripoll_graph_export(g, rowptr=None, col=None, etime=None, tlabel=None, rank
 def tripoll_survey(g: int, spec: tp_survey_spec, stream=None) -> tp_survey_result:
     res = tp_survey_result()
     _check(load().tripoll_survey(g, ctypes.byref(spec), ctypes.byref(res), stream))
+    return res
+
+
+def tripoll_survey_noalloc(g: int, spec: tp_survey_spec, stream=None) -> tp_survey_result:
+    res = tp_survey_result()
+    _check(load().tripoll_survey_noalloc(g, ctypes.byref(spec), ctypes.byref(res), stream))
     return res
 
 
