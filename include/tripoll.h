@@ -192,10 +192,10 @@ tp_status tripoll_graph_export(const tp_graph *g, uint64_t *rowptr, uint32_t *co
  *                triples of ceil(log2 d) of p, q, r; in the degree order
  *                d(p) <= d(q) <= d(r), so that triple is already sorted)
  * with bin(D) = 0 for D <= 1 and min(31, ceil(log2 D)) otherwise, computed
- * exactly in integers.  The triangle count is always produced.  MAX_EDGE,
- * DEGREE_TABLE and DIRECTED are produced by tripoll_survey and
- * tripoll_survey_async only (batches and served requests return
- * TP_ERR_UNSUPPORTED for them). */
+ * exactly in integers.  The triangle count is always produced.  Every
+ * output is produced by the single-graph surveys, by batch surveys (per
+ * graph) and by served requests; tripoll_survey on a batch handle (the
+ * union's totals) does not produce DEGREE_TABLE. */
 #define TP_OUT_COUNT 0x01u
 #define TP_OUT_CLOSE_HIST 0x02u
 #define TP_OUT_LABEL_TABLE 0x04u
@@ -293,7 +293,8 @@ typedef struct {
  * Errors: TP_ERR_INVALID for NULL arguments, n_labels outside 1..16, a graph
  * label >= n_labels when labels are used, t_lo > t_hi, max_edge_shift > 31,
  * reserved != 0, or DIRECTED on a graph built without TP_EDGES_DIRECTED;
- * TP_ERR_UNSUPPORTED for MAX_EDGE, DEGREE_TABLE or DIRECTED on a batch;
+ * TP_ERR_UNSUPPORTED for DEGREE_TABLE on a batch handle (use
+ * tripoll_survey_batch);
  * TP_ERR_DEVICE.
  */
 tp_status tripoll_survey(const tp_graph *g, const tp_survey_spec *spec, tp_survey_result *out,
@@ -403,6 +404,8 @@ tp_status tripoll_participation(const tp_graph *g, const tp_survey_spec *spec, u
  *                  no vertices must own no edges); the sum is < 2^32 - 1
  *   src, dst, edge_time, vertex_label, mem_space, tie_hash: as in
  *                  tp_edge_list, concatenated over the graphs
+ *   flags          0, or TP_EDGES_DIRECTED (every graph's edges are arcs
+ *                  src -> dst, kept for the DIRECTED census as in tp_edge_list)
  */
 typedef struct {
     uint32_t n_graphs;
@@ -414,7 +417,7 @@ typedef struct {
     const uint32_t *edge_time;
     const uint8_t *vertex_label;
     uint32_t tie_hash;
-    uint32_t reserved;
+    uint32_t flags;
 } tp_batch_edges;
 
 /*
@@ -435,7 +438,12 @@ tp_status tripoll_graph_count(const tp_graph *g, uint32_t *n_graphs);
  * Per-graph result block of a batch survey, in uint64 words:
  *   [TP_BW_TRIANGLES] [TP_BW_SPREAD] [TP_BW_PROBES] [TP_BW_HIST, +32)
  *   then C(n_labels+2, 3) label-table words if LABEL_TABLE is requested,
- *   then 32*32 open/close words if OPEN_CLOSE is requested.
+ *   then 32*32 open/close words if OPEN_CLOSE is requested,
+ *   then TP_MAX_EDGE_BINS max-edge words if MAX_EDGE is requested,
+ *   then TP_DEGREE_MAX degree-table words if DEGREE_TABLE is requested
+ *   (each graph's degrees are its own),
+ *   then 8 directed-census words if DIRECTED is requested (the batch must be
+ *   built with TP_EDGES_DIRECTED).
  * tripoll_batch_words(spec) returns the block length (0 for a NULL spec).
  */
 #define TP_BW_TRIANGLES 0u
@@ -549,8 +557,13 @@ tp_status tripoll_tune(tp_graph *g, const tp_survey_spec *spec, void *stream, tp
  * is admitted against the server's budget.  A worker thread owned by the
  * server drives the device; all functions are thread-safe.
  *
- * Served survey kinds: outputs COUNT, CLOSE_HIST, LABEL_TABLE, SPREAD_COUNT
- * (OPEN_CLOSE is TP_ERR_UNSUPPORTED); filters WINDOW and LABEL_MASK.
+ * Served survey kinds: every output and filter of tripoll_survey.  Requests
+ * for COUNT, CLOSE_HIST, LABEL_TABLE and SPREAD_COUNT share each step's
+ * pass; requests that also ask for OPEN_CLOSE, MAX_EDGE, DEGREE_TABLE or
+ * DIRECTED (whose counters do not fit the shared pass's LDS) take part in
+ * the same steps and segments but run the single-request kernels over each
+ * segment into result words of their own (their memory is
+ * TP_RESULT_WORDS * 8 bytes of the budget).
  */
 typedef struct tp_server tp_server;
 
@@ -620,8 +633,9 @@ tp_status tripoll_server_graph(tp_server *srv, uint32_t graph_id, const tp_graph
  * Queue a survey of graph `graph_id`.  Returns at once with a ticket.
  * `tag` (0..7) groups requests for the latency statistics.
  * Errors: TP_ERR_NOT_FOUND (graph), TP_ERR_INVALID (spec as tripoll_survey;
- * labels used with n_labels other than the server's), TP_ERR_UNSUPPORTED
- * (OPEN_CLOSE), TP_ERR_BUSY (queue full; the request is not kept).
+ * labels used with n_labels other than the server's; DIRECTED on a graph
+ * built without TP_EDGES_DIRECTED), TP_ERR_BUSY (queue full; the request is
+ * not kept).
  */
 tp_status tripoll_server_submit(tp_server *srv, uint32_t graph_id, const tp_survey_spec *spec, uint32_t tag,
                                 uint64_t *ticket);

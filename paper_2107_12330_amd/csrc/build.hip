@@ -308,20 +308,26 @@ __device__ __forceinline__ uint32_t degree_bin(uint32_t d)
 // Ranks are in degree order, so the degree bins are ranges of ranks:
 // first[k] = the first rank whose bin is >= k (first[] is pre-filled with
 // 2^32 - 1 for bins above the largest).  Rank i writes the bins it opens.
-__global__ void k_dbin_rank(const uint32_t *deg, const uint32_t *perm, uint32_t n, uint32_t *first)
+// In a batch (rank_gid set) each graph's ranks are a range of their own in
+// degree order, so each graph g gets its own 32 bounds at first[32 g + k],
+// and a graph's first rank opens every bin up to its own.
+__global__ void k_dbin_rank(const uint32_t *deg, const uint32_t *perm, uint32_t n, const uint32_t *rank_gid,
+                            uint32_t *first)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const uint32_t b = degree_bin(deg[perm[i]]);
-        const int prev = i ? (int)degree_bin(deg[perm[i - 1]]) : -1;
-        for (int k = prev + 1; k <= (int)b; ++k) first[k] = (uint32_t)i;
+        const uint32_t g = rank_gid ? rank_gid[i] : 0u;
+        const bool opens = i == 0 || (rank_gid && rank_gid[i - 1] != g);
+        const int prev = opens ? -1 : (int)degree_bin(deg[perm[i - 1]]);
+        for (int k = prev + 1; k <= (int)b; ++k) first[(size_t)g * 32 + k] = (uint32_t)i;
     }
 }
 
 // The same boundaries as CSR slots: rows are laid out by rank.
-__global__ void k_dbin_slot(const uint32_t *first, const uint64_t *rowptr, uint64_t *slot)
+__global__ void k_dbin_slot(const uint32_t *first, const uint64_t *rowptr, size_t count, uint64_t *slot)
 {
-    const uint32_t k = threadIdx.x;
-    if (k < 32) slot[k] = first[k] == 0xffffffffu ? ~0ull : rowptr[first[k]];
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x)
+        slot[k] = first[k] == 0xffffffffu ? ~0ull : rowptr[first[k]];
 }
 
 __global__ void fill_u32(uint32_t *p, size_t n, uint32_t v)
@@ -1035,22 +1041,24 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
         g->rlab.reset(n, s);
         k_rank_scatter<<<grid_for(n, kB), kB, 0, s>>>(g->perm.get(), n, vlab, rank.get(), g->rlab.get());
         TP_CHECK_LAUNCH();
-        if (!hb) {
-            // bins 0 .. bin(d_max) are in use
-            uint32_t top = 0;
-            for (uint64_t d = mx[0]; d > 1 && top < 31; ++top) d = (d + 1) / 2;
-            g->dbin_values = top + 1;
-            g->dbin_rank.reset(32, s);
-            fill_u32<<<1, 64, 0, s>>>(g->dbin_rank.get(), 32, 0xffffffffu);
-            TP_CHECK_LAUNCH();
-            k_dbin_rank<<<grid_for(n, kB), kB, 0, s>>>(deg.get(), g->perm.get(), n, g->dbin_rank.get());
-            TP_CHECK_LAUNCH();
-        }
         if (hb) {
             g->n_graphs = hb->n_graphs;
             g->rank_gid.reset(n, s);
             k_rank_graph<<<grid_for(n, kB), kB, 0, s>>>(g->perm.get(), n, d_voff.get(), hb->n_graphs,
                                                        g->rank_gid.get());
+            TP_CHECK_LAUNCH();
+        }
+        {
+            // bins 0 .. bin(d_max) are in use; 32 bounds per graph
+            uint32_t top = 0;
+            for (uint64_t d = mx[0]; d > 1 && top < 31; ++top) d = (d + 1) / 2;
+            g->dbin_values = top + 1;
+            const size_t nbins = (size_t)32 * (hb ? hb->n_graphs : 1u);
+            g->dbin_rank.reset(nbins, s);
+            fill_u32<<<grid_for(nbins, kB), kB, 0, s>>>(g->dbin_rank.get(), nbins, 0xffffffffu);
+            TP_CHECK_LAUNCH();
+            k_dbin_rank<<<grid_for(n, kB), kB, 0, s>>>(deg.get(), g->perm.get(), n, hb ? g->rank_gid.get() : nullptr,
+                                                       g->dbin_rank.get());
             TP_CHECK_LAUNCH();
         }
     }
@@ -1102,8 +1110,9 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
     k_row_stats<<<grid_for(n, kB), kB, 0, s>>>(g->rowptr.get(), n, c_wedge, c_dpmax);
     TP_CHECK_LAUNCH();
     if (g->dbin_rank.get()) {
-        g->dbin_slot.reset(32, s);
-        k_dbin_slot<<<1, 64, 0, s>>>(g->dbin_rank.get(), g->rowptr.get(), g->dbin_slot.get());
+        const size_t nbins = g->dbin_rank.n;
+        g->dbin_slot.reset(nbins, s);
+        k_dbin_slot<<<grid_for(nbins, 64), 64, 0, s>>>(g->dbin_rank.get(), g->rowptr.get(), nbins, g->dbin_slot.get());
         TP_CHECK_LAUNCH();
     }
     TP_HIP(hipEventRecord(ev[6], s));
@@ -1208,6 +1217,8 @@ extern "C" tp_status tripoll_build_batch(const tp_batch_edges *be, void *stream,
         el.edge_time = be->edge_time;
         el.vertex_label = be->vertex_label;
         el.tie_hash = be->tie_hash;
+        if (be->flags & ~TP_EDGES_DIRECTED) fail(TP_ERR_INVALID, "tripoll_build_batch: unknown flags");
+        el.flags = be->flags;
         build_impl(&el, (hipStream_t)stream, out, &hb);
     });
 }

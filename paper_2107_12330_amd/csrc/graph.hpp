@@ -59,8 +59,8 @@ struct tp_graph {
     // degree bins (bin(d) = ceil(log2 d), 0 for d <= 1): ranks are in degree
     // order, so each bin is a range of ranks and of CSR slots (single graphs)
     uint32_t dbin_values = 0;          // bin(d_max) + 1
-    tp::DArray<uint32_t> dbin_rank;    // [32] first rank of bin >= k, or 2^32 - 1
-    tp::DArray<uint64_t> dbin_slot;    // [32] first CSR slot of a rank of bin >= k, or 2^64 - 1
+    tp::DArray<uint32_t> dbin_rank;    // [32 per graph] first rank of bin >= k, or 2^32 - 1
+    tp::DArray<uint64_t> dbin_slot;    // [32 per graph] first CSR slot of a rank of bin >= k, or 2^64 - 1
     uint32_t n_graphs = 0;         // > 0 for a batch of disjoint graphs
     tp::DArray<uint32_t> rank_gid; // [n] graph of each rank (batches only)
     uint64_t n_tiles[kNumClasses] = {};

@@ -39,6 +39,15 @@ void multi_segment_enqueue(const tp_graph *g, const SlotSpec *dev_slots, uint32_
                            bool labels, unsigned long long *dev_out, unsigned long long *dev_counter, uint32_t seg,
                            uint32_t n_seg, uint32_t grid_eighths, hipStream_t s);
 
+// Enqueue segment `seg` of `n_seg` of a single-request pass: the survey of
+// `sp` (any outputs and filters tripoll_survey takes, with the kernels it
+// uses) over the same tiles as multi_segment_enqueue's segment, accumulated
+// into a result block of TP_RESULT_WORDS words at `dev_out` (cleared by the
+// caller before the first segment; its scratch words hold the tile counter).
+// For served requests whose counters do not fit the shared pass.
+void solo_segment_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned long long *dev_out, uint32_t seg,
+                          uint32_t n_seg, uint32_t grid_eighths, hipStream_t s);
+
 // Zero `n` device words with a fill kernel (safe inside recorded graphs).
 void zero_words(unsigned long long *p, size_t n, hipStream_t s);
 

@@ -81,7 +81,16 @@ struct Request {
     double t_arrive = 0, t_admit = 0, t_done = 0;
     tp_survey_result res{};
     std::string error;
+    // Requests whose counters do not fit the shared pass (OPEN_CLOSE,
+    // MAX_EDGE, DEGREE_TABLE, DIRECTED) keep their slot for the segment
+    // bookkeeping but run the single-request kernels over each segment, into
+    // result words of their own.
+    bool solo = false;
+    DArray<unsigned long long> dres;                       // TP_RESULT_WORDS on the device
+    std::unique_ptr<HostArray<unsigned long long>> hres;  // the counters, copied back at completion
 };
+
+constexpr uint32_t kSoloOutputs = TP_OUT_OPEN_CLOSE | TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE | TP_OUT_DIRECTED;
 
 }  // namespace
 
@@ -125,14 +134,29 @@ struct tp_server {
         r.state = 2;
         r.t_done = now_us();
         std::memset(&r.res, 0, sizeof(r.res));
-        r.res.triangles = blk[TP_BW_TRIANGLES];
-        r.res.spread_count = blk[TP_BW_SPREAD];
-        r.res.probes = G.g->stats.probes;
-        for (int i = 0; i < 32; ++i) r.res.close_hist[i] = blk[TP_BW_HIST + i];
-        if (r.spec.outputs & TP_OUT_LABEL_TABLE) {
-            const uint32_t ts = words - TP_BW_TABLE;
-            for (uint32_t i = 0; i < ts && i < TP_TABLE_MAX; ++i) r.res.label_table[i] = blk[TP_BW_TABLE + i];
+        if (r.solo) {
+            // the result words of tripoll_survey's layout
+            const unsigned long long *h = r.hres->p;
+            r.res.triangles = h[TP_RW_TRIANGLES];
+            r.res.spread_count = h[TP_RW_SPREAD];
+            for (int i = 0; i < 32; ++i) r.res.close_hist[i] = h[TP_RW_HIST + i];
+            for (uint32_t i = 0; i < TP_TABLE_MAX; ++i) r.res.label_table[i] = h[TP_RW_TABLE + i];
+            for (int i = 0; i < 1024; ++i) r.res.open_close[i] = h[TP_RW_OPEN_CLOSE + i];
+            for (uint32_t i = 0; i < TP_MAX_EDGE_BINS; ++i) r.res.max_edge[i] = h[TP_RW_MAX_EDGE + i];
+            for (uint32_t i = 0; i < TP_DEGREE_MAX; ++i) r.res.degree_table[i] = h[TP_RW_DEGREE + i];
+            for (int i = 0; i < 7; ++i) r.res.directed[i] = h[TP_RW_DIRECTED + i];
+            r.dres.release();
+            r.hres.reset();
+        } else {
+            r.res.triangles = blk[TP_BW_TRIANGLES];
+            r.res.spread_count = blk[TP_BW_SPREAD];
+            for (int i = 0; i < 32; ++i) r.res.close_hist[i] = blk[TP_BW_HIST + i];
+            if (r.spec.outputs & TP_OUT_LABEL_TABLE) {
+                const uint32_t ts = words - TP_BW_TABLE;
+                for (uint32_t i = 0; i < ts && i < TP_TABLE_MAX; ++i) r.res.label_table[i] = blk[TP_BW_TABLE + i];
+            }
         }
+        r.res.probes = G.g->stats.probes;
         r.res.total_ms = (float)((r.t_done - r.t_admit) * 1e-3);
         budget.give(r.mem);
         ++completed;
@@ -169,6 +193,14 @@ struct tp_server {
             r.state = 1;
             r.t_admit = now_us();
             G.spec[s] = r.slot;
+            if (r.solo) {
+                // the shared pass skips the slot; the request's own words
+                // are cleared on the graph's stream before its first step
+                G.spec[s].off = 1;
+                r.dres.reset(TP_RESULT_WORDS, G.stream);
+                zero_words(r.dres.get(), TP_RESULT_WORDS, G.stream);
+                r.hres = std::make_unique<HostArray<unsigned long long>>(TP_RW_SCRATCH);
+            }
             return true;
         });
         return n > 0;
@@ -225,12 +257,27 @@ struct tp_server {
                                   G.stream));
             for (uint32_t i : fresh) zero_words(G.dout.get() + (size_t)i * words, words, G.stream);
             const bool labels = true;
-            multi_segment_enqueue(G.g, G.dslots.get(), hw, cfg.n_labels, labels, G.dout.get(),
-                                  G.dout.get() + (size_t)cfg.max_slots * words, G.eng.cursor(), G.eng.n_seg(),
-                                  G.small ? 8u : eighths, G.stream);
-            for (uint32_t i : G.finishing)
-                TP_HIP(hipMemcpyAsync(G.hres->p + (size_t)i * words, G.dout.get() + (size_t)i * words, words * 8,
-                                      hipMemcpyDeviceToHost, G.stream));
+            bool shared = false;
+            for (uint32_t i : G.part) shared = shared || !reqs.at(G.eng.slot(i).ticket).solo;
+            if (shared)
+                multi_segment_enqueue(G.g, G.dslots.get(), hw, cfg.n_labels, labels, G.dout.get(),
+                                      G.dout.get() + (size_t)cfg.max_slots * words, G.eng.cursor(), G.eng.n_seg(),
+                                      G.small ? 8u : eighths, G.stream);
+            for (uint32_t i : G.part) {
+                Request &r = reqs.at(G.eng.slot(i).ticket);
+                if (r.solo)
+                    solo_segment_enqueue(G.g, &r.spec, r.dres.get(), G.eng.cursor(), G.eng.n_seg(),
+                                         G.small ? 8u : eighths, G.stream);
+            }
+            for (uint32_t i : G.finishing) {
+                Request &r = reqs.at(G.eng.slot(i).ticket);
+                if (r.solo)
+                    TP_HIP(hipMemcpyAsync(r.hres->p, r.dres.get(), TP_RW_SCRATCH * 8, hipMemcpyDeviceToHost,
+                                          G.stream));
+                else
+                    TP_HIP(hipMemcpyAsync(G.hres->p + (size_t)i * words, G.dout.get() + (size_t)i * words,
+                                          words * 8, hipMemcpyDeviceToHost, G.stream));
+            }
             TP_HIP(hipEventRecord(G.ev, G.stream));
             ++steps;
             issued = true;
@@ -274,9 +321,11 @@ void check_served_spec(tp_server *srv, const tp_graph *g, const tp_survey_spec *
     const uint32_t known = TP_OUT_COUNT | TP_OUT_CLOSE_HIST | TP_OUT_LABEL_TABLE | TP_OUT_SPREAD_COUNT |
                            TP_OUT_OPEN_CLOSE | TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE | TP_OUT_DIRECTED;
     if (sp->outputs & ~known) fail(TP_ERR_INVALID, "tripoll_server_submit: unknown output bits");
-    if (sp->outputs & (TP_OUT_OPEN_CLOSE | TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE | TP_OUT_DIRECTED))
-        fail(TP_ERR_UNSUPPORTED,
-             "tripoll_server_submit: the open/close, max-edge, degree and directed tables are not served");
+    if ((sp->outputs & TP_OUT_MAX_EDGE) && sp->max_edge_shift > 31)
+        fail(TP_ERR_INVALID, "tripoll_server_submit: max_edge_shift must be in 0..31");
+    if ((sp->outputs & TP_OUT_DIRECTED) && !g->directed)
+        fail(TP_ERR_INVALID, "tripoll_server_submit: the directed census needs a graph built with TP_EDGES_DIRECTED");
+    if (sp->reserved != 0) fail(TP_ERR_INVALID, "tripoll_server_submit: reserved field must be 0");
     if (sp->filters & ~(TP_FILT_WINDOW | TP_FILT_LABEL_MASK))
         fail(TP_ERR_INVALID, "tripoll_server_submit: unknown filter bits");
     if (sp->strategy > TP_STRAT_TABLE_STRESS) fail(TP_ERR_INVALID, "tripoll_server_submit: unknown strategy");
@@ -443,7 +492,8 @@ extern "C" tp_status tripoll_server_submit(tp_server *srv, uint32_t graph_id, co
         r.tag = tag;
         r.spec = *spec;
         r.slot = make_slot(*spec);
-        r.mem = (uint64_t)srv->words * 8 + sizeof(SlotSpec);
+        r.solo = (spec->outputs & kSoloOutputs) != 0;
+        r.mem = r.solo ? (uint64_t)TP_RESULT_WORDS * 8 : (uint64_t)srv->words * 8 + sizeof(SlotSpec);
         r.t_arrive = now_us();
         if (!srv->queue.push(r.ticket)) {
             ++srv->rejected;

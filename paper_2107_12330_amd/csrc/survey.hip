@@ -112,8 +112,8 @@ struct SurveyParams {
     const uint8_t *edir;      // directions of the oriented edges (directed builds)
     uint8_t dir_type[64];     // triangle type by dir(p,q) << 4 | dir(p,r) << 2 | dir(q,r); 7 for none
     unsigned long long *part_edge;  // participation: one counter per CSR slot
-    const uint32_t *dbin_rank;  // [32] first rank of degree bin >= k (DEGREE_TABLE)
-    const uint64_t *dbin_slot;  // [32] first CSR slot of a rank of degree bin >= k
+    const uint32_t *dbin_rank;  // [32 per graph] first rank of degree bin >= k (DEGREE_TABLE)
+    const uint64_t *dbin_slot;  // [32 per graph] first CSR slot of a rank of degree bin >= k
     uint32_t t_lo32, t_hi32;  // window, clamped to the uint32 time range
     uint32_t spread_le;       // spread counter: close <= spread_le ...
     uint32_t spread_any;      // ... and spread_lt > 0
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     unsigned long long *cnt = cnt_all + (size_t)grp * nc;
     uint16_t *lut = reinterpret_cast<uint16_t *>(lds + L.off_lut);
     __shared__ uint64_t mask_lds[13];
-    __shared__ uint32_t dbin_lds[32];
+    __shared__ uint32_t dbin_lds[kGroups * 32];  // per group: the degree-bin bounds of its graph
     __shared__ uint8_t dtype_lds[EXT ? 64 : 1];
     __shared__ SlotSpec slot_lds[MULTI ? kMaxSlots : 1];
     __shared__ unsigned long long s_tile;
@@ -478,7 +478,8 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     uint4 *ring = reinterpret_cast<uint4 *>(lds + L.off_ring) + (size_t)w * kRing;
     for (uint32_t i = tid; i < nc * kGroups; i += BLOCK) cnt_all[i] = 0;
     if (tid < 13) mask_lds[tid] = P.label_mask[tid];
-    if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE) && tid < 32) dbin_lds[tid] = P.dbin_rank[tid];
+    if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE))
+        for (int i = tid; i < kGroups * 32; i += BLOCK) dbin_lds[i] = P.dbin_rank[i & 31];
     if (EXT && tid < 64) dtype_lds[tid] = P.dir_type[tid];
     if (MULTI) {
         const uint32_t *src = reinterpret_cast<const uint32_t *>(P.slots);
@@ -544,7 +545,9 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     uint32_t pk0 = 0, pn = 0;  // the table holds Adj+(q) slots [kq + pk0, kq + pk0 + pn)
     uint32_t n_stash = 0;  // keys in the stash
     bool gmode = LOG_SLOTS == 0;  // search Adj+(q) in HBM (huge targets, or a failed table)
+    uint32_t *dbin_g = dbin_lds + grp * 32;
     // degree bin cursor of the pivots this wave walks: bin pb spans CSR slots [pb_lo, pb_hi)
+    // (bounds of the graph whose tiles the group walks: 32 per graph of a batch)
     uint32_t pb = 0;
     uint64_t pb_lo = 0, pb_hi = ~0ull;
     if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE)) pb_hi = sload(P.dbin_slot + 1);
@@ -577,7 +580,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                 // table keeps that of every key
                 h.b_p = e.w & 0xffu;
                 h.b_q = bin_q;
-                h.b_r = !G ? hbin[where] : degree_bin_of(dbin_lds, P.col[kq + where]);
+                h.b_r = !G ? hbin[where] : degree_bin_of(dbin_g, P.col[kq + where]);
             }
             if (kdir) {
                 // ... and the directions of (p, q) and (p, r) above it
@@ -697,6 +700,14 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                     if (g != cur_g) {
                         flush(cur_g);
                         cur_g = g;
+                        if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE)) {
+                            // the new graph's degree-bin bounds (published by
+                            // the barrier below) and a fresh pivot cursor
+                            for (uint32_t i = gtid; i < 32; i += kGroup) dbin_g[i] = P.dbin_rank[(size_t)g * 32 + i];
+                            pb = 0;
+                            pb_lo = 0;
+                            pb_hi = sload(P.dbin_slot + (size_t)g * 32 + 1);
+                        }
                     }
                 }
                 gsync();
@@ -711,7 +722,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                 l_q = META ? __builtin_amdgcn_readfirstlane(P.rlab[cur_q]) : 0u;
                 if (ENUM) id_q = sload(P.perm + cur_q);
                 if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE))
-                    bin_q = __builtin_amdgcn_readfirstlane(degree_bin_of(dbin_lds, cur_q));
+                    bin_q = __builtin_amdgcn_readfirstlane(degree_bin_of(dbin_g, cur_q));
                 pk0 = PIECES ? min(cur_piece, piece_count(dq)) * piece_size(dq) : 0u;
                 pn = PIECES ? (pk0 < dq ? min(dq - pk0, piece_size(dq)) : 0u) : dq;
                 log_s = 5;
@@ -768,7 +779,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                                 hcnt[h] = 0;
                             }
                             if (kdir) hdir[h] = P.edir[kq + pk0 + i];
-                            if (kbins) hbin[h] = (uint8_t)degree_bin_of(dbin_lds, r);
+                            if (kbins) hbin[h] = (uint8_t)degree_bin_of(dbin_g, r);
                             if (ENUM) hpos[h] = P.perm[r];
                         }
                     }
@@ -833,15 +844,16 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                         // a wave meets its records in increasing slot order
                         // within a tile, so the bin cursor mostly moves forward
                         const uint64_t s0 = r.k;
+                        const uint64_t *dslot = P.dbin_slot + (size_t)cur_g * 32;
                         if (s0 < pb_lo) {
                             pb = 0;
                             pb_lo = 0;
-                            pb_hi = sload(P.dbin_slot + 1);
+                            pb_hi = sload(dslot + 1);
                         }
                         while (s0 >= pb_hi) {
                             ++pb;
                             pb_lo = pb_hi;
-                            pb_hi = pb < 31 ? sload(P.dbin_slot + pb + 1) : ~0ull;
+                            pb_hi = pb < 31 ? sload(dslot + pb + 1) : ~0ull;
                         }
                         r.p = pb;
                     }
@@ -1305,7 +1317,8 @@ void launch_all(const tp_graph *g, SurveyParams P, uint32_t strategy, hipStream_
     }
 }
 
-void validate_spec(const tp_graph *g, const tp_survey_spec *sp)
+// per_graph: a batch survey (results per graph of a batch)
+void validate_spec(const tp_graph *g, const tp_survey_spec *sp, bool per_graph = false)
 {
     if (!g || !sp) fail(TP_ERR_INVALID, "tripoll_survey: NULL argument");
     const uint32_t known = TP_OUT_COUNT | TP_OUT_CLOSE_HIST | TP_OUT_LABEL_TABLE | TP_OUT_SPREAD_COUNT |
@@ -1314,8 +1327,9 @@ void validate_spec(const tp_graph *g, const tp_survey_spec *sp)
     if (sp->reserved != 0) fail(TP_ERR_INVALID, "tripoll_survey: reserved field must be 0");
     if ((sp->outputs & TP_OUT_MAX_EDGE) && sp->max_edge_shift > 31)
         fail(TP_ERR_INVALID, "tripoll_survey: max_edge_shift must be in 0..31");
-    if ((sp->outputs & (TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE | TP_OUT_DIRECTED)) && g->n_graphs)
-        fail(TP_ERR_UNSUPPORTED, "tripoll_survey: max-edge, degree and directed tables are not produced for batches");
+    if ((sp->outputs & TP_OUT_DEGREE_TABLE) && g->n_graphs && !per_graph)
+        fail(TP_ERR_UNSUPPORTED, "tripoll_survey: the degree table of a batch is produced per graph, by "
+                                 "tripoll_survey_batch");
     if ((sp->outputs & TP_OUT_DIRECTED) && !g->directed)
         fail(TP_ERR_INVALID, "tripoll_survey: the directed census needs a graph built with TP_EDGES_DIRECTED");
     if (sp->filters & ~(TP_FILT_WINDOW | TP_FILT_LABEL_MASK)) fail(TP_ERR_INVALID, "tripoll_survey: unknown filter bits");
@@ -1392,10 +1406,10 @@ SurveyParams make_params(const tp_graph *g, const tp_survey_spec *sp, unsigned l
     P.max_edge_shift = sp->max_edge_shift;
     P.copies = 1;  // raised per launch where LDS allows
     // the degree table needs only the bins up to bin(d_max)
-    P.deg_words = ((sp->outputs & TP_OUT_DEGREE_TABLE) && !g->n_graphs) ? table_size(g->dbin_values) : 0;
+    P.deg_words = (sp->outputs & TP_OUT_DEGREE_TABLE) ? table_size(g->dbin_values) : 0;
     P.dbin_rank = g->dbin_rank.get();
     P.dbin_slot = g->dbin_slot.get();
-    P.dir_words = ((sp->outputs & TP_OUT_DIRECTED) && g->directed && !g->n_graphs) ? 8u : 0u;
+    P.dir_words = ((sp->outputs & TP_OUT_DIRECTED) && g->directed) ? 8u : 0u;
     P.o_dir = TP_RW_DIRECTED;
     P.edir = g->edir.get();
     for (uint32_t i = 0; i < 64; ++i) P.dir_type[i] = directed_type(i >> 4, (i >> 2) & 3u, i & 3u);
@@ -1461,6 +1475,9 @@ uint32_t batch_words(const tp_survey_spec *sp)
     uint32_t w = TP_BW_TABLE;
     if (sp->outputs & TP_OUT_LABEL_TABLE) w += table_size(sp->n_labels);
     if (sp->outputs & TP_OUT_OPEN_CLOSE) w += 1024;
+    if (sp->outputs & TP_OUT_MAX_EDGE) w += TP_MAX_EDGE_BINS;
+    if (sp->outputs & TP_OUT_DEGREE_TABLE) w += TP_DEGREE_MAX;
+    if (sp->outputs & TP_OUT_DIRECTED) w += 8;
     return w;
 }
 
@@ -1470,8 +1487,6 @@ uint32_t graph_count(const tp_graph *g) { return g->n_graphs ? g->n_graphs : 1u;
 // `dev_out`, followed by the tile counter.  Allocates nothing.
 void survey_batch_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned long long *dev_out, hipStream_t s)
 {
-    if (sp->outputs & (TP_OUT_MAX_EDGE | TP_OUT_DEGREE_TABLE | TP_OUT_DIRECTED))
-        fail(TP_ERR_UNSUPPORTED, "tripoll_survey_batch: max-edge, degree and directed tables have no place in a batch block");
     const uint32_t words = batch_words(sp);
     const uint64_t total = (uint64_t)graph_count(g) * words + TP_BATCH_SCRATCH_WORDS;
     zero_u64<<<grid_for(total, 256), 256, 0, s>>>(dev_out, total);
@@ -1485,8 +1500,13 @@ void survey_batch_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned 
     P.o_hist = TP_BW_HIST;
     P.o_table = TP_BW_TABLE;
     P.o_oc = TP_BW_TABLE + P.table_words;
+    P.o_maxe = P.o_oc + P.oc_words;
+    P.o_deg = P.o_maxe + P.maxe_words;
+    P.o_dir = P.o_deg + ((sp->outputs & TP_OUT_DEGREE_TABLE) ? TP_DEGREE_MAX : 0u);
     if (g->m == 0 || g->n_in == 0) return;
-    if (needs_meta(sp))
+    if (needs_ext(sp))
+        launch_all<true, false, kFormExt>(g, P, sp->strategy, s);
+    else if (needs_meta(sp))
         launch_all<true, false>(g, P, sp->strategy, s);
     else
         launch_all<false, false>(g, P, sp->strategy, s);
@@ -1823,7 +1843,7 @@ extern "C" tp_status tripoll_survey_batch(const tp_graph *g, const tp_survey_spe
 {
     return guard([&] {
         if (!dev_out) fail(TP_ERR_INVALID, "tripoll_survey_batch: NULL output");
-        validate_spec(g, spec);
+        validate_spec(g, spec, true);
         survey_batch_enqueue(g, spec, reinterpret_cast<unsigned long long *>(dev_out), (hipStream_t)stream);
     });
 }
@@ -1845,7 +1865,7 @@ extern "C" tp_status tripoll_survey_capture(const tp_graph *g, const tp_survey_s
 {
     return guard([&] {
         if (!dev_out || !out) fail(TP_ERR_INVALID, "tripoll_survey_capture: NULL argument");
-        validate_spec(g, spec);
+        validate_spec(g, spec, true);
         // the kernels' attributes are set outside the capture: one eager
         // survey on a private stream prepares every launch.  It writes a
         // temporary buffer of the same size, never dev_out, which work on
@@ -1945,6 +1965,27 @@ void tp::multi_segment_enqueue(const tp_graph *g, const SlotSpec *dev_slots, uin
         P.tiles = g->tiles[c].get() + a;
         P.n_tiles = b - a;
         launch_variant<true, false, true>(c, resolve_variant(g, c, TP_STRAT_AUTO), P, s, g->device);
+    }
+}
+
+void tp::solo_segment_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned long long *dev_out, uint32_t seg,
+                              uint32_t n_seg, uint32_t grid_eighths, hipStream_t s)
+{
+    if (n_seg == 0 || seg >= n_seg) fail(TP_ERR_INVALID, "single-request segment: bad segment");
+    validate_spec(g, sp);
+    if (g->m == 0 || g->n_in == 0) return;
+    SurveyParams P = make_params(g, sp, dev_out, dev_out + TP_RW_SCRATCH);
+    P.grid_eighths = grid_eighths;
+    for (int c = 0; c < kNumClasses; ++c) {
+        const uint64_t nt = g->n_tiles[c];
+        const uint64_t a = nt * seg / n_seg, b = nt * (seg + 1) / n_seg;
+        if (a == b) continue;
+        P.tiles = g->tiles[c].get() + a;
+        P.n_tiles = b - a;
+        const uint32_t v = resolve_variant(g, c, sp->strategy);
+        if (needs_ext(sp)) launch_variant<true, false, false, kFormExt>(c, v, P, s, g->device);
+        else if (needs_meta(sp)) launch_variant<true, false>(c, v, P, s, g->device);
+        else launch_variant<false, false>(c, v, P, s, g->device);
     }
 }
 

@@ -60,7 +60,7 @@ class tp_batch_edges(ctypes.Structure):
     _fields_ = [("n_graphs", ctypes.c_uint32), ("mem_space", ctypes.c_uint32), ("edge_offsets", ctypes.c_void_p),
                 ("vertex_counts", ctypes.c_void_p), ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
                 ("edge_time", ctypes.c_void_p), ("vertex_label", ctypes.c_void_p), ("tie_hash", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32)]
 
 
 class tp_graph_stats(ctypes.Structure):
@@ -535,9 +535,10 @@ def export(graph: Graph) -> dict:
 # ------------------------------------------------------------------ batches
 
 def batch_edges(edge_offsets, vertex_counts, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX,
-                device=None) -> tuple:
+                device=None, directed=False) -> tuple:
     """Pack a batch into a tp_batch_edges.  Returns (struct, keep-alive host
-    arrays); the offsets and counts are always host arrays."""
+    arrays); the offsets and counts are always host arrays.  directed=True
+    keeps every edge's direction src -> dst for the directed census."""
     if device is None:
         device = not isinstance(src, np.ndarray)
     eoff = np.ascontiguousarray(edge_offsets, np.uint64)
@@ -548,11 +549,13 @@ def batch_edges(edge_offsets, vertex_counts, src, dst, ts=None, vlab=None, tie=T
     be.edge_offsets, be.vertex_counts = eoff.ctypes.data, vcnt.ctypes.data
     be.src, be.dst, be.edge_time, be.vertex_label = _addr(src), _addr(dst), _addr(ts), _addr(vlab)
     be.tie_hash = tie
+    be.flags = TP_EDGES_DIRECTED if directed else 0
     return be, (eoff, vcnt)
 
 
-def build_batch(edge_offsets, vertex_counts, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX, stream=None) -> Graph:
-    be, keep = batch_edges(edge_offsets, vertex_counts, src, dst, ts, vlab, tie)
+def build_batch(edge_offsets, vertex_counts, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX, stream=None,
+                directed=False) -> Graph:
+    be, keep = batch_edges(edge_offsets, vertex_counts, src, dst, ts, vlab, tie, directed=directed)
     h = tripoll_build_batch(be, stream)
     del keep
     return Graph(h)
@@ -571,8 +574,19 @@ def batch_dicts(words: np.ndarray, n_graphs: int, spec: tp_survey_spec, n_labels
                  close_hist=r[TP_BW_HIST:TP_BW_HIST + 32].copy())
         if ts:
             d["label_table"] = r[TP_BW_TABLE:TP_BW_TABLE + ts].copy()
+        at = oc
         if spec.outputs & TP_OUT_OPEN_CLOSE:
-            d["open_close"] = r[oc:oc + 1024].reshape(32, 32).copy()
+            d["open_close"] = r[at:at + 1024].reshape(32, 32).copy()
+            at += 1024
+        if spec.outputs & TP_OUT_MAX_EDGE:
+            d["max_edge"] = r[at:at + TP_MAX_EDGE_BINS].copy()
+            at += TP_MAX_EDGE_BINS
+        if spec.outputs & TP_OUT_DEGREE_TABLE:
+            d["degree_table"] = r[at:at + TP_DEGREE_MAX].copy()
+            at += TP_DEGREE_MAX
+        if spec.outputs & TP_OUT_DIRECTED:
+            d["directed"] = r[at:at + 7].copy()
+            at += 8
         out.append(d)
     return out
 
@@ -635,8 +649,8 @@ class Server:
         self.n_labels = n_labels
         self.handle = tripoll_server_create(cfg)
 
-    def add_graph(self, n, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX) -> int:
-        return tripoll_server_add_graph(self.handle, edge_list(n, src, dst, ts, vlab, tie))
+    def add_graph(self, n, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX, directed=False) -> int:
+        return tripoll_server_add_graph(self.handle, edge_list(n, src, dst, ts, vlab, tie, directed=directed))
 
     def remove_graph(self, graph_id: int):
         tripoll_server_remove_graph(self.handle, graph_id)

@@ -229,3 +229,43 @@ def test_batch_input_errors(torch_cuda):
         torch.cuda.synchronize()
         got = tp.batch_dicts(out.cpu().numpy().view(np.uint64), 2, spec, 4)
         assert [r["triangles"] for r in got] == [1, 0]
+
+
+def test_batch_extended_outputs(torch_cuda):
+    """Algorithm 3's max-edge bins, the degree table (each graph's own
+    degrees), the directed census and the joint open/close histogram, per
+    graph of a directed batch: every block equals the oracle's survey of the
+    graph alone, eager and from a recorded launch."""
+    torch = torch_cuda
+    graphs = small_batch()
+    eoff, vcnt, src, dst, ts, vlab = concat(graphs)
+    stream = torch.cuda.current_stream().cuda_stream
+    dev = [upload(torch, x) for x in (src, dst, ts, vlab)]
+    outputs = ("count", "close_hist", "open_close", "max_edge", "degree_table", "directed")
+    spec = tp.make_spec(outputs=outputs, n_labels=8, max_edge_shift=10)
+    with tp.build_batch(eoff, vcnt, *dev, stream=stream, directed=True) as G:
+        bw = tp.tripoll_batch_words(spec)
+        assert bw == 35 + 1024 + tp.TP_MAX_EDGE_BINS + tp.TP_DEGREE_MAX + 8
+        out = torch.zeros(len(graphs) * bw + tp.TP_BATCH_SCRATCH_WORDS, dtype=torch.int64, device="cuda")
+        tp.tripoll_survey_batch(G.handle, spec, out.data_ptr(), stream)
+        torch.cuda.synchronize()
+        words = out.cpu().numpy().view(np.uint64).copy()
+        got = tp.batch_dicts(words, len(graphs), spec, 8)
+        rec = torch.zeros_like(out)
+        with tp.Launch(tp.tripoll_survey_capture(G.handle, spec, rec.data_ptr())) as L:
+            L.replay(stream)
+            torch.cuda.synchronize()
+        assert np.array_equal(rec.cpu().numpy().view(np.uint64), words)
+        # the union's degree table is refused outside the batch survey
+        with pytest.raises(tp.TripollError) as e:
+            tp.tripoll_survey(G.handle, spec, stream)
+        assert e.value.status == tp.TP_ERR_UNSUPPORTED
+    for i, (n, s, t, tt, vl) in enumerate(graphs):
+        if n == 0:
+            assert got[i]["triangles"] == 0
+            continue
+        ref = oracle.survey(n, s, t, tt, vl, outputs=outputs, n_labels=8, max_edge_shift=10)
+        say("graph %d: %d triangles" % (i, ref["triangles"]))
+        assert got[i]["triangles"] == ref["triangles"], i
+        for k in ("close_hist", "open_close", "max_edge", "degree_table", "directed"):
+            assert np.array_equal(np.asarray(got[i][k]).ravel(), np.asarray(ref[k]).ravel()), (i, k)

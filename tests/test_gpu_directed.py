@@ -142,5 +142,5 @@ def test_directed_refusals(torch_cuda):
     with tp.Server(max_slots=2, n_labels=4) as srv:
         gid = srv.add_graph(3, T.from_numpy(src).cuda(), T.from_numpy(dst).cuda())
         with pytest.raises(tp.TripollError) as ei:
-            srv.submit(gid, outputs=("directed",))
-        assert ei.value.status == tp.TP_ERR_UNSUPPORTED
+            srv.submit(gid, outputs=("directed",))  # built without directions
+        assert ei.value.status == tp.TP_ERR_INVALID

@@ -202,21 +202,26 @@ def test_refusals(torch_cuda):
         with pytest.raises(tp.TripollError) as ei:
             tp.tripoll_survey(G.handle, sp, stream(T))
         assert ei.value.status == tp.TP_ERR_INVALID
-        # a single graph through the batch entry point has no block for them
-        out = T.zeros(4096, dtype=T.int64, device="cuda")
-        with pytest.raises(tp.TripollError) as ei:
-            tp.tripoll_survey_batch(G.handle, tp.make_spec(outputs=("degree_table",)), out.data_ptr(), stream(T))
-        assert ei.value.status == tp.TP_ERR_UNSUPPORTED
-    # a batch of two graphs
+        # a single graph through the batch entry point: one block with its table
+        spec = tp.make_spec(outputs=("degree_table",))
+        out = T.zeros(tp.tripoll_batch_words(spec) + tp.TP_BATCH_SCRATCH_WORDS, dtype=T.int64, device="cuda")
+        tp.tripoll_survey_batch(G.handle, spec, out.data_ptr(), stream(T))
+        T.cuda.synchronize()
+        blk = tp.batch_dicts(out.cpu().numpy().view(np.uint64), 1, spec, 4)[0]
+        one = tp.survey(G, stream=stream(T), outputs=("degree_table",))
+        assert blk["triangles"] == one["triangles"] == 1
+        assert np.array_equal(blk["degree_table"], one["degree_table"])
+    # a batch of two graphs: the union's degree table is refused outside the batch survey
     src2 = np.concatenate([src, src])
     dst2 = np.concatenate([dst, dst])
     with tp.build_batch([0, 3, 6], [3, 3], src2, dst2, stream=stream(T)) as B:
         with pytest.raises(tp.TripollError) as ei:
-            tp.survey(B, stream=stream(T), outputs=("max_edge",))
+            tp.survey(B, stream=stream(T), outputs=("degree_table",))
         assert ei.value.status == tp.TP_ERR_UNSUPPORTED
+        # the union's Algorithm 3 bins are those of its two triangles
+        assert tp.survey(B, stream=stream(T), outputs=("max_edge",))["triangles"] == 2
     with tp.Server(max_slots=2, n_labels=4) as srv:
         gid = srv.add_graph(3, T.from_numpy(src).cuda(), T.from_numpy(dst).cuda())
         for outputs in [("max_edge",), ("degree_table",)]:
-            with pytest.raises(tp.TripollError) as ei:
-                srv.submit(gid, outputs=outputs)
-            assert ei.value.status == tp.TP_ERR_UNSUPPORTED
+            r, _ = srv.wait(srv.submit(gid, outputs=outputs), timeout_us=60_000_000)
+            assert r["triangles"] == 1 and r["max_edge" if "max_edge" in outputs else "degree_table"].sum() <= 1

@@ -225,6 +225,58 @@ def test_served_config_graphs_against_oracle(torch_cuda):
             assert r["spread_count"] == want["spread_count"]
 
 
+def test_served_extended_kinds(torch_cuda):
+    """Requests for the joint open/close histogram, Algorithm 3's max-edge
+    bins, the degree table and the directed census (each in result words of
+    its own, over the same segments as the shared pass) mixed with shared-pass
+    requests on a directed graph of many segments and a small one: each result
+    equals tripoll_survey on the same resident graph and the oracle."""
+    torch = torch_cuda
+    big = graph_arrays(14, synth.MASTER_SEED + 511)
+    small = graph_arrays(10, synth.MASTER_SEED + 512, ef=8)
+    specs = [dict(outputs=("count", "close_hist", "open_close")),
+             dict(outputs=("count", "open_close", "max_edge", "degree_table"), window=(1 << 12, 3 << 18),
+                  max_edge_shift=10),
+             dict(outputs=("count", "directed", "label_table"), label_mask=list(range(0, 120, 2))),
+             dict(outputs=("count", "close_hist", "label_table", "spread_count"), spread_lt=1 << 15),
+             dict(outputs=("count", "max_edge", "degree_table", "directed", "open_close"), max_edge_shift=8)]
+    keys = ("triangles", "spread_count", "close_hist", "label_table", "open_close", "max_edge", "degree_table",
+            "directed")
+    with tp.Server(max_slots=4, n_labels=L, step_wedges=1 << 16) as srv:
+        ids = []
+        for a in (big, small):
+            n, dev = upload(torch, a)
+            ids.append(srv.add_graph(n, *dev, directed=True))
+        st = srv.graph_stats(ids[0])
+        say("directed served graph: probes", st["probes"], "segments ~", -(-st["probes"] // (1 << 16)))
+        assert st["probes"] > 4 * (1 << 16)
+        jobs = []
+        for rep in range(2):
+            for k, sp in enumerate(specs):
+                which = (k + rep) % 2
+                jobs.append((srv.submit(ids[which], tag=which, **sp), which, sp))
+                time.sleep(0.002)
+        results = [srv.wait(t, timeout_us=120_000_000)[0] for t, _, _ in jobs]
+        stream = torch.cuda.current_stream().cuda_stream
+        alone = {}
+        for (t, which, sp), r in zip(jobs, results):
+            key = (which, repr(sp))
+            if key not in alone:
+                alone[key] = tp.result_dict(tp.tripoll_survey(srv.graph(ids[which]), tp.make_spec(n_labels=L, **sp),
+                                                              stream), L)
+            for k in keys:
+                assert np.array_equal(np.asarray(r[k]), np.asarray(alone[key][k])), (which, sp, k)
+    for which, a in ((0, big), (1, small)):
+        n, s, d, t, v = a
+        for sp in specs:
+            ref = oracle.survey(n, s, d, t, v, n_labels=L, **sp)
+            got = alone[(which, repr(sp))]
+            assert got["triangles"] == ref["triangles"], (which, sp)
+            for k in ("close_hist", "label_table", "open_close", "max_edge", "degree_table", "directed"):
+                if k in sp["outputs"]:
+                    assert np.array_equal(np.asarray(got[k]).ravel(), np.asarray(ref[k]).ravel()), (which, sp, k)
+
+
 def test_concurrent_submitters(torch_cuda):
     """Several host threads submit and wait at once."""
     torch = torch_cuda
@@ -262,8 +314,11 @@ def test_server_errors(torch_cuda):
             srv.submit(gid + 100, outputs=("count",))
         assert e.value.status == tp.TP_ERR_NOT_FOUND
         with pytest.raises(tp.TripollError) as e:
-            srv.submit(gid, outputs=("count", "open_close"))
-        assert e.value.status == tp.TP_ERR_UNSUPPORTED
+            srv.submit(gid, outputs=("count", "directed"))  # the graph was built without directions
+        assert e.value.status == tp.TP_ERR_INVALID
+        with pytest.raises(tp.TripollError) as e:
+            srv.submit(gid, outputs=("count", "max_edge"), max_edge_shift=40)
+        assert e.value.status == tp.TP_ERR_INVALID
         with pytest.raises(tp.TripollError) as e:
             srv.submit(gid, outputs=("label_table",), n_labels=4)
         assert e.value.status == tp.TP_ERR_INVALID
