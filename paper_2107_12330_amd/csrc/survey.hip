@@ -55,7 +55,14 @@ template <bool WAVE> struct Depth {
     static constexpr uint32_t kChunkCand = kSub * 64;
 };
 constexpr uint32_t kRing = 128;    // per-wave ring of queued hits: slot|label(p), time(p,r), time(p,q), p
-constexpr uint64_t kChunk = 4;     // tiles claimed at a time by a workgroup
+// Tiles claimed with one atomic on the tile counter: at most 8 by a workgroup
+// and 16 by a wave of the per-wave form, fewer when the class has too few
+// tiles for every claimer to make about 8 claims (the tail stays balanced).
+// Every claim is an atomic on one counter, which at 131 M tiny tiles (the
+// 20,000-graph batch) serialises: 8 per wave took that batch's survey to
+// 515 ms, 16 per wave and 8 per workgroup to about 450 ms.
+constexpr uint32_t kMaxClaimGroup = 8;
+constexpr uint32_t kMaxClaimWave = 16;
 constexpr int kRsrcWord3 = 0x00020000;  // buffer resource word 3 for raw 32-bit loads on CDNA
 constexpr uint32_t kEmpty = 0xffffffffu;
 // kernel forms (see survey_kernel)
@@ -140,6 +147,7 @@ struct SurveyParams {
     const SlotSpec *slots;
     uint32_t n_slots, slot_words, slot_labels;
     uint32_t grid_eighths;    // share of the device the persistent grid may fill (0 or 8: all)
+    uint32_t claim;           // tiles a wave (per-wave form) or workgroup claims at a time
     // single-graph surveys: after class c, the running triangle count is
     // copied to class_tri[c] (so that each class's triangles are known)
     unsigned long long *class_tri;
@@ -428,9 +436,14 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     constexpr int kW = WAVE ? 1 : kWaves;       // waves sharing one table
     constexpr int kGroup = WAVE ? kWave : BLOCK;  // threads sharing one table
     constexpr int kGroups = WAVE ? kWaves : 1;  // tables per workgroup
-    constexpr uint64_t kClaim = WAVE ? 8 : kChunk;  // tiles claimed at a time
+    const uint64_t kClaim = P.claim ? P.claim : 1u;  // tiles claimed at a time
     extern __shared__ __align__(16) unsigned char lds[];
     constexpr uint32_t kSlots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
+    // The per-wave form stages its table's keys (fewer than 2^LOG_SLOTS = 64,
+    // so at most one per lane) with their times and labels in registers, so
+    // the table costs one round trip to memory; the workgroup forms, whose
+    // registers bound their occupancy, load the keys twice.
+    constexpr bool kStage = WAVE && LOG_SLOTS > 0 && (1 << LOG_SLOTS) <= kGroup;
     static_assert(!MULTI || (META && !ENUM), "multi-request passes reduce metadata");
     constexpr bool EXT = FORM == kFormExt;
     constexpr bool PART = FORM == kFormPart;
@@ -653,7 +666,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     };
 
     for (;;) {
-        // claim a chunk of kChunk consecutive tiles; consecutive tiles mostly
+        // claim a chunk of kClaim consecutive tiles; consecutive tiles mostly
         // share their target, whose table is then built once
         uint64_t t_begin;
         if (WAVE) {
@@ -731,8 +744,18 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                 // classes never send one) is searched in HBM
                 if (LOG_SLOTS > 0) gmode = log_s > (uint32_t)LOG_SLOTS;
                 if (LOG_SLOTS > 0 && !gmode) {
-                    // two tables of 2^log_s >= 1.25 dq slots each, then the stash
+                    // two tables of 2^log_s >= 1.25 dq slots each, then the stash.
+                    // Staged keys, times and labels are requested before the
+                    // clearing, which their latency overlaps.
                     const uint32_t S = 1u << log_s;
+                    uint32_t kcol = kEmpty, kts = 0, klab = 0;  // this lane's key (gtid < pn), staged
+                    if (kStage && gtid < pn) {
+                        kcol = P.col[kq + pk0 + gtid];
+                        if (META || ENUM) {
+                            kts = P.ets[kq + pk0 + gtid];
+                            klab = P.tlab[kq + pk0 + gtid];
+                        }
+                    }
                     for (uint32_t i = gtid; i < 2 * S + kStash; i += kGroup) hkey[i] = kEmpty;
                     if (gtid == 0) {
                         s_stash = 0;
@@ -743,7 +766,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                     // its slot in the other; keys still homeless after
                     // kMaxKicks moves go to the stash
                     for (uint32_t i = gtid; i < pn; i += kGroup) {
-                        uint32_t cur = P.col[kq + pk0 + i];
+                        uint32_t cur = kStage ? kcol : P.col[kq + pk0 + i];
                         uint32_t t = 0;
                         for (uint32_t it = 0; it < P.max_kicks; ++it) {
                             const uint32_t h = t == 0 ? hash0(cur, log_s) : S + hash1(cur, log_s);
@@ -763,7 +786,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                     // the metadata of every key goes beside its final slot
                     if ((META || ENUM) && !gmode) {
                         for (uint32_t i = gtid; i < pn; i += kGroup) {
-                            const uint32_t r = P.col[kq + pk0 + i];
+                            const uint32_t r = kStage ? kcol : P.col[kq + pk0 + i];
                             uint32_t h = hash0(r, log_s);
                             if (hkey[h] != r) {
                                 h = S + hash1(r, log_s);
@@ -772,8 +795,8 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                                     while (hkey[h] != r) ++h;
                                 }
                             }
-                            hts[h] = P.ets[kq + pk0 + i];
-                            hlab[h] = P.tlab[kq + pk0 + i];
+                            hts[h] = kStage ? kts : P.ets[kq + pk0 + i];
+                            hlab[h] = kStage ? (uint8_t)klab : P.tlab[kq + pk0 + i];
                             if (PART) {
                                 hpos[h] = pk0 + i;
                                 hcnt[h] = 0;
@@ -1207,14 +1230,20 @@ void launch_class(const SurveyParams &P, hipStream_t s, int device)
         std::lock_guard<std::mutex> lock(mu);
         resident[{device, L.total}] = fit;
     }
-    // each workgroup claims kChunk tiles at a time, or 8 per wave
-    const uint64_t claims = WAVE ? (P.n_tiles + 8 * groups - 1) / (8 * groups) : (P.n_tiles + kChunk - 1) / kChunk;
+    // tiles per claim: as many as keep about 8 claims per claiming wave or
+    // workgroup of a full grid
+    SurveyParams Q = P;
+    const uint64_t units = fit * groups;
+    uint32_t claim = WAVE ? kMaxClaimWave : kMaxClaimGroup;
+    while (claim > 1 && Q.n_tiles < (uint64_t)claim * units * 8) claim >>= 1;
+    Q.claim = claim;
+    const uint64_t claims = (Q.n_tiles + (uint64_t)claim * groups - 1) / ((uint64_t)claim * groups);
     uint64_t grid = fit;
     if (P.grid_eighths > 0 && P.grid_eighths < 8) grid = std::max<uint64_t>(1, fit * P.grid_eighths / 8);
     if (grid > claims) grid = claims;
-    zero_u64<<<1, 64, 0, s>>>(P.tile_counter, 1);
+    zero_u64<<<1, 64, 0, s>>>(Q.tile_counter, 1);
     TP_CHECK_LAUNCH();
-    kern<<<(unsigned)grid, BLOCK, L.total, s>>>(P);
+    kern<<<(unsigned)grid, BLOCK, L.total, s>>>(Q);
     TP_CHECK_LAUNCH();
 }
 
