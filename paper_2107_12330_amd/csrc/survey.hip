@@ -258,6 +258,18 @@ struct Hit {
 // fields, to the label-multiset index.
 // The prefilters alone: the window on the three times and the label-mask
 // bit of the multiset (labels must be below 2^lut_shift when it is used).
+// ARITH: the multiset index is computed rather than looked up in `lut`
+// (the per-wave form, whose register budget a lookup's address and wait
+// strain: 20,000-graph batch survey 466 -> 437 ms; the workgroup forms keep
+// the lookup, which is faster there).
+template <bool ARITH = false>
+__device__ __forceinline__ uint32_t label_index(const SurveyParams &P, const Hit &h, const uint16_t *lut)
+{
+    if (ARITH) return multiset_index(h.l_p, h.l_q, h.l_r);
+    return lut[(((h.l_p << P.lut_shift) | h.l_q) << P.lut_shift) | h.l_r];
+}
+
+template <bool ARITH = false>
 __device__ __forceinline__ bool passes_filters(const SurveyParams &P, const Hit &h, const uint64_t *mask_lds,
                                                const uint16_t *lut)
 {
@@ -269,13 +281,13 @@ __device__ __forceinline__ bool passes_filters(const SurveyParams &P, const Hit 
             return false;
     }
     if (f & TP_FILT_LABEL_MASK) {
-        const uint32_t idx = lut[(((h.l_p << P.lut_shift) | h.l_q) << P.lut_shift) | h.l_r];
+        const uint32_t idx = label_index<ARITH>(P, h, lut);
         if (!((mask_lds[idx >> 6] >> (idx & 63)) & 1ull)) return false;
     }
     return true;
 }
 
-template <bool EXT>
+template <bool EXT, bool ARITH = false>
 __device__ __forceinline__ uint32_t reduce_hit(const SurveyParams &P, const Hit &h, unsigned long long *cnt,
                                                const uint64_t *mask_lds, const uint16_t *lut, uint32_t &spread)
 {
@@ -288,7 +300,7 @@ __device__ __forceinline__ uint32_t reduce_hit(const SurveyParams &P, const Hit 
     }
     uint32_t idx = 0;
     if ((P.outputs & TP_OUT_LABEL_TABLE) || (f & TP_FILT_LABEL_MASK))
-        idx = lut[(((h.l_p << P.lut_shift) | h.l_q) << P.lut_shift) | h.l_r];
+        idx = label_index<ARITH>(P, h, lut);
     if (f & TP_FILT_LABEL_MASK) {
         if (!((mask_lds[idx >> 6] >> (idx & 63)) & 1ull)) return 0;
     }
@@ -606,13 +618,13 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                 e_r = !G ? hpos[where] : P.perm[P.col[kq + where]];
                 e_p = e.w;
             } else if (!MULTI) {
-                tri = reduce_hit<EXT>(P, h, cnt, mask_lds, lut, spread);
+                tri = reduce_hit<EXT, WAVE>(P, h, cnt, mask_lds, lut, spread);
             }
         }
         if (ENUM) {
             // the wave's records that pass the prefilters take consecutive
             // places, claimed with one atomic
-            const bool pass = valid && (!P.filters || passes_filters(P, h, mask_lds, lut));
+            const bool pass = valid && (!P.filters || passes_filters<WAVE>(P, h, mask_lds, lut));
             const uint64_t vm = __ballot(pass);
             if (vm) {
                 const unsigned k = (unsigned)__popcll(vm);
@@ -1023,7 +1035,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                                         h.t_qr = P.ets[kq + slot];
                                         h.l_r = P.tlab[kq + slot];
                                     }
-                                    pass = passes_filters(P, h, mask_lds, lut);
+                                    pass = passes_filters<WAVE>(P, h, mask_lds, lut);
                                 }
                                 const uint64_t pm = __ballot(pass);
                                 if (pass) {
