@@ -13,7 +13,8 @@ Survey outputs are selected by name:
   "open_close"    32 x 32 joint (open, close) bins (Algorithm 4)
   "max_edge"      Algorithm 3: over triangles with pairwise distinct vertex
                   labels, counts of the largest edge time t3 in 1024 bins
-                  t3 >> max_edge_shift (the last bin takes the rest)
+                  t3 >> max_edge_shift (the last bin takes the rest);
+                  max_edge_counts() gives its exact counting set
   "degree_table"  counts per sorted triple of ceil(log2 d(v)) over the three
                   vertices (the degree metadata of the evaluation), indexed
                   like the label table, 5984 entries (values 0..31)
@@ -97,6 +98,10 @@ def _load():
     lib.oracle_survey.argtypes = [ctypes.c_uint32, ctypes.c_uint64, p, p, p, p, p,
                                   ctypes.POINTER(_Spec), ctypes.POINTER(_Result), ctypes.c_int,
                                   p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.oracle_max_edge_values.restype = ctypes.c_int
+    lib.oracle_max_edge_values.argtypes = [ctypes.c_uint32, ctypes.c_uint64, p, p, p, p, ctypes.POINTER(_Spec),
+                                           ctypes.POINTER(_Result), ctypes.c_int, p, ctypes.c_uint64,
+                                           ctypes.POINTER(ctypes.c_uint64)]
     lib.oracle_directed_type.restype = ctypes.c_uint32
     lib.oracle_directed_type.argtypes = [ctypes.c_uint32] * 3
     lib.oracle_participation.restype = ctypes.c_int
@@ -234,6 +239,43 @@ def survey(n: int, src, dst, ts, vlab, **kw):
     out = survey_clean(n, u, v, t, vlab, **kw)
     out["m"] = len(u)
     return out
+
+
+def max_edge_counts(n: int, src, dst, ts, vlab, n_labels: int = 4, window=None, label_mask=None,
+                    threads: int = 0):
+    """Algorithm 3's exact counting set (Section 4.5): over the triangles of
+    the cleaned graph whose three vertex labels are pairwise distinct and
+    that pass the filters (as in survey), every distinct largest edge time
+    with its number of triangles.  Written from the definition: the largest
+    time of every such triangle (oracle_max_edge_values, sized by the binned
+    output's total), then numpy's unique to count equal values.  Returns
+    (values ascending as uint32, counts as uint64)."""
+    u, v, t = clean(n, src, dst, ts)
+    kw = dict(n_labels=n_labels, window=window, label_mask=label_mask, threads=threads)
+    total = int(survey_clean(n, u, v, t, vlab, outputs=("max_edge",), max_edge_shift=31, **kw)["max_edge"].sum())
+    sp = _Spec()
+    sp.n_labels = n_labels
+    if window is not None:
+        sp.filters |= 1
+        sp.t_lo, sp.t_hi = int(window[0]), int(window[1])
+    if label_mask is not None:
+        sp.filters |= 2
+        for idx in label_mask:
+            sp.label_mask[idx // 64] |= 1 << (idx % 64)
+    u, v, t = (np.ascontiguousarray(a, np.uint32) for a in (u, v, t))
+    lab = np.ascontiguousarray(vlab, np.uint8)
+    vals = np.zeros(max(total, 1), np.uint32)
+    got = ctypes.c_uint64(0)
+    res = _Result()
+    rc = _load().oracle_max_edge_values(n, len(u), _ptr(u), _ptr(v), _ptr(t), _ptr(lab), ctypes.byref(sp),
+                                        ctypes.byref(res), threads, _ptr(vals), total, ctypes.byref(got))
+    if rc == -3:
+        raise ValueError("vertex label >= n_labels")
+    if rc != 0:
+        raise RuntimeError("oracle_max_edge_values failed: %d" % rc)
+    assert got.value == total
+    vals, cnts = np.unique(vals[:total], return_counts=True)
+    return vals.astype(np.uint32), cnts.astype(np.uint64)
 
 
 def participation(n: int, src, dst, ts, vlab, n_labels: int = 4, window=None, label_mask=None, threads: int = 0):

@@ -432,9 +432,38 @@ static void emit_record(orc_tri *rec, uint32_t p, uint32_t q, uint32_t r,
  * Returns 0, or -2 on allocation failure, -3 if a label >= n_labels is met
  * while the label table or mask is used.
  */
+static int survey_impl(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev, const uint32_t *et,
+                       const uint8_t *edir, const uint8_t *vlab, const orc_spec *sp, orc_result *out, int n_threads,
+                       orc_tri *records, uint64_t capacity, uint64_t *n_records,
+                       uint32_t *maxe, uint64_t maxe_cap, uint64_t *n_maxe);
+
 int oracle_survey(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev, const uint32_t *et,
                   const uint8_t *edir, const uint8_t *vlab, const orc_spec *sp, orc_result *out, int n_threads,
                   orc_tri *records, uint64_t capacity, uint64_t *n_records)
+{
+    return survey_impl(n, m, eu, ev, et, edir, vlab, sp, out, n_threads, records, capacity, n_records, NULL, 0,
+                       NULL);
+}
+
+/*
+ * Algorithm 3's counting set, as its raw material (Section 4.5): for every
+ * triangle of the cleaned graph whose three vertex labels are pairwise
+ * distinct and that passes the spec's filters, the largest of its three
+ * edge times, written to values[] (at most `capacity`, in no particular
+ * order; their number in *n_values).  Counting equal values gives the set.
+ * Returns as oracle_survey (the spec's outputs are surveyed too).
+ */
+int oracle_max_edge_values(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev, const uint32_t *et,
+                           const uint8_t *vlab, const orc_spec *sp, orc_result *out, int n_threads,
+                           uint32_t *values, uint64_t capacity, uint64_t *n_values)
+{
+    return survey_impl(n, m, eu, ev, et, NULL, vlab, sp, out, n_threads, NULL, 0, NULL, values, capacity, n_values);
+}
+
+static int survey_impl(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev, const uint32_t *et,
+                       const uint8_t *edir, const uint8_t *vlab, const orc_spec *sp, orc_result *out, int n_threads,
+                       orc_tri *records, uint64_t capacity, uint64_t *n_records,
+                       uint32_t *maxe, uint64_t maxe_cap, uint64_t *n_maxe)
 {
     orc_graph g;
     memset(out, 0, sizeof(*out));
@@ -451,7 +480,7 @@ int oracle_survey(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev
         out->wedges += d ? d * (d - 1) / 2 : 0;
     }
 
-    uint64_t n_rec = 0;
+    uint64_t n_rec = 0, n_max = 0;
     int err = 0;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -497,6 +526,15 @@ int oracle_survey(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev
                         if (slot < capacity)
                             emit_record(&records[slot], (uint32_t)p, q, r, t_pq, t_pr, t_qr, vlab);
                     }
+                    if (maxe && l_p != l_q && l_q != l_r && l_p != l_r &&
+                        passes(sp, t_pq, t_pr, t_qr, l_p, l_q, l_r)) {
+                        uint32_t t3 = t_pq > t_pr ? t_pq : t_pr;
+                        if (t_qr > t3) t3 = t_qr;
+                        uint64_t slot;
+#pragma omp atomic capture
+                        slot = n_max++;
+                        if (slot < maxe_cap) maxe[slot] = t3;
+                    }
                     ++x;
                     ++y;
                 }
@@ -518,6 +556,7 @@ int oracle_survey(uint32_t n, uint64_t m, const uint32_t *eu, const uint32_t *ev
         free(acc);
     }
     if (n_records) *n_records = n_rec;
+    if (n_maxe) *n_maxe = n_max;
     free_graph(&g);
     return err;
 }

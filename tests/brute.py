@@ -68,7 +68,7 @@ def survey(n, src, dst, ts, vlab, n_labels=4, spread_lt=0, window=None, label_ma
     res = dict(triangles=0, spread_count=0, close_hist=np.zeros(32, np.uint64),
                label_table=np.zeros(len(idx_of), np.uint64), open_close=np.zeros((32, 32), np.uint64),
                max_edge=np.zeros(1024, np.uint64), degree_table=np.zeros(len(deg_idx), np.uint64),
-               m=len(edges), tris=tris)
+               max_edge_exact={}, m=len(edges), tris=tris)
     for a, b, c, tab, tac, tbc in tris:
         times = sorted((tab, tac, tbc))
         if window is not None and not all(window[0] <= x <= window[1] for x in times):
@@ -88,6 +88,8 @@ def survey(n, src, dst, ts, vlab, n_labels=4, spread_lt=0, window=None, label_ma
         # Algorithm 3: pairwise distinct vertex labels, largest edge time
         if len({int(vlab[a]), int(vlab[b]), int(vlab[c])}) == 3:
             res["max_edge"][min(1023, times[2] // 2 ** max_edge_shift)] += 1
+            # and its exact counting set: largest time -> triangles
+            res["max_edge_exact"][times[2]] = res["max_edge_exact"].get(times[2], 0) + 1
         # degree metadata: sorted triple of ceil(log2 d)
         dl = tuple(sorted(ceil_log2_bin(degree[x]) for x in (a, b, c)))
         res["degree_table"][deg_idx[dl]] += 1

@@ -116,6 +116,27 @@ static void random_multigraph(uint32_t n, uint64_t raw, int threads)
     check(sum_u64(r->degree_table, ORC_DEGREE_MAX) == brute, "degree table sums to T");
     check(sum_u64(r->directed, 7) == brute, "directed census sums to T");
     check(r->spread_count <= brute, "spread count at most T");
+    {
+        /* Algorithm 3's values: one per distinct-label triangle, as many as
+         * the binned output counts, each the largest time of a record */
+        const uint64_t want = sum_u64(r->max_edge, 1024);
+        uint32_t *mv = calloc(want + 1, sizeof(uint32_t));
+        uint64_t got = 0, distinct = 0;
+        orc_result *r2 = calloc(1, sizeof(orc_result));
+        memset(&sp, 0, sizeof(sp));
+        sp.n_labels = 4;
+        rc = oracle_max_edge_values(n, (uint64_t)m, u, v, t, lab, &sp, r2, threads, mv, want + 1, &got);
+        check(rc == 0, "max-edge values return 0");
+        check(got == want, "one value per distinct-label triangle");
+        for (uint64_t i = 0; i < nrec; ++i) {
+            const orc_tri *x = &rec[i];
+            if (x->l_a == x->l_b || x->l_b == x->l_c || x->l_a == x->l_c) continue;
+            ++distinct;
+        }
+        check(distinct == want, "distinct-label records match the values");
+        free(r2);
+        free(mv);
+    }
     uint64_t *vc = calloc(n, 8), *ec = calloc((size_t)m, 8);
     memset(&sp, 0, sizeof(sp));
     sp.n_labels = 4;

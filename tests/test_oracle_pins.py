@@ -176,6 +176,59 @@ def test_max_edge_label_classes_and_saturation():
                                       for a, b, c in combinations(range(4), 3))
 
 
+def _exact_dict(vals, cnts):
+    assert (np.diff(vals.astype(np.int64)) > 0).all()  # ascending, each value once
+    return dict(zip(vals.tolist(), cnts.tolist()))
+
+
+@pytest.mark.parametrize("n", [3, 8, 16])
+def test_max_edge_exact_complete_graph_closed_form(n):
+    # K_n, ts(u,v) = max(u,v), labels = ids: every triangle a<b<c has largest
+    # time c, and c closes C(c,2) of them, so the counting set is {c: C(c,2)}
+    e = np.array(complete(n, lambda u, v: max(u, v)), np.int64).reshape(-1, 3)
+    vals, cnts = oracle.max_edge_counts(n, e[:, 0].astype(np.uint32), e[:, 1].astype(np.uint32),
+                                        e[:, 2].astype(np.uint32), np.arange(n, dtype=np.uint8), n_labels=16)
+    assert _exact_dict(vals, cnts) == {c: math.comb(c, 2) for c in range(2, n)}
+
+
+def test_max_edge_exact_degenerate():
+    # no distinct-label triangle (two label classes), no triangle, no edge
+    n = 10
+    e = np.array(complete(n, lambda u, v: u * v), np.int64).reshape(-1, 3)
+    s, d, t = (e[:, i].astype(np.uint32) for i in range(3))
+    vals, cnts = oracle.max_edge_counts(n, s, d, t, (np.arange(n) % 2).astype(np.uint8))
+    assert len(vals) == 0 and len(cnts) == 0
+    star = np.arange(1, n, dtype=np.uint32)
+    vals, _ = oracle.max_edge_counts(n, np.zeros(n - 1, np.uint32), star, star, np.arange(n, dtype=np.uint8),
+                                     n_labels=16)
+    assert len(vals) == 0
+    vals, _ = oracle.max_edge_counts(n, np.zeros(0, np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.uint32),
+                                     np.zeros(n, np.uint8))
+    assert len(vals) == 0
+
+
+@pytest.mark.parametrize("seed,n,M,L", [(11, 40, 400, 3), (12, 90, 1800, 4), (13, 150, 3000, 8),
+                                        (14, 60, 1500, 16)])
+def test_max_edge_exact_against_brute_force(seed, n, M, L):
+    # the exact counting set against the brute force, with and without the
+    # filters; summed into bins it is the binned output of Algorithm 3
+    rng = np.random.default_rng(seed)
+    src, dst, ts, vlab = _random_graph(rng, n, M, tbits=int(rng.integers(4, 33)), L=L)
+    b = brute.survey(n, src, dst, ts, vlab, n_labels=L)
+    vals, cnts = oracle.max_edge_counts(n, src, dst, ts, vlab, n_labels=L)
+    assert _exact_dict(vals, cnts) == b["max_edge_exact"]
+    for shift in (0, 5, 20):
+        r = oracle.survey(n, src, dst, ts, vlab, outputs=("max_edge",), n_labels=L, max_edge_shift=shift)
+        binned = np.zeros(1024, np.uint64)
+        np.add.at(binned, np.minimum(vals.astype(np.int64) >> shift, 1023), cnts)
+        assert (binned == r["max_edge"]).all()
+    lo, hi = np.quantile(ts.astype(np.float64), [0.2, 0.9]).astype(np.int64)
+    mask = set(range(0, brute.colex_multisets(L).__len__(), 3))
+    b = brute.survey(n, src, dst, ts, vlab, n_labels=L, window=(lo, hi), label_mask=mask)
+    vals, cnts = oracle.max_edge_counts(n, src, dst, ts, vlab, n_labels=L, window=(lo, hi), label_mask=mask)
+    assert _exact_dict(vals, cnts) == b["max_edge_exact"]
+
+
 def test_max_edge_shift_range():
     with pytest.raises(ValueError):
         run(4, complete(4), outputs=("count", "max_edge"), max_edge_shift=32)
