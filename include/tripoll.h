@@ -272,7 +272,8 @@ typedef struct {
  * last TP_RW_SCRATCH_WORDS words are used by the survey itself: the first
  * four are work counters whose content is unspecified; then, at
  * TP_RW_CLASS_TRI + c, the triangles counted by target classes 0..c (a
- * running sum, taken after each class's kernel). */
+ * running sum, taken after each class's kernel); the last eight are work
+ * counters again. */
 #define TP_RW_TRIANGLES 0u
 #define TP_RW_SPREAD 1u
 #define TP_RW_PROBES 2u
@@ -283,7 +284,7 @@ typedef struct {
 #define TP_RW_DEGREE (TP_RW_MAX_EDGE + TP_MAX_EDGE_BINS)
 #define TP_RW_DIRECTED (TP_RW_DEGREE + TP_DEGREE_MAX)
 #define TP_RW_SCRATCH (TP_RW_DIRECTED + 8u)
-#define TP_RW_SCRATCH_WORDS 8u
+#define TP_RW_SCRATCH_WORDS 16u
 #define TP_RW_CLASS_TRI (TP_RW_SCRATCH + 4u)
 #define TP_RESULT_WORDS (TP_RW_SCRATCH + TP_RW_SCRATCH_WORDS)
 
@@ -308,6 +309,33 @@ tp_status tripoll_survey(const tp_graph *g, const tp_survey_spec *spec, tp_surve
  */
 tp_status tripoll_survey_async(const tp_graph *g, const tp_survey_spec *spec, uint64_t *dev_out,
                                void *stream);
+
+/*
+ * The exact counting set of Algorithm 3 (Section 4.5, "Containers" in
+ * Section 4.1): over the triangles whose three vertex labels are pairwise
+ * distinct and that pass the spec's filters, every distinct value of the
+ * largest of the three edge times, with the number of triangles that have
+ * it.  (TP_OUT_MAX_EDGE reports the same triangles binned into 1024 ranges
+ * of 2^max_edge_shift times; this call keeps every value.)
+ *   spec        filters, n_labels and strategy apply as in tripoll_survey;
+ *               outputs and max_edge_shift are ignored
+ *   dev_values  device buffer of `capacity` uint32 owned by the caller: the
+ *               distinct largest times, ascending
+ *   dev_counts  device buffer of `capacity` uint64 owned by the caller: the
+ *               number of triangles of each value
+ *   n_values    host: the number of distinct values written
+ * Synchronous with respect to the host.  Works in a device table of 2^k >=
+ * 2 m entries of 16 bytes (m: oriented edges, at most 2^32 entries),
+ * allocated for the call; each counted triangle costs two device-scope
+ * atomics there, so the call is slower than the binned output.  At most m
+ * values exist, so capacity = m always suffices.
+ * Errors: TP_ERR_INVALID for a null pointer or a spec tripoll_survey
+ * refuses, and when more than `capacity` distinct values exist (then
+ * *n_values holds their number and the buffers are untouched);
+ * TP_ERR_UNSUPPORTED on a batch handle; TP_ERR_OOM; TP_ERR_DEVICE.
+ */
+tp_status tripoll_max_edge_counts(const tp_graph *g, const tp_survey_spec *spec, uint32_t *dev_values,
+                                  uint64_t *dev_counts, uint64_t capacity, uint64_t *n_values, void *stream);
 
 /*
  * As tripoll_survey, for callers that cannot allocate device memory (code
@@ -451,7 +479,7 @@ tp_status tripoll_graph_count(const tp_graph *g, uint32_t *n_graphs);
 #define TP_BW_PROBES 2u
 #define TP_BW_HIST 3u
 #define TP_BW_TABLE 35u
-#define TP_BATCH_SCRATCH_WORDS 4u
+#define TP_BATCH_SCRATCH_WORDS 8u
 uint64_t tripoll_batch_words(const tp_survey_spec *spec);
 
 /*

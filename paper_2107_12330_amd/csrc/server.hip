@@ -55,7 +55,7 @@ struct Resident {
     sched::Engine eng;
     hipStream_t stream = nullptr;
     DArray<SlotSpec> dslots;
-    DArray<unsigned long long> dout;  // slots * words, then one scratch word
+    DArray<unsigned long long> dout;  // slots * words, then the claim counters
     std::unique_ptr<HostArray<SlotSpec>> hstage;   // slot table for the next step
     std::unique_ptr<HostArray<unsigned long long>> hres;  // result blocks of finishing slots
     std::vector<SlotSpec> spec;       // slot table as admitted
@@ -415,7 +415,7 @@ extern "C" tp_status tripoll_server_add_graph(tp_server *srv, const tp_edge_list
         R->eng = sched::Engine(srv->cfg.max_slots, (uint32_t)std::min<uint64_t>(nseg, 4096));
         R->stream = R->small ? srv->small : srv->big;
         R->dslots.reset(kMaxSlots, srv->big);
-        R->dout.reset((size_t)srv->cfg.max_slots * srv->words + 1, srv->big);
+        R->dout.reset((size_t)srv->cfg.max_slots * srv->words + kClaimWords, srv->big);
         R->hstage = std::make_unique<HostArray<SlotSpec>>(kMaxSlots);
         R->hres = std::make_unique<HostArray<unsigned long long>>((size_t)srv->cfg.max_slots * srv->words);
         R->spec.assign(srv->cfg.max_slots, SlotSpec{});

@@ -63,6 +63,18 @@ constexpr uint32_t kRing = 128;    // per-wave ring of queued hits: slot|label(p
 // 515 ms, 16 per wave and 8 per workgroup to about 450 ms.
 constexpr uint32_t kMaxClaimGroup = 8;
 constexpr uint32_t kMaxClaimWave = 16;
+// The tiles of a batch's launch are cut into kClaimSegs contiguous segments,
+// one per XCD, each with its own claim counter.  Workgroups are dispatched to
+// the 8 XCDs round robin, so workgroup b starts on segment b % 8: the waves of
+// one XCD then work through one stretch of graphs, whose rows its L2 holds,
+// instead of every XCD fetching the same rows into its own L2 (20,000-graph
+// batch: 1.87 -> 1.08 TB fetched by the survey).  A workgroup whose segment is
+// used up takes what is left of the next ones.  A single graph keeps one
+// counter: there all XCDs share one stretch of ranks, whose rows the
+// device-wide last-level cache then holds once (scale 26: tiny class 8 ms
+// with one counter, 14 ms with eight).
+constexpr uint32_t kClaimSegs = 8;
+static_assert(kClaimSegs <= kClaimWords && kClaimSegs == 8, "one claim counter per segment, 2^3 segments");
 constexpr int kRsrcWord3 = 0x00020000;  // buffer resource word 3 for raw 32-bit loads on CDNA
 constexpr uint32_t kEmpty = 0xffffffffu;
 // kernel forms (see survey_kernel)
@@ -102,7 +114,7 @@ struct SurveyParams {
     uint32_t kbits;
     const TileDesc *tiles;
     uint64_t n_tiles;
-    unsigned long long *tile_counter;
+    unsigned long long *tile_counter;  // kClaimSegs claim counters
     unsigned long long *out;  // result words (one block per graph of a batch)
     const uint32_t *rank_gid; // graph of each rank (batches), or null
     uint32_t g_stride;        // words per graph block
@@ -148,6 +160,13 @@ struct SurveyParams {
     uint32_t n_slots, slot_words, slot_labels;
     uint32_t grid_eighths;    // share of the device the persistent grid may fill (0 or 8: all)
     uint32_t claim;           // tiles a wave (per-wave form) or workgroup claims at a time
+    uint32_t claim_seg_log;   // log2 of the claim segments (0 or 3)
+    // exact counting set of Algorithm 3 (extended form): an open-addressing
+    // table of maxe_mask + 1 slots; key value + 1 (0: empty) and its count
+    unsigned long long *maxe_keys;
+    unsigned long long *maxe_counts;
+    uint64_t maxe_mask;
+    unsigned *maxe_overflow;  // set when a value finds no slot
     // single-graph surveys: after class c, the running triangle count is
     // copied to class_tri[c] (so that each class's triangles are known)
     unsigned long long *class_tri;
@@ -287,6 +306,33 @@ __device__ __forceinline__ bool passes_filters(const SurveyParams &P, const Hit 
     return true;
 }
 
+// One more triangle whose largest edge time is v, in the exact counting set:
+// linear probing from a hash of v (the "lowbias32" integer mixer published
+// with C. Wellons' hash-prospector); a slot, once claimed by a compare
+// and swap, keeps its value, so a plain read that already shows v (or any
+// other value) is final and only an empty-looking slot needs the atomic.
+__device__ __forceinline__ void maxe_count(const SurveyParams &P, uint32_t v)
+{
+    const unsigned long long key = (unsigned long long)v + 1ull;
+    uint32_t x = v;
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    uint64_t s = x & P.maxe_mask;
+    for (uint64_t probe = 0; probe <= P.maxe_mask; ++probe) {
+        unsigned long long k = __hip_atomic_load(P.maxe_keys + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == 0ull) k = atomicCAS(P.maxe_keys + s, 0ull, key);
+        if (k == 0ull || k == key) {
+            atomicAdd(P.maxe_counts + s, 1ull);
+            return;
+        }
+        s = (s + 1) & P.maxe_mask;
+    }
+    atomicOr(P.maxe_overflow, 1u);
+}
+
 template <bool EXT, bool ARITH = false>
 __device__ __forceinline__ uint32_t reduce_hit(const SurveyParams &P, const Hit &h, unsigned long long *cnt,
                                                const uint64_t *mask_lds, const uint16_t *lut, uint32_t &spread)
@@ -320,6 +366,10 @@ __device__ __forceinline__ uint32_t reduce_hit(const SurveyParams &P, const Hit 
         // Algorithm 3: vertex labels pairwise distinct; bin of the largest edge time
         if (h.l_p != h.l_q && h.l_q != h.l_r && h.l_p != h.l_r)
             atomicAdd(&cnt[B.maxe + min(t3 >> P.max_edge_shift, 1023u)], 1ull);
+    }
+    if (EXT && P.maxe_keys) {
+        // Algorithm 3's exact counting set: the same triangles, every value kept
+        if (h.l_p != h.l_q && h.l_q != h.l_r && h.l_p != h.l_r) maxe_count(P, t3);
     }
     if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE))
         atomicAdd(&cnt[B.deg + multiset_index(h.b_p, h.b_q, h.b_r)], 1ull);
@@ -677,24 +727,37 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
         }
     };
 
+    // this workgroup's segment of the launch's tiles first, then the others
+    const uint32_t nseg = 1u << P.claim_seg_log;
+    uint32_t seg = blockIdx.x & (nseg - 1);
+    uint32_t segs_left = nseg;
+    uint64_t seg_lo = (P.n_tiles * seg) >> P.claim_seg_log;
+    uint64_t seg_hi = (P.n_tiles * (seg + 1)) >> P.claim_seg_log;
     for (;;) {
         // claim a chunk of kClaim consecutive tiles; consecutive tiles mostly
         // share their target, whose table is then built once
         uint64_t t_begin;
         if (WAVE) {
             unsigned long long c = 0;
-            if (lane == 0) c = atomicAdd(P.tile_counter, 1ull);
+            if (lane == 0) c = atomicAdd(P.tile_counter + seg, 1ull);
             const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)c);
             const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(c >> 32));
-            t_begin = (((uint64_t)hi << 32) | lo) * kClaim;
+            t_begin = seg_lo + (((uint64_t)hi << 32) | lo) * kClaim;
         } else {
-            if (tid == 0) s_tile = atomicAdd(P.tile_counter, 1ull);
+            if (tid == 0) s_tile = atomicAdd(P.tile_counter + seg, 1ull);
             __syncthreads();
-            t_begin = s_tile * kClaim;
+            t_begin = seg_lo + s_tile * kClaim;
             __syncthreads();  // everyone has read s_tile before it is claimed again
         }
-        if (t_begin >= P.n_tiles) break;
-        const uint64_t t_end = min(t_begin + kClaim, P.n_tiles);
+        if (t_begin >= seg_hi) {
+            // the segment is used up (its counter only grows): the next one
+            if (--segs_left == 0) break;
+            seg = (seg + 1) & (nseg - 1);
+            seg_lo = (P.n_tiles * seg) >> P.claim_seg_log;
+            seg_hi = (P.n_tiles * (seg + 1)) >> P.claim_seg_log;
+            continue;
+        }
+        const uint64_t t_end = min(t_begin + kClaim, seg_hi);
         for (uint64_t ti = t_begin; ti < t_end; ++ti) {
             const TileDesc d = sload(P.tiles + (P.n_tiles - 1 - ti));
             if (ENUM) cur_tile = P.tile_gbase + (P.n_tiles - 1 - ti);
@@ -1249,11 +1312,12 @@ void launch_class(const SurveyParams &P, hipStream_t s, int device)
     uint32_t claim = WAVE ? kMaxClaimWave : kMaxClaimGroup;
     while (claim > 1 && Q.n_tiles < (uint64_t)claim * units * 8) claim >>= 1;
     Q.claim = claim;
+    Q.claim_seg_log = P.rank_gid ? 3u : 0u;  // segments per XCD for batches (kClaimSegs)
     const uint64_t claims = (Q.n_tiles + (uint64_t)claim * groups - 1) / ((uint64_t)claim * groups);
     uint64_t grid = fit;
     if (P.grid_eighths > 0 && P.grid_eighths < 8) grid = std::max<uint64_t>(1, fit * P.grid_eighths / 8);
     if (grid > claims) grid = claims;
-    zero_u64<<<1, 64, 0, s>>>(Q.tile_counter, 1);
+    zero_u64<<<1, 64, 0, s>>>(Q.tile_counter, kClaimSegs);
     TP_CHECK_LAUNCH();
     kern<<<(unsigned)grid, BLOCK, L.total, s>>>(Q);
     TP_CHECK_LAUNCH();
@@ -1493,7 +1557,7 @@ void survey_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned long l
 {
     zero_u64<<<grid_for(TP_RESULT_WORDS, 256), 256, 0, s>>>(dev_out, TP_RESULT_WORDS);
     TP_CHECK_LAUNCH();
-    SurveyParams P = make_params(g, sp, dev_out, dev_out + TP_RW_SCRATCH);
+    SurveyParams P = make_params(g, sp, dev_out, dev_out + kRwClaim);
     if (g->m == 0 || g->n_in == 0) return;
     if (!ENUM) P.class_tri = dev_out + TP_RW_CLASS_TRI;
     if (ENUM) {
@@ -1532,7 +1596,7 @@ void survey_batch_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsigned 
     const uint64_t total = (uint64_t)graph_count(g) * words + TP_BATCH_SCRATCH_WORDS;
     zero_u64<<<grid_for(total, 256), 256, 0, s>>>(dev_out, total);
     TP_CHECK_LAUNCH();
-    SurveyParams P = make_params(g, sp, dev_out, dev_out + (total - TP_BATCH_SCRATCH_WORDS));
+    SurveyParams P = make_params(g, sp, dev_out, dev_out + (total - kClaimWords));
     P.rank_gid = g->n_graphs ? g->rank_gid.get() : nullptr;
     P.g_stride = words;
     P.o_tri = TP_BW_TRIANGLES;
@@ -1604,6 +1668,104 @@ extern "C" tp_status tripoll_survey_async(const tp_graph *g, const tp_survey_spe
         if (!dev_out) fail(TP_ERR_INVALID, "tripoll_survey_async: NULL output");
         validate_spec(g, spec);
         survey_enqueue<false>(g, spec, reinterpret_cast<unsigned long long *>(dev_out), (hipStream_t)stream);
+    });
+}
+
+// ---------------------------------------------------------------- exact counting set of Algorithm 3
+
+namespace {
+
+__global__ void k_maxe_flags(const unsigned long long *keys, uint64_t n, uint32_t *occupied)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        occupied[i] = keys[i] != 0ull ? 1u : 0u;
+}
+
+// the occupied slots packed in slot order: value (the sort key), its place
+// in the packed order, and its count
+__global__ void k_maxe_pack(const unsigned long long *keys, const unsigned long long *counts, const uint64_t *pos,
+                            uint64_t n, uint64_t *value, uint32_t *place, unsigned long long *count)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const unsigned long long k = keys[i];
+        if (!k) continue;
+        const uint64_t j = pos[i];
+        value[j] = k - 1ull;
+        place[j] = (uint32_t)j;
+        count[j] = counts[i];
+    }
+}
+
+__global__ void k_maxe_out(const uint64_t *value, const uint32_t *place, const unsigned long long *count, uint64_t n,
+                           uint32_t *out_value, uint64_t *out_count)
+{
+    for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < n; j += (uint64_t)gridDim.x * blockDim.x) {
+        out_value[j] = (uint32_t)value[j];
+        out_count[j] = count[place[j]];
+    }
+}
+
+}  // namespace
+
+extern "C" tp_status tripoll_max_edge_counts(const tp_graph *g, const tp_survey_spec *spec, uint32_t *dev_values,
+                                             uint64_t *dev_counts, uint64_t capacity, uint64_t *n_values, void *stream)
+{
+    return guard([&] {
+        if (!spec || !n_values) fail(TP_ERR_INVALID, "tripoll_max_edge_counts: NULL argument");
+        if (capacity && (!dev_values || !dev_counts))
+            fail(TP_ERR_INVALID, "tripoll_max_edge_counts: NULL output buffer");
+        *n_values = 0;
+        tp_survey_spec sp = *spec;
+        sp.outputs = TP_OUT_COUNT;
+        sp.max_edge_shift = 0;
+        validate_spec(g, &sp);
+        if (g->n_graphs) fail(TP_ERR_UNSUPPORTED, "tripoll_max_edge_counts: single graphs only");
+        if (g->m == 0 || g->n_in == 0) return;
+        hipStream_t s = (hipStream_t)stream;
+        // at most m distinct times: a table of at least 2 m slots stays at
+        // most half full
+        uint64_t slots = 1024;
+        while (slots < 2 * g->m && slots < (1ull << 32)) slots <<= 1;
+        DArray<unsigned long long> keys(slots, s), counts(slots, s), res(TP_RESULT_WORDS, s), flag(1, s);
+        zero_u64<<<grid_for(slots, 256), 256, 0, s>>>(keys.get(), slots);
+        zero_u64<<<grid_for(slots, 256), 256, 0, s>>>(counts.get(), slots);
+        zero_u64<<<grid_for(TP_RESULT_WORDS, 256), 256, 0, s>>>(res.get(), TP_RESULT_WORDS);
+        zero_u64<<<1, 64, 0, s>>>(flag.get(), 1);
+        TP_CHECK_LAUNCH();
+        SurveyParams P = make_params(g, &sp, res.get(), res.get() + kRwClaim);
+        P.maxe_keys = keys.get();
+        P.maxe_counts = counts.get();
+        P.maxe_mask = slots - 1;
+        P.maxe_overflow = reinterpret_cast<unsigned *>(flag.get());
+        launch_all<true, false, kFormExt>(g, P, sp.strategy, s);
+        // pack the occupied slots, then sort them by value
+        DArray<uint32_t> occupied(slots, s);
+        DArray<uint64_t> pos(slots + 1, s);
+        k_maxe_flags<<<grid_for(slots, 256), 256, 0, s>>>(keys.get(), slots, occupied.get());
+        TP_CHECK_LAUNCH();
+        scan_u32_to_u64(occupied.get(), pos.get(), slots, s);
+        uint64_t total = 0;
+        unsigned long long over = 0;
+        TP_HIP(hipMemcpyAsync(&total, pos.get() + slots, 8, hipMemcpyDeviceToHost, s));
+        TP_HIP(hipMemcpyAsync(&over, flag.get(), 8, hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+        if (over) fail(TP_ERR_DEVICE, "tripoll_max_edge_counts: a value found no slot in the table");
+        *n_values = total;
+        if (total > capacity)
+            fail(TP_ERR_INVALID, "tripoll_max_edge_counts: " + std::to_string(total) + " distinct values, capacity " +
+                                     std::to_string(capacity));
+        if (total == 0) return;
+        DArray<uint64_t> va(total, s), vb(total, s);
+        DArray<uint32_t> pa(total, s), pb(total, s);
+        DArray<unsigned long long> cnt(total, s);
+        k_maxe_pack<<<grid_for(slots, 256), 256, 0, s>>>(keys.get(), counts.get(), pos.get(), slots, va.get(), pa.get(),
+                                                         cnt.get());
+        TP_CHECK_LAUNCH();
+        const bool alt = radix_sort_pairs(va.get(), pa.get(), vb.get(), pb.get(), total, 32, s);
+        k_maxe_out<<<grid_for(total, 256), 256, 0, s>>>(alt ? vb.get() : va.get(), alt ? pb.get() : pa.get(), cnt.get(),
+                                                        total, dev_values, dev_counts);
+        TP_CHECK_LAUNCH();
+        TP_HIP(hipStreamSynchronize(s));
     });
 }
 
@@ -1745,7 +1907,7 @@ extern "C" tp_status tripoll_enum_open(const tp_graph *g, const tp_survey_spec *
         TP_HIP(hipMemsetAsync(e->cursor.get(), 0, std::max<uint64_t>(T, 1) * sizeof(unsigned), s));
         if (T && g->m && g->n_in) {
             // one counting pass: the records of every tile
-            SurveyParams P = make_params(g, &e->spec, e->res.get(), e->res.get() + TP_RW_SCRATCH);
+            SurveyParams P = make_params(g, &e->spec, e->res.get(), e->res.get() + kRwClaim);
             P.enum_tile_count = count.get();
             P.enum_srow = e->srow.get();
             enum_tiles(e.get(), P, 0, T, s);
@@ -1803,7 +1965,7 @@ extern "C" tp_status tripoll_enum_next(tp_enum_stream *e, uint32_t *dev_records,
             fail(TP_ERR_INVALID, "tripoll_enum_next: capacity " + std::to_string(capacity) +
                                      " is below the next tile's records (the largest tile has " +
                                      std::to_string(e->max_tile) + ")");
-        SurveyParams P = make_params(e->g, &e->spec, e->res.get(), e->res.get() + TP_RW_SCRATCH);
+        SurveyParams P = make_params(e->g, &e->spec, e->res.get(), e->res.get() + kRwClaim);
         P.enum_out = dev_records;
         P.enum_cap = capacity;
         P.enum_tile_base = e->base.get();
@@ -1846,7 +2008,7 @@ extern "C" tp_status tripoll_participation(const tp_graph *g, const tp_survey_sp
             zero_u64<<<grid_for(g->m, 256), 256, 0, s>>>(edge, g->m);
             TP_CHECK_LAUNCH();
         }
-        SurveyParams P = make_params(g, &sp, res.get(), res.get() + TP_RW_SCRATCH);
+        SurveyParams P = make_params(g, &sp, res.get(), res.get() + kRwClaim);
         P.part_edge = edge;
         if (g->m && g->n_in) launch_all<true, false, kFormPart>(g, P, sp.strategy, s);
         if (vertex_counts) {
@@ -2015,7 +2177,7 @@ void tp::solo_segment_enqueue(const tp_graph *g, const tp_survey_spec *sp, unsig
     if (n_seg == 0 || seg >= n_seg) fail(TP_ERR_INVALID, "single-request segment: bad segment");
     validate_spec(g, sp);
     if (g->m == 0 || g->n_in == 0) return;
-    SurveyParams P = make_params(g, sp, dev_out, dev_out + TP_RW_SCRATCH);
+    SurveyParams P = make_params(g, sp, dev_out, dev_out + kRwClaim);
     P.grid_eighths = grid_eighths;
     for (int c = 0; c < kNumClasses; ++c) {
         const uint64_t nt = g->n_tiles[c];
@@ -2077,7 +2239,7 @@ PlanCfg to_cfg(const tp_plan *p)
 float time_class(const tp_graph *g, const tp_survey_spec *sp, unsigned long long *buf, int c, uint32_t v, int reps,
                  hipStream_t s)
 {
-    SurveyParams P = make_params(g, sp, buf, buf + TP_RW_SCRATCH);
+    SurveyParams P = make_params(g, sp, buf, buf + kRwClaim);
     P.tiles = g->tiles[c].get();
     P.n_tiles = g->n_tiles[c];
     float best = 0.f;

@@ -113,6 +113,13 @@ struct DArray {
 
 constexpr int kWave = 64;
 
+// Claim counters of a survey launch: the last kClaimWords words of a result
+// buffer's scratch and of a batch buffer.
+constexpr uint32_t kClaimWords = 8;
+constexpr uint32_t kRwClaim = TP_RW_SCRATCH + TP_RW_SCRATCH_WORDS - kClaimWords;
+static_assert(TP_RW_SCRATCH_WORDS >= 8 + kClaimWords, "four counters, four class counts, the claim counters");
+static_assert(TP_BATCH_SCRATCH_WORDS >= kClaimWords, "a batch buffer holds the claim counters");
+
 inline unsigned grid_for(size_t n, int block, unsigned cap = 256u * 8u * 8u)
 {
     size_t g = (n + block - 1) / block;

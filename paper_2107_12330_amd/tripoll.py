@@ -41,9 +41,9 @@ TP_RW_DEGREE = TP_RW_MAX_EDGE + TP_MAX_EDGE_BINS
 TP_RW_DIRECTED = TP_RW_DEGREE + TP_DEGREE_MAX
 TP_RW_SCRATCH = TP_RW_DIRECTED + 8
 TP_RW_CLASS_TRI = TP_RW_SCRATCH + 4
-TP_RESULT_WORDS = TP_RW_SCRATCH + 8
+TP_RESULT_WORDS = TP_RW_SCRATCH + 16
 TP_BW_TRIANGLES, TP_BW_SPREAD, TP_BW_PROBES, TP_BW_HIST, TP_BW_TABLE = 0, 1, 2, 3, 35
-TP_BATCH_SCRATCH_WORDS = 4
+TP_BATCH_SCRATCH_WORDS = 8
 
 OUT_BITS = {"count": TP_OUT_COUNT, "close_hist": TP_OUT_CLOSE_HIST, "label_table": TP_OUT_LABEL_TABLE,
             "spread_count": TP_OUT_SPREAD_COUNT, "open_close": TP_OUT_OPEN_CLOSE,
@@ -141,6 +141,8 @@ SIGNATURES = {
     "tripoll_survey_async": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, _P]),
     "tripoll_survey_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), ctypes.POINTER(tp_survey_result),
                                               _P]),
+    "tripoll_max_edge_counts": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, _P, ctypes.c_uint64,
+                                               ctypes.POINTER(ctypes.c_uint64), _P]),
     "tripoll_enumerate": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64), _P]),
     "tripoll_participation": (ctypes.c_int, [_P, ctypes.POINTER(tp_survey_spec), _P, _P,
                                              ctypes.POINTER(ctypes.c_uint64), _P]),
@@ -238,6 +240,20 @@ def tripoll_survey_noalloc(g: int, spec: tp_survey_spec, stream=None) -> tp_surv
 
 def tripoll_survey_async(g: int, spec: tp_survey_spec, dev_out: int, stream=None) -> None:
     _check(load().tripoll_survey_async(g, ctypes.byref(spec), dev_out, stream))
+
+
+def tripoll_max_edge_counts(g: int, spec: tp_survey_spec, dev_values: int, dev_counts: int, capacity: int,
+                            stream=None) -> int:
+    """Number of distinct values written; on TP_ERR_INVALID for a too small
+    capacity the error's n_values holds the number needed."""
+    n = ctypes.c_uint64(0)
+    st = load().tripoll_max_edge_counts(g, ctypes.byref(spec), dev_values, dev_counts, capacity, ctypes.byref(n),
+                                        stream)
+    if st != TP_OK:
+        err = TripollError(st, load().tripoll_last_error().decode())
+        err.n_values = n.value
+        raise err
+    return n.value
 
 
 def tripoll_enumerate(g: int, dev_records: int, capacity: int, stream=None) -> int:
@@ -521,6 +537,18 @@ def build_graph(n, src, dst, ts=None, vlab=None, tie=TP_TIE_MIX, stream=None, di
 def survey(graph: Graph, stream=None, n_labels=4, **spec_kw) -> dict:
     res = tripoll_survey(graph.handle, make_spec(n_labels=n_labels, **spec_kw), stream)
     return result_dict(res, n_labels)
+
+
+def max_edge_counts(graph: Graph, torch, stream=None, **spec_kw):
+    """Algorithm 3's exact counting set of a graph as (values, counts) numpy
+    arrays, values ascending; device buffers of m entries (enough for any
+    graph) come from torch."""
+    spec = make_spec(**spec_kw)
+    m = max(1, graph.stats()["n_edges"])
+    vals = torch.empty(m, dtype=torch.int32, device="cuda")
+    cnts = torch.empty(m, dtype=torch.int64, device="cuda")
+    n = tripoll_max_edge_counts(graph.handle, spec, vals.data_ptr(), cnts.data_ptr(), m, stream)
+    return (vals[:n].cpu().numpy().view(np.uint32).copy(), cnts[:n].cpu().numpy().view(np.uint64).copy())
 
 
 def export(graph: Graph) -> dict:

@@ -14,8 +14,14 @@ the degree-log table and the directed census (the raw edges read as arcs
 src -> dst), and checksums of the per-vertex and per-edge participation
 counts (see participation_checksums).
 
+    python tests/golden/make_golden.py 2 --max-edge-exact   # golden_maxe_w2_s22.json
     python tests/golden/make_golden.py 4 --batch      # golden_batch_w4.json
     python tests/golden/make_golden.py 5 --served     # golden_served_pool.json
+
+--max-edge-exact stores Algorithm 3's exact counting set (every distinct
+largest edge time over the distinct-label triangles, with its count): its
+size, its total, SHA-256 digests of the ascending values (uint32 little
+endian) and of their counts (uint64 little endian), and every 10000th entry.
 
 --batch surveys every graph of the 20,000-graph batch on its own (one oracle
 process per graph, in a pool) and stores every graph's triangle count, the
@@ -94,6 +100,29 @@ def extended(w, threads):
         "participation": participation_checksums(g.n, vc, pu, pv, ec),
         "oracle_seconds": {"survey": round(t1 - t0, 2), "participation": round(t2 - t1, 2)},
         "host_threads": threads or os.cpu_count(),
+    }
+
+
+def max_edge_exact(w, threads):
+    import hashlib
+    g = w.graph
+    data = synth.generate(g)
+    t0 = time.time()
+    vals, cnts = oracle.max_edge_counts(g.n, data["src"], data["dst"], data["ts"], data["vlab"],
+                                        n_labels=w.n_labels, threads=threads)
+    t1 = time.time()
+    pick = np.arange(0, len(vals), 10000)
+    return {
+        "about": "Oracle exact counting set of Algorithm 3 for the seeded synthetic workload %d (%s); written by "
+                 "tests/golden/make_golden.py --max-edge-exact, which calls only the oracle and the input generator."
+                 % (w.number, w.name),
+        "workload": w.number, "name": w.name, "scale": g.scale, "seed": g.seed, "n_labels": w.n_labels,
+        "n_values": int(len(vals)), "total": int(cnts.sum(dtype=np.uint64)),
+        "sha256_values": hashlib.sha256(vals.astype("<u4").tobytes()).hexdigest(),
+        "sha256_counts": hashlib.sha256(cnts.astype("<u8").tobytes()).hexdigest(),
+        "sample_stride": 10000,
+        "sample": [[int(i), int(vals[i]), int(cnts[i])] for i in pick],
+        "oracle_seconds": round(t1 - t0, 2), "host_threads": threads or os.cpu_count(),
     }
 
 
@@ -217,8 +246,16 @@ def main():
     ap.add_argument("--extended", action="store_true")
     ap.add_argument("--batch", action="store_true")
     ap.add_argument("--served", action="store_true")
+    ap.add_argument("--max-edge-exact", action="store_true")
     a = ap.parse_args()
     w = synth.workload(a.workload, scale=a.scale)
+    if a.max_edge_exact:
+        out = max_edge_exact(w, a.threads)
+        path = os.path.join(HERE, "golden_maxe_w%d_s%d.json" % (w.number, w.graph.scale))
+        with open(path, "w") as f:
+            json.dump(out, f, separators=(",", ":"))
+        print("wrote", path, out["n_values"], out["total"], out["oracle_seconds"])
+        return
     if a.batch or a.served:
         out = batch(w, a.threads) if a.batch else served(w, a.threads)
         path = os.path.join(HERE, "golden_batch_w4.json" if a.batch else "golden_served_pool.json")

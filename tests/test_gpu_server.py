@@ -358,7 +358,7 @@ def test_memory_admission_and_queue_limit(torch_cuda):
     per_req = words * 8 + 136
     with tp.build_graph(n, *dev, stream=torch.cuda.current_stream().cuda_stream) as G:
         gbytes = G.stats()["device_bytes"]
-    graph_bytes = gbytes + 16 * 136 + (4 * words + 1) * 8
+    graph_bytes = gbytes + 16 * 136 + (4 * words + 8) * 8  # 4 result blocks and 8 claim counters
     with tp.Server(max_slots=4, n_labels=L, hbm_budget=graph_bytes + per_req + 64, step_wedges=1 << 10,
                    max_queue=3) as srv:
         gid = srv.add_graph(n, *dev)
