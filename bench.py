@@ -78,6 +78,16 @@ def algorithmic_bytes(st: dict, c: int, meta: bool, hits: int) -> int:
             + 8 * st["class_records"][c] + 16 * st["class_tiles"][c])
 
 
+def batch_work(st: dict, triangles: int, survey_ms: float, meta: bool) -> dict:
+    """Work of a batch survey per target class, and the whole survey's bytes
+    by the work model (all triangles are hits of some class) against its
+    recorded time and the 8 TB/s peak."""
+    b_alg = sum(algorithmic_bytes(st, c, meta, 0) for c in range(4)) + (4 * triangles if meta else 0)
+    return {"class_probes": st["class_probes"], "class_records": st["class_records"],
+            "class_staged": st["class_staged"], "survey_algorithmic_bytes": b_alg,
+            "survey_frac": round(b_alg / (survey_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+
+
 def loaded_bytes(st: dict, c: int, meta: bool) -> int:
     """Bytes the kernel of class c loads by design: every candidate's rank
     and, for metadata surveys, its edge time (a hit rate near one in five
@@ -318,7 +328,8 @@ def batch_bench(args, torch, synth, tp) -> dict:
         "batch": {"build_ms": round(st["build_ms"], 2), "build_phase_ms": [round(x, 2) for x in st["phase_ms"]],
                   "recorded_survey_ms_p50": round(statistics.median(rec_ms), 3),
                   "recorded_survey_triangles_per_s": tri / (statistics.median(rec_ms) * 1e-3),
-                  "tiles": st["class_tiles"], "tune": tune},
+                  "tiles": st["class_tiles"], "tune": tune,
+                  "work": batch_work(st, tri, statistics.median(rec_ms), meta=tuple(outputs) != ("count",))},
         "one_graph_loop": {"sampled_graphs": len(sample), "stride": k,
                            "build_s_est": round(loop_build * k, 3), "survey_s_est": round(loop_survey * k, 3),
                            "total_s_est": round(loop_total_est, 3),

@@ -506,6 +506,12 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     // the table costs one round trip to memory; the workgroup forms, whose
     // registers bound their occupancy, load the keys twice.
     constexpr bool kStage = WAVE && LOG_SLOTS > 0 && (1 << LOG_SLOTS) <= kGroup;
+    // The per-wave tables of the plain survey walk four records at a time,
+    // one per 16-lane quarter of the wave: records of tiny targets are short
+    // (about 13 candidates in the 20,000-graph batch), so a 64-lane step per
+    // record left most lanes idle and spent the step's scalar bookkeeping on
+    // a handful of checks (the kernel was bound by scalar issue).
+    constexpr bool kQuarters = WAVE && LOG_SLOTS > 0 && FORM == kFormSurvey && !ENUM && !MULTI && !PIECES;
     static_assert(!MULTI || (META && !ENUM), "multi-request passes reduce metadata");
     constexpr bool EXT = FORM == kFormExt;
     constexpr bool PART = FORM == kFormPart;
@@ -918,6 +924,131 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                 RecBlock blk_cur = gather(kb0);
                 RecBlock blk_nxt = gather(kb1);
                 KeyBlock key_nxt = load_keys(2);
+                if constexpr (kQuarters && !G) {
+                    // ---- four records at a time: quarter u (lanes 16u ..
+                    // 16u + 15) walks one record, 16 candidates a step, and
+                    // takes the next record once its own is done
+                    const uint32_t sub = lane & 15u;
+                    const uint32_t lead = lane & ~15u;              // the quarter's first lane
+                    const uint64_t lower = (1ull << lead) - 1ull;  // lanes of the quarters below
+                    uint32_t cb = 0;    // block held in blk_cur: records 64 cb .. 64 cb + 63
+                    uint32_t next = 0;  // records handed out
+                    uint64_t qs = 0;    // this quarter's next candidate slot
+                    uint32_t qleft = 0, qtpq = 0, qlp = 0;  // its candidates left, time(p, q), label(p)
+                    uint32_t wave_work = 0, wave_hits = 0;
+                    // quarters without a record take the next ones, in order
+                    auto refill = [&]() {
+                        const uint64_t need = __ballot(sub == 0 && qleft == 0);
+                        if (need == 0 || next >= nw) return;
+                        const uint32_t k = (uint32_t)__popcll(need);
+                        const uint32_t j = next + (uint32_t)__popcll(need & lower);
+                        const uint32_t src = j & (kWave - 1);
+                        uint32_t klo = __shfl((uint32_t)blk_cur.key, (int)src);
+                        uint32_t khi = __shfl((uint32_t)(blk_cur.key >> 32), (int)src);
+                        uint32_t pay = __shfl(blk_cur.pay, (int)src);
+                        uint32_t tpq = __shfl(blk_cur.t_pq, (int)src);
+                        if (((next + k - 1) >> 6) != cb) {
+                            // some of them are in the next block
+                            const uint32_t nlo = __shfl((uint32_t)blk_nxt.key, (int)src);
+                            const uint32_t nhi = __shfl((uint32_t)(blk_nxt.key >> 32), (int)src);
+                            const uint32_t npay = __shfl(blk_nxt.pay, (int)src);
+                            const uint32_t ntpq = __shfl(blk_nxt.t_pq, (int)src);
+                            if ((j >> 6) != cb) {
+                                klo = nlo;
+                                khi = nhi;
+                                pay = npay;
+                                tpq = ntpq;
+                            }
+                        }
+                        if (((need >> lead) & 1ull) && j < nw) {
+                            qs = ((((uint64_t)khi << 32) | klo) & kmask) + 1;
+                            qleft = pay & 0xffffffu;
+                            qtpq = tpq;
+                            qlp = pay >> 24;
+                        }
+                        next = min(next + k, nw);
+                        if (next >= 64u * (cb + 1u) && next < nw) {
+                            blk_cur = blk_nxt;
+                            blk_nxt = gather(key_nxt);
+                            key_nxt = load_keys(cb + 3u);
+                            ++cb;
+                        }
+                    };
+                    struct Step {
+                        uint32_t cand, tpr, tpq, lp;
+                        uint64_t live;
+                    };
+                    // request the next 16 candidates of every quarter's record
+                    auto issue = [&](Step &st) -> bool {
+                        const uint32_t n = min(qleft, 16u);
+                        const bool lv = sub < n;
+                        st.live = __ballot(lv);
+                        if (st.live == 0) return false;
+                        st.cand = 0;
+                        st.tpr = 0;
+                        if (lv) {
+                            st.cand = P.col[qs + sub];
+                            if (META) st.tpr = P.ets[qs + sub];
+                        }
+                        st.tpq = qtpq;
+                        st.lp = qlp;
+                        wave_work += (uint32_t)__popcll(st.live);
+                        qs += n;
+                        qleft -= n;
+                        return true;
+                    };
+                    auto probe = [&](const Step &st) {
+                        const uint32_t r = st.cand;
+                        const uint32_t h0 = hash0(r, log_s), h1 = (1u << log_s) + hash1(r, log_s);
+                        const uint32_t k0 = hkey[h0], k1 = hkey[h1];
+                        bool hit = k0 == r || k1 == r;
+                        uint32_t slot = k0 == r ? h0 : h1;
+                        if (n_stash) {
+                            const uint32_t st0 = 2u << log_s;
+                            for (uint32_t x = 0; x < n_stash; ++x) {
+                                if (hkey[st0 + x] == r) {
+                                    hit = true;
+                                    slot = st0 + x;
+                                }
+                            }
+                        }
+                        const uint64_t m = __ballot(hit) & st.live;
+                        if (!META) {
+                            wave_hits += (uint32_t)__popcll(m);
+                            return;
+                        }
+                        if (m) {
+                            if ((m >> lane) & 1ull) {
+                                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                                ring[(qt + below) & (kRing - 1)] = make_uint4(slot | (st.lp << 22), st.tpr, st.tpq, 0u);
+                            }
+                            qt = __builtin_amdgcn_readfirstlane(qt + (uint32_t)__popcll(m));
+                            if (qt - qh >= (uint32_t)kWave) drain(kWave, gm);
+                        }
+                    };
+                    // two steps in flight: the next step's loads are issued
+                    // before the current one is probed
+                    Step sa, sb;
+                    refill();
+                    if (issue(sa)) {
+                        for (;;) {
+                            refill();
+                            const bool more_b = issue(sb);
+                            probe(sa);
+                            if (!more_b) break;
+                            refill();
+                            const bool more_a = issue(sa);
+                            probe(sb);
+                            if (!more_a) break;
+                        }
+                    }
+                    if (lane == 0) {
+                        probes += wave_work;
+                        my_tri += wave_hits;
+                    }
+                    return;
+                }
                 struct WaveRec {
                     uint64_t k, start;  // slot of p -> q, first candidate
                     uint32_t len, t_pq, l_p, p;

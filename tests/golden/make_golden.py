@@ -11,8 +11,9 @@ tests regenerate the same inputs and compare against these files.
 
 --extended stores the extended outputs instead: Algorithm 3's max-edge bins,
 the degree-log table and the directed census (the raw edges read as arcs
-src -> dst), and checksums of the per-vertex and per-edge participation
-counts (see participation_checksums).
+src -> dst), and digests of the per-vertex and per-edge participation
+counts (see participation_checksums; their SHA-256 digests compare every
+count).
 
     python tests/golden/make_golden.py 2 --max-edge-exact   # golden_maxe_w2_s22.json
     python tests/golden/make_golden.py 4 --batch      # golden_batch_w4.json
@@ -60,19 +61,25 @@ def max_edge_shift(w) -> int:
 
 
 def participation_checksums(n, vcount, lo, hi, ecount) -> dict:
-    """Order-free digests of participation counts: their sums, sums of
-    squares, and sums weighted by the vertex id or by the edge's endpoint
-    ids, all modulo 2^64."""
+    """Digests of participation counts: their sums, sums of squares, and
+    sums weighted by the vertex id or by the edge's endpoint ids, all modulo
+    2^64; and SHA-256 of every count in a canonical order (vertices by id,
+    edges by (lower id, higher id), little-endian uint64), which compares
+    the counts element by element."""
+    import hashlib
     vc = np.asarray(vcount, np.uint64)
     ec = np.asarray(ecount, np.uint64)
     ids = np.arange(len(vc), dtype=np.uint64)
     key = np.asarray(lo, np.uint64) * np.uint64(n) + np.asarray(hi, np.uint64)
+    order = np.argsort(key, kind="stable")
     with np.errstate(over="ignore"):
         return {"vertex_sum": int(vc.sum(dtype=np.uint64)), "vertex_sq": int((vc * vc).sum(dtype=np.uint64)),
                 "vertex_weighted": int((vc * (ids * np.uint64(2654435761) + np.uint64(1))).sum(dtype=np.uint64)),
                 "edge_sum": int(ec.sum(dtype=np.uint64)), "edge_sq": int((ec * ec).sum(dtype=np.uint64)),
                 "edge_weighted": int((ec * (key * np.uint64(2654435761) + np.uint64(1))).sum(dtype=np.uint64)),
-                "edges_with_triangles": int((ec > 0).sum())}
+                "edges_with_triangles": int((ec > 0).sum()),
+                "vertex_sha256": hashlib.sha256(vc.astype("<u8").tobytes()).hexdigest(),
+                "edge_sha256_by_pair": hashlib.sha256(ec[order].astype("<u8").tobytes()).hexdigest()}
 
 
 def extended(w, threads):
