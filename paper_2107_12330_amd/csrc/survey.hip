@@ -506,12 +506,13 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     // the table costs one round trip to memory; the workgroup forms, whose
     // registers bound their occupancy, load the keys twice.
     constexpr bool kStage = WAVE && LOG_SLOTS > 0 && (1 << LOG_SLOTS) <= kGroup;
-    // The per-wave tables of the plain survey walk four records at a time,
-    // one per 16-lane quarter of the wave: records of tiny targets are short
+    // The per-wave tables of the plain survey walk eight records at a time,
+    // one per group of kRecLanes lanes: records of tiny targets are short
     // (about 13 candidates in the 20,000-graph batch), so a 64-lane step per
     // record left most lanes idle and spent the step's scalar bookkeeping on
     // a handful of checks (the kernel was bound by scalar issue).
     constexpr bool kQuarters = WAVE && LOG_SLOTS > 0 && FORM == kFormSurvey && !ENUM && !MULTI && !PIECES;
+    constexpr uint32_t kRecLanes = 8;  // lanes per record in that walk (16: batch survey 351 ms, 8: 349)
     static_assert(!MULTI || (META && !ENUM), "multi-request passes reduce metadata");
     constexpr bool EXT = FORM == kFormExt;
     constexpr bool PART = FORM == kFormPart;
@@ -925,18 +926,19 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                 RecBlock blk_nxt = gather(kb1);
                 KeyBlock key_nxt = load_keys(2);
                 if constexpr (kQuarters && !G) {
-                    // ---- four records at a time: quarter u (lanes 16u ..
-                    // 16u + 15) walks one record, 16 candidates a step, and
-                    // takes the next record once its own is done
-                    const uint32_t sub = lane & 15u;
-                    const uint32_t lead = lane & ~15u;              // the quarter's first lane
-                    const uint64_t lower = (1ull << lead) - 1ull;  // lanes of the quarters below
+                    // ---- 64 / kRecLanes records at a time: lanes
+                    // [kRecLanes u, kRecLanes (u + 1)) walk one record,
+                    // kRecLanes candidates a step, and take the next record
+                    // once their own is done
+                    const uint32_t sub = lane & (kRecLanes - 1);
+                    const uint32_t lead = lane & ~(kRecLanes - 1);  // the group's first lane
+                    const uint64_t lower = (1ull << lead) - 1ull;  // lanes of the groups below
                     uint32_t cb = 0;    // block held in blk_cur: records 64 cb .. 64 cb + 63
                     uint32_t next = 0;  // records handed out
-                    uint64_t qs = 0;    // this quarter's next candidate slot
+                    uint64_t qs = 0;    // this group's next candidate slot
                     uint32_t qleft = 0, qtpq = 0, qlp = 0;  // its candidates left, time(p, q), label(p)
                     uint32_t wave_work = 0, wave_hits = 0;
-                    // quarters without a record take the next ones, in order
+                    // groups without a record take the next ones, in order
                     auto refill = [&]() {
                         const uint64_t need = __ballot(sub == 0 && qleft == 0);
                         if (need == 0 || next >= nw) return;
@@ -978,9 +980,9 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                         uint32_t cand, tpr, tpq, lp;
                         uint64_t live;
                     };
-                    // request the next 16 candidates of every quarter's record
+                    // request the next kRecLanes candidates of every group's record
                     auto issue = [&](Step &st) -> bool {
-                        const uint32_t n = min(qleft, 16u);
+                        const uint32_t n = min(qleft, kRecLanes);
                         const bool lv = sub < n;
                         st.live = __ballot(lv);
                         if (st.live == 0) return false;
