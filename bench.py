@@ -533,6 +533,15 @@ def kind_bench(args, torch, synth, tp) -> dict:
         if args.kind == "ext":
             r = tp.result_dict(tp.tripoll_survey(h, spec, sptr), w.n_labels)
             return r["triangles"], 0, r
+        if args.kind == "maxe":
+            # Algorithm 3's exact counting set: values and counts of at most m entries
+            if "mv" not in bufs:
+                bufs["mv"] = torch.empty(max(st["n_edges"], 1), dtype=torch.int32, device="cuda")
+                bufs["mc"] = torch.empty(max(st["n_edges"], 1), dtype=torch.int64, device="cuda")
+            nv = tp.tripoll_max_edge_counts(h, spec, bufs["mv"].data_ptr(), bufs["mc"].data_ptr(), st["n_edges"],
+                                            sptr)
+            tri = int(bufs["mc"][:nv].sum().item()) if nv else 0
+            return tri, 12 * nv, None
         if args.kind == "participation":
             if "v" not in bufs:
                 bufs["v"] = torch.empty(gs.n, dtype=torch.int64, device="cuda")
@@ -622,10 +631,11 @@ def main():
                     help="workload 4: time the one-graph-per-launch loop on every k-th graph")
     ap.add_argument("--scale", type=int, default=None, help="override the R-MAT scale (same recipe)")
     ap.add_argument("--count-only", action="store_true", help="survey the triangle count only")
-    ap.add_argument("--kind", default="survey", choices=("survey", "ext", "participation", "enum"),
+    ap.add_argument("--kind", default="survey", choices=("survey", "ext", "participation", "enum", "maxe"),
                     help="workloads 1-3: what each step runs after the build: the survey (default), the survey "
                          "with Algorithm 3's max-edge bins and the degree table added, the per-vertex and "
-                         "per-edge participation counts, or the streamed enumeration of every triangle")
+                         "per-edge participation counts, the streamed enumeration of every triangle, or "
+                         "Algorithm 3's exact counting set (maxe)")
     ap.add_argument("--enum-capacity", type=int, default=1 << 28, help="--kind enum: records per chunk")
     ap.add_argument("--enum-tile", type=int, default=256,
                     help="--kind enum: records per tile of the plan the enumeration runs with (small tiles keep "
