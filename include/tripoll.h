@@ -407,7 +407,12 @@ tp_status tripoll_enum_close(tp_enum_stream *e);
  *                  or NULL (then a temporary is allocated)
  *   triangles      host; receives the number of triangles counted; or NULL
  * The sums of both arrays are three times *triangles.
- * Errors: as tripoll_survey; TP_ERR_UNSUPPORTED for a batch.
+ * On a batch handle the counts are those of the union of its graphs (no
+ * triangle spans two graphs): vertex ids are the batch's global ids (graph
+ * g's vertices follow those of graphs 0 .. g-1), the ranks and CSR slots of
+ * graph g are contiguous and follow those of graphs 0 .. g-1, and
+ * *triangles is the batch's total.
+ * Errors: as tripoll_survey.
  */
 tp_status tripoll_participation(const tp_graph *g, const tp_survey_spec *spec, uint64_t *vertex_counts,
                                 uint64_t *edge_counts, uint64_t *triangles, void *stream);

@@ -506,12 +506,13 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     // the table costs one round trip to memory; the workgroup forms, whose
     // registers bound their occupancy, load the keys twice.
     constexpr bool kStage = WAVE && LOG_SLOTS > 0 && (1 << LOG_SLOTS) <= kGroup;
-    // The per-wave tables of the plain survey walk eight records at a time,
+    // The per-wave tables of the plain survey (and of the multi-request
+    // passes, whose hits carry the same items) walk eight records at a time,
     // one per group of kRecLanes lanes: records of tiny targets are short
     // (about 13 candidates in the 20,000-graph batch), so a 64-lane step per
     // record left most lanes idle and spent the step's scalar bookkeeping on
     // a handful of checks (the kernel was bound by scalar issue).
-    constexpr bool kQuarters = WAVE && LOG_SLOTS > 0 && FORM == kFormSurvey && !ENUM && !MULTI && !PIECES;
+    constexpr bool kQuarters = WAVE && LOG_SLOTS > 0 && FORM == kFormSurvey && !ENUM && !PIECES;
     constexpr uint32_t kRecLanes = 8;  // lanes per record in that walk (16: batch survey 351 ms, 8: 349)
     static_assert(!MULTI || (META && !ENUM), "multi-request passes reduce metadata");
     constexpr bool EXT = FORM == kFormExt;
@@ -2123,9 +2124,10 @@ extern "C" tp_status tripoll_participation(const tp_graph *g, const tp_survey_sp
 {
     return guard([&] {
         validate_spec(g, spec);
-        if (g->n_graphs) fail(TP_ERR_UNSUPPORTED, "tripoll_participation: not available for batches");
         hipStream_t s = (hipStream_t)stream;
-        // the filters of the spec apply; its outputs do not
+        // the filters of the spec apply; its outputs do not.  A batch is
+        // counted as the union of its graphs, which no triangle spans: its
+        // vertex ids and CSR slots are those of the union, graph by graph
         tp_survey_spec sp = *spec;
         sp.outputs = TP_OUT_COUNT;
         DArray<unsigned long long> res(TP_RESULT_WORDS, s);

@@ -152,11 +152,44 @@ def test_degenerate_and_null_outputs(torch_cuda):
         assert tp.tripoll_participation(G.handle, tp.make_spec(), 0, 0, stream(T)) == k
 
 
-def test_batch_refused(torch_cuda):
+def test_batch_of_two_triangles(torch_cuda):
+    # two graphs, each one triangle: the union has two, every vertex and
+    # every edge is in exactly one; without output arrays only the total
     T = torch_cuda
     src = np.array([0, 1, 0, 0, 1, 0], np.uint32)
     dst = np.array([1, 2, 2, 1, 2, 2], np.uint32)
     with tp.build_batch([0, 3, 6], [3, 3], src, dst, stream=stream(T)) as B:
-        with pytest.raises(tp.TripollError) as ei:
-            tp.tripoll_participation(B.handle, tp.make_spec(), 0, 0, stream(T))
-        assert ei.value.status == tp.TP_ERR_UNSUPPORTED
+        assert tp.tripoll_participation(B.handle, tp.make_spec(), 0, 0, stream(T)) == 2
+        gv, ge, tri = gpu_participation(T, B)
+        assert tri == 2
+        assert gv.tolist() == [1] * 6
+        assert ge == {(0, 1): 1, (0, 2): 1, (1, 2): 1, (3, 4): 1, (3, 5): 1, (4, 5): 1}
+
+
+def test_batch_participation_per_graph(torch_cuda):
+    """A batch handle counts the union of its graphs: every graph's slice of
+    the vertex and edge counts equals the oracle's counts of that graph
+    alone (ids offset by the graphs before it), with and without filters."""
+    torch = torch_cuda
+    specs = synth.batch_specs(14, master=synth.MASTER_SEED + 771, scale_lo=4, scale_hi=10)
+    d = synth.generate_batch(specs)
+    dev = [torch.from_numpy(d[k]).cuda() for k in ("src", "dst", "ts", "vlab")]
+    e = d["edge_offsets"]
+    voff = np.concatenate([[0], np.cumsum(d["vertex_counts"].astype(np.int64))])
+    with tp.build_batch(d["edge_offsets"], d["vertex_counts"], *dev, stream=stream(torch)) as B:
+        for kw in ({}, {"window": (1 << 17, 1 << 19)}, {"label_mask": {0, 3, 9, 17}}):
+            say("batch participation %s" % kw)
+            gv, ge, tri = gpu_participation(torch, B, n_labels=8, **kw)
+            total = 0
+            for g, sp in enumerate(specs):
+                lo, hi = int(voff[g]), int(voff[g + 1])
+                ref_v, (u, v, t, ref_e) = oracle.participation(
+                    sp.n, d["src"][e[g]:e[g + 1]], d["dst"][e[g]:e[g + 1]], d["ts"][e[g]:e[g + 1]],
+                    d["vlab"][lo:hi], n_labels=8, **kw)
+                assert np.array_equal(gv[lo:hi], ref_v), g
+                want = dict(zip(zip((u.astype(np.int64) + lo).tolist(), (v.astype(np.int64) + lo).tolist()),
+                                ref_e.tolist()))
+                got = {k: c for k, c in ge.items() if lo <= k[0] < hi}
+                assert got == want, g
+                total += int(ref_e.sum())
+            assert 3 * tri == total == int(gv.sum())
