@@ -512,7 +512,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     // (about 13 candidates in the 20,000-graph batch), so a 64-lane step per
     // record left most lanes idle and spent the step's scalar bookkeeping on
     // a handful of checks (the kernel was bound by scalar issue).
-    constexpr bool kQuarters = WAVE && LOG_SLOTS > 0 && FORM == kFormSurvey && !ENUM && !PIECES;
+    constexpr bool kGroupWalk = WAVE && LOG_SLOTS > 0 && FORM == kFormSurvey && !ENUM && !PIECES;
     constexpr uint32_t kRecLanes = 8;  // lanes per record in that walk (16: batch survey 351 ms, 8: 349)
     static_assert(!MULTI || (META && !ENUM), "multi-request passes reduce metadata");
     constexpr bool EXT = FORM == kFormExt;
@@ -926,7 +926,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                 RecBlock blk_cur = gather(kb0);
                 RecBlock blk_nxt = gather(kb1);
                 KeyBlock key_nxt = load_keys(2);
-                if constexpr (kQuarters && !G) {
+                if constexpr (kGroupWalk && !G) {
                     // ---- 64 / kRecLanes records at a time: lanes
                     // [kRecLanes u, kRecLanes (u + 1)) walk one record,
                     // kRecLanes candidates a step, and take the next record
