@@ -512,7 +512,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     // (about 13 candidates in the 20,000-graph batch), so a 64-lane step per
     // record left most lanes idle and spent the step's scalar bookkeeping on
     // a handful of checks (the kernel was bound by scalar issue).
-    constexpr bool kGroupWalk = WAVE && LOG_SLOTS > 0 && FORM == kFormSurvey && !ENUM && !PIECES;
+    constexpr bool kGroupWalk = WAVE && LOG_SLOTS > 0 && (FORM == kFormSurvey || FORM == kFormPart) && !ENUM && !PIECES;
     constexpr uint32_t kRecLanes = 8;  // lanes per record in that walk (16: batch survey 351 ms, 8: 349)
     static_assert(!MULTI || (META && !ENUM), "multi-request passes reduce metadata");
     constexpr bool EXT = FORM == kFormExt;
@@ -938,6 +938,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                     uint32_t next = 0;  // records handed out
                     uint64_t qs = 0;    // this group's next candidate slot
                     uint32_t qleft = 0, qtpq = 0, qlp = 0;  // its candidates left, time(p, q), label(p)
+                    uint64_t qpq = 0;   // slot of p -> q (participation)
                     uint32_t wave_work = 0, wave_hits = 0;
                     // groups without a record take the next ones, in order
                     auto refill = [&]() {
@@ -965,6 +966,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                         }
                         if (((need >> lead) & 1ull) && j < nw) {
                             qs = ((((uint64_t)khi << 32) | klo) & kmask) + 1;
+                            qpq = qs - 1;
                             qleft = pay & 0xffffffu;
                             qtpq = tpq;
                             qlp = pay >> 24;
@@ -980,6 +982,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                     struct Step {
                         uint32_t cand, tpr, tpq, lp;
                         uint64_t live;
+                        uint64_t pr, pq;  // participation: slots of (p, r) and of p -> q
                     };
                     // request the next kRecLanes candidates of every group's record
                     auto issue = [&](Step &st) -> bool {
@@ -995,6 +998,10 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                         }
                         st.tpq = qtpq;
                         st.lp = qlp;
+                        if constexpr (PART) {
+                            st.pr = qs + sub;
+                            st.pq = qpq;
+                        }
                         wave_work += (uint32_t)__popcll(st.live);
                         qs += n;
                         qleft -= n;
@@ -1018,6 +1025,26 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                         const uint64_t m = __ballot(hit) & st.live;
                         if (!META) {
                             wave_hits += (uint32_t)__popcll(m);
+                            return;
+                        }
+                        if constexpr (PART) {
+                            // one count for each edge of every triangle that
+                            // passes the prefilters: (p, r) by its slot, (q, r)
+                            // per table slot, (p, q) once per record group
+                            bool pass = (m >> lane) & 1ull;
+                            if (pass && P.filters) {
+                                Hit h{st.tpq, st.tpr, hts[slot], st.lp, l_q, hlab[slot], 0, 0, 0, 0};
+                                pass = passes_filters<WAVE>(P, h, mask_lds, lut);
+                            }
+                            const uint64_t pm = __ballot(pass);
+                            if (pass) {
+                                atomicAdd(&P.part_edge[st.pr], 1ull);
+                                atomicAdd(&hcnt[slot], 1u);
+                            }
+                            const uint64_t gm_mask = (kRecLanes == 64 ? ~0ull : ((1ull << kRecLanes) - 1)) << lead;
+                            const uint32_t in_group = (uint32_t)__popcll(pm & gm_mask);
+                            if (sub == 0 && in_group) atomicAdd(&P.part_edge[st.pq], (unsigned long long)in_group);
+                            wave_hits += (uint32_t)__popcll(pm);
                             return;
                         }
                         if (m) {
