@@ -235,23 +235,20 @@ __device__ __forceinline__ void add_runs(uint64_t v, bool ok, uint32_t *cnt)
 }
 
 // d(v) counts each unique pair at both ends.  The pairs are sorted by their
-// lower end, so that half is counted by runs; the higher ends are sorted on
-// their own first (k_high_ends, a 32-bit radix sort) and counted the same
-// way, instead of one scattered atomic per pair.
-__global__ void k_degree_low(const uint64_t *ukey, size_t m, PairCode pc, uint32_t *deg)
+// lower end, so that half is counted by runs; the higher ends are written
+// out here (one read of the pairs for both), sorted on their own (a 32-bit
+// radix sort) and counted the same way by k_degree_runs, instead of one
+// scattered atomic per pair.
+__global__ void k_degree_low(const uint64_t *ukey, size_t m, PairCode pc, uint32_t *deg, uint32_t *hi)
 {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t base = blockIdx.x * (size_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < m; base += stride) {
         const size_t i = base + lane_id();
         const bool ok = i < m;
-        add_runs(ok ? pc.hi(ukey[i]) : ~0ull, ok, deg);
+        const uint64_t k = ok ? ukey[i] : 0ull;
+        add_runs(ok ? pc.hi(k) : ~0ull, ok, deg);
+        if (ok) hi[i] = pc.lo(k);
     }
-}
-
-__global__ void k_high_ends(const uint64_t *ukey, size_t m, PairCode pc, uint32_t *hi)
-{
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x)
-        hi[i] = pc.lo(ukey[i]);
 }
 
 __global__ void k_degree_runs(const uint32_t *v, size_t m, uint32_t *deg)
@@ -375,8 +372,10 @@ __global__ void k_rank_graph(const uint32_t *perm, uint32_t n, const uint32_t *v
 // With directions (udir set), the oriented key carries two bits below the
 // pair: bit 0 for the arc source -> target of the oriented edge, bit 1 for
 // the reverse.
-__global__ void k_orient(const uint64_t *ukey, const uint32_t *uts, const uint8_t *udir, size_t m, PairCode pc,
-                         const uint32_t *rank, uint64_t *okey, uint32_t *ots)
+// (The times stay where the dedup wrote them: the orientation sort takes
+// them as its values in place, so that they are not copied here.)
+__global__ void k_orient(const uint64_t *ukey, const uint8_t *udir, size_t m, PairCode pc, const uint32_t *rank,
+                         uint64_t *okey)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
         const uint64_t k = ukey[i];
@@ -391,36 +390,36 @@ __global__ void k_orient(const uint64_t *ukey, const uint32_t *uts, const uint8_
             o = (o << 2) | (a < b ? d : (((d & 1u) << 1) | (d >> 1)));
         }
         okey[i] = o;
-        ots[i] = uts[i];
     }
 }
 
-// d+(s) from the oriented pairs sorted by source: each wave adds one count
-// per run of equal sources among its 64 pairs, to increasing addresses.
-__global__ void k_dplus(const uint64_t *okey, size_t m, PairCode pc, int dshift, uint32_t *dplus)
+
+
+// ------------------------------------------------------------ phase 5
+
+// The oriented pairs sorted by source: position i is CSR slot i.  One read
+// of them writes each slot's target, its label, its source and (directed
+// builds) the two direction bits below the pair into edir, and counts d+(s):
+// each wave adds one count per run of equal sources among its 64 pairs, to
+// increasing addresses.
+__global__ void k_csr(const uint64_t *okey, size_t m, PairCode pc, const uint8_t *rlab, uint32_t *col, uint8_t *tlab,
+                      uint32_t *srow, uint8_t *edir, uint32_t *dplus)
 {
+    const int dshift = edir ? 2 : 0;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t base = blockIdx.x * (size_t)blockDim.x + (threadIdx.x & ~(kWave - 1)); base < m; base += stride) {
         const size_t i = base + lane_id();
         const bool ok = i < m;
-        add_runs(ok ? pc.hi(okey[i] >> dshift) : ~0ull, ok, dplus);
-    }
-}
-
-// ------------------------------------------------------------ phase 5
-
-// edir (directed builds) receives the two direction bits below the pair.
-__global__ void k_csr(const uint64_t *okey, size_t m, PairCode pc, const uint8_t *rlab, uint32_t *col, uint8_t *tlab,
-                      uint32_t *srow, uint8_t *edir)
-{
-    const int dshift = edir ? 2 : 0;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
-        const uint64_t k = okey[i];
-        const uint32_t t = pc.lo(k >> dshift);
-        col[i] = t;
-        tlab[i] = rlab[t];
-        srow[i] = pc.hi(k >> dshift);
-        if (edir) edir[i] = (uint8_t)(k & 3u);
+        const uint64_t k = ok ? okey[i] : 0ull;
+        const uint32_t src = pc.hi(k >> dshift);
+        add_runs(ok ? (uint64_t)src : ~0ull, ok, dplus);
+        if (ok) {
+            const uint32_t t = pc.lo(k >> dshift);
+            col[i] = t;
+            tlab[i] = rlab[t];
+            srow[i] = src;
+            if (edir) edir[i] = (uint8_t)(k & 3u);
+        }
     }
 }
 
@@ -976,7 +975,9 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
 
     const size_t Mcap = std::max<size_t>(M, 1);
     DArray<uint64_t> keyA(Mcap, s), keyB(Mcap, s);
-    DArray<uint32_t> valA(Mcap, s), valB(Mcap, s);
+    // (the value buffers end with room for the row pad: one of them becomes
+    // the graph's edge times)
+    DArray<uint32_t> valA(Mcap + kRowPad, s), valB(Mcap + kRowPad, s);
     BatchMap bm{0, nullptr, nullptr};
     DArray<uint64_t> d_eoff;
     DArray<uint32_t> d_voff;
@@ -1049,12 +1050,10 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
         DArray<uint32_t> deg(n, s);
         TP_HIP(hipMemsetAsync(deg.get(), 0, n * sizeof(uint32_t), s));
         if (m) {
-            k_degree_low<<<grid_for(m, kB), kB, 0, s>>>(ukey, m, pc, deg.get());
-            TP_CHECK_LAUNCH();
             // the sorted (pre-dedup) pairs are no longer needed: their buffer
             // holds the two halves of the higher-end sort
             uint32_t *hiA = reinterpret_cast<uint32_t *>(skey), *hiB = hiA + Mcap;
-            k_high_ends<<<grid_for(m, kB), kB, 0, s>>>(ukey, m, pc, hiA);
+            k_degree_low<<<grid_for(m, kB), kB, 0, s>>>(ukey, m, pc, deg.get(), hiA);
             TP_CHECK_LAUNCH();
             const bool hb2 = radix_sort_u32(hiA, hiB, m, nb, s);
             k_degree_runs<<<grid_for(m, kB), kB, 0, s>>>(hb2 ? hiB : hiA, m, deg.get());
@@ -1113,30 +1112,26 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
     DArray<uint32_t> dplus(n, s);
     TP_HIP(hipMemsetAsync(dplus.get(), 0, n * sizeof(uint32_t), s));
     if (m) {
-        k_orient<<<grid_for(m, kB), kB, 0, s>>>(ukey, uts, udir.get(), m, pc, rank.get(), skey, sval);
+        k_orient<<<grid_for(m, kB), kB, 0, s>>>(ukey, udir.get(), m, pc, rank.get(), skey);
         TP_CHECK_LAUNCH();
     }
     rank.release();
     udir.release();
-    const bool ob = radix_sort_pairs(skey, sval, ukey, uts, m, kb + dbit2, s);
+    // keys from k_orient, values the dedup's times (same order); the
+    // dedup's keys and the free value buffer take the other halves
+    const bool ob = radix_sort_pairs(skey, uts, ukey, sval, m, kb + dbit2, s);
     uint64_t *okey = ob ? ukey : skey;
-    uint32_t *ots = ob ? uts : sval;
-    uint32_t *spare_val = ob ? sval : uts;
-    if (m) {
-        k_dplus<<<grid_for(m, kB), kB, 0, s>>>(okey, m, pc, dbit2, dplus.get());
-        TP_CHECK_LAUNCH();
-    }
+    uint32_t *ots = ob ? sval : uts;
+    uint32_t *spare_val = ob ? uts : sval;
     TP_HIP(hipEventRecord(ev[5], s));
 
     // ---- phase 5: CSR with co-located metadata
-    g->rowptr.reset((size_t)n + 1, s);
-    scan_u32_to_u64(dplus.get(), g->rowptr.get(), n, s);
-    dplus.release();
     // col and ets carry kRowPad zeroed slots past the end: the survey loads a
-    // whole wave of slots from any row start
+    // whole wave of slots from any row start.  The sorted times are ets
+    // itself: their buffer (sized for that pad) moves into the graph.
     g->col.reset(m + kRowPad, s);
     g->tlab.reset(std::max<uint64_t>(m, 1), s);
-    g->ets.reset(m + kRowPad, s);
+    g->ets = std::move(ots == valA.get() ? valA : valB);
     TP_HIP(hipMemsetAsync(g->col.get() + m, 0, kRowPad * sizeof(uint32_t), s));
     TP_HIP(hipMemsetAsync(g->ets.get() + m, 0, kRowPad * sizeof(uint32_t), s));
     if (directed) {
@@ -1147,10 +1142,12 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
     uint32_t *srow = spare_val;
     if (m) {
         k_csr<<<grid_for(m, kB), kB, 0, s>>>(okey, m, pc, g->rlab.get(), g->col.get(), g->tlab.get(), srow,
-                                             g->edir.get());
+                                             g->edir.get(), dplus.get());
         TP_CHECK_LAUNCH();
-        TP_HIP(hipMemcpyAsync(g->ets.get(), ots, m * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     }
+    g->rowptr.reset((size_t)n + 1, s);
+    scan_u32_to_u64(dplus.get(), g->rowptr.get(), n, s);
+    dplus.release();
     k_row_stats<<<grid_for(n, kB), kB, 0, s>>>(g->rowptr.get(), n, c_wedge, c_dpmax);
     TP_CHECK_LAUNCH();
     if (g->dbin_rank.get()) {
@@ -1167,9 +1164,10 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
         if (kbits + nb + 1 > 64) fail(TP_ERR_UNSUPPORTED, "tripoll_build: graph too large for the in-edge keys");
         g->kbits = (uint32_t)kbits;
         uint64_t *ikey = keyA.get(), *ikey_alt = keyB.get();
-        // the payloads go to the buffer that held the sorted times (copied
-        // into ets); srow's buffer is free once the keys are written
-        uint32_t *ival = (srow == valA.get()) ? valB.get() : valA.get(), *ival_alt = srow;
+        // the payloads go to a buffer of their own (the sorted times became
+        // ets); srow's buffer is free once the keys are written
+        DArray<uint32_t> pay(std::max<uint64_t>(m, 1), s);
+        uint32_t *ival = pay.get(), *ival_alt = srow;
         DArray<unsigned long long> kept(1, s);
         TP_HIP(hipMemsetAsync(kept.get(), 0, sizeof(unsigned long long), s));
         DArray<uint64_t> has_out;
@@ -1189,7 +1187,7 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
         }
         // keep the sorted buffers as the index; the others go back to the pool
         DArray<uint64_t> &kk = (ikey == keyA.get()) ? keyA : keyB;
-        DArray<uint32_t> &vv = (ival == valA.get()) ? valA : valB;
+        DArray<uint32_t> &vv = (ival == pay.get()) ? pay : ((ival == valA.get()) ? valA : valB);
         g->inkey = std::move(kk);
         g->inpay = std::move(vv);
     }
