@@ -301,6 +301,42 @@ def test_builder_invariants(torch_cuda):
     assert np.array_equal(ex["rank_label"], g["vlab"][rid])
 
 
+def test_clique_csr_layout(torch_cuda):
+    # A clique on 4200 vertices: every degree is 4199, so the order is the
+    # tie hash and the rank-r row holds 4199 - r targets, rows of every
+    # length up to 4199 in one graph.  The CSR (rows ascending), its times
+    # and labels, and the counts (C(n,3) triangles and wedges, all closed)
+    # must come out exact.
+    n = 4200
+    rng = np.random.default_rng(4200)
+    i, j = np.triu_indices(n, 1)
+    flip = rng.random(len(i)) < 0.5
+    src = np.where(flip, j, i).astype(np.uint32)
+    dst = np.where(flip, i, j).astype(np.uint32)
+    ts = rng.integers(0, 1 << 30, len(i)).astype(np.uint32)
+    vlab = rng.integers(0, 5, n).astype(np.uint8)
+    say("clique rows", n, len(src))
+    with gpu_build(torch_cuda, n, src, dst, ts, vlab) as G:
+        st = G.stats()
+        ex = tp.export(G)
+        r = gpu_survey(torch_cuda, G, outputs=("count",))
+    tri = n * (n - 1) * (n - 2) // 6
+    assert st["dplus_max"] == n - 1 and st["wedges"] == tri and r["triangles"] == tri
+    rowptr, col = ex["rowptr"].astype(np.int64), ex["col"].astype(np.int64)
+    dplus = np.diff(rowptr)
+    assert np.array_equal(dplus, np.arange(n - 1, -1, -1))
+    src_rank = np.repeat(np.arange(n), dplus)
+    same_row = src_rank[1:] == src_rank[:-1]
+    assert (col > src_rank).all() and (col[1:][same_row] > col[:-1][same_row]).all()
+    rid = ex["rank_to_id"].astype(np.int64)
+    a, b = rid[src_rank], rid[col]
+    got = np.minimum(a, b) * n + np.maximum(a, b)
+    order = np.argsort(got)
+    assert np.array_equal(got[order], i.astype(np.int64) * n + j)
+    assert np.array_equal(ex["etime"][order], ts)
+    assert np.array_equal(ex["tlabel"], vlab[rid[col]])
+
+
 def test_enumeration_exactly_once(torch_cuda):
     T = torch_cuda
     w = synth.workload(1, scale=11)
