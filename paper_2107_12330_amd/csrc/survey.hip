@@ -81,6 +81,16 @@ constexpr uint32_t kEmpty = 0xffffffffu;
 constexpr int kFormSurvey = 0;
 constexpr int kFormExt = 1;
 constexpr int kFormPart = 2;
+// The plain metadata survey of the 1024-thread workgroup (large and huge
+// targets, 16 waves per compute unit) keeps twice the ring and reduces its
+// hits two to a lane, 128 at a time, so that the two hits' LDS reads and
+// counter adds overlap (scale-26 large class 327.6 -> 319.5 ms); the
+// other kernels keep kRing and reduce 64 at a time.
+template <bool WAVE, int BLOCK, bool META, bool ENUM, bool MULTI, int FORM>
+constexpr uint32_t ring_size()
+{
+    return (!WAVE && BLOCK == 1024 && META && !ENUM && !MULTI && FORM == kFormSurvey) ? 2 * kRing : kRing;
+}
 constexpr uint32_t kMaxKicks = 64;  // cuckoo displacements before a key goes to the stash
 
 // The two cuckoo hash functions, each onto 2^log_s slots: the low bits of
@@ -187,7 +197,7 @@ __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a -
 // bins: the degree bin of each key (extended form with the degree table)
 __host__ __device__ inline LdsLayout lds_layout(uint32_t slots, bool meta, uint32_t counter_words, int waves,
                                                 uint32_t lut_shift, bool part = false, bool dir = false,
-                                                bool ids = false, bool bins = false)
+                                                bool ids = false, bool bins = false, uint32_t ring = kRing)
 {
     LdsLayout L;
     L.slots = slots;
@@ -206,7 +216,7 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t slots, bool meta, uint3
     L.off_hcnt = o;
     if (part) o += (size_t)slots * 4;
     L.off_ring = o;
-    if (meta && !part) o += (size_t)waves * kRing * 16;
+    if (meta && !part) o += (size_t)waves * ring * 16;
     L.off_cnt = o;
     o += (size_t)counter_words * 8;
     L.off_lut = o;
@@ -521,8 +531,9 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     const uint32_t nc = counter_words<MULTI, FORM>(P);
     const bool kdir = EXT && P.dir_words;  // the directed census
     const bool kbins = EXT && (P.outputs & TP_OUT_DEGREE_TABLE);  // the degree table
+    constexpr uint32_t kRingK = ring_size<WAVE, BLOCK, META, ENUM, MULTI, FORM>();
     const LdsLayout L =
-        lds_layout(kSlots * kGroups, META || ENUM, nc * kGroups, kWaves, P.lut_shift, PART, kdir, ENUM, kbins);
+        lds_layout(kSlots * kGroups, META || ENUM, nc * kGroups, kWaves, P.lut_shift, PART, kdir, ENUM, kbins, kRingK);
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
     const int grp = WAVE ? w : 0;     // this thread's group
@@ -558,7 +569,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     };
 
     const uint32_t lane = lane_id();
-    uint4 *ring = reinterpret_cast<uint4 *>(lds + L.off_ring) + (size_t)w * kRing;
+    uint4 *ring = reinterpret_cast<uint4 *>(lds + L.off_ring) + (size_t)w * kRingK;
     for (uint32_t i = tid; i < nc * kGroups; i += BLOCK) cnt_all[i] = 0;
     if (tid < 13) mask_lds[tid] = P.label_mask[tid];
     if (EXT && (P.outputs & TP_OUT_DEGREE_TABLE))
@@ -645,7 +656,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
         uint32_t e_p = 0, e_r = 0;  // original ids of p and r (enumeration)
         const bool valid = lane < count;
         if (valid) {
-            const uint4 e = ring[(qh + lane) & (kRing - 1)];
+            const uint4 e = ring[(qh + lane) & (kRingK - 1)];
             const uint32_t where = e.x & 0x3fffffu;
             h.t_pq = e.z;
             h.l_p = e.x >> 22;
@@ -717,7 +728,41 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
         my_spread += spread;
         qh = __builtin_amdgcn_readfirstlane(qh + count);
     };
+    // reduce 128 queued hits, two per lane (the doubled ring of the plain
+    // survey): both hits' reads are issued before either is reduced
+    auto drain2 = [&](auto gm) {
+        constexpr bool G = decltype(gm)::value;
+        const uint4 e0 = ring[(qh + lane) & (kRingK - 1)];
+        const uint4 e1 = ring[(qh + kWave + lane) & (kRingK - 1)];
+        const uint32_t w0 = e0.x & 0x3fffffu, w1 = e1.x & 0x3fffffu;
+        Hit h0{e0.z, e0.y, 0, e0.x >> 22, l_q, 0, 0, 0, 0, 0};
+        Hit h1{e1.z, e1.y, 0, e1.x >> 22, l_q, 0, 0, 0, 0, 0};
+        if constexpr (!G) {
+            h0.t_qr = hts[w0];
+            h1.t_qr = hts[w1];
+            h0.l_r = hlab[w0];
+            h1.l_r = hlab[w1];
+        } else {
+            h0.t_qr = P.ets[kq + w0];
+            h1.t_qr = P.ets[kq + w1];
+            h0.l_r = P.tlab[kq + w0];
+            h1.l_r = P.tlab[kq + w1];
+        }
+        uint32_t spread = 0;
+        uint32_t tri = reduce_hit<EXT, WAVE>(P, h0, cnt, mask_lds, lut, spread);
+        tri += reduce_hit<EXT, WAVE>(P, h1, cnt, mask_lds, lut, spread);
+        my_tri += tri;
+        my_spread += spread;
+        qh = __builtin_amdgcn_readfirstlane(qh + 2 * kWave);
+    };
     auto drain_queued = [&]() {
+        if constexpr (kRingK > kRing) {
+            // the doubled ring may hold more than a wave's 64
+            while (qt - qh > (uint32_t)kWave) {
+                if (gmode) drain(kWave, std::true_type{});
+                else drain(kWave, std::false_type{});
+            }
+        }
         if (qt == qh) return;
         if (gmode) drain(qt - qh, std::true_type{});
         else drain(qt - qh, std::false_type{});
@@ -1051,7 +1096,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                             if ((m >> lane) & 1ull) {
                                 const uint32_t below = __builtin_amdgcn_mbcnt_hi(
                                     (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                                ring[(qt + below) & (kRing - 1)] = make_uint4(slot | (st.lp << 22), st.tpr, st.tpq, 0u);
+                                ring[(qt + below) & (kRingK - 1)] = make_uint4(slot | (st.lp << 22), st.tpr, st.tpq, 0u);
                             }
                             qt = __builtin_amdgcn_readfirstlane(qt + (uint32_t)__popcll(m));
                             if (qt - qh >= (uint32_t)kWave) drain(kWave, gm);
@@ -1282,13 +1327,17 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                                     // position among the wave's hits: hits in the lanes below
                                     const uint32_t below = __builtin_amdgcn_mbcnt_hi(
                                         (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                                    ring[(qt + below) & (kRing - 1)] =
+                                    ring[(qt + below) & (kRingK - 1)] =
                                         make_uint4(slot | (chs[c].l_p << 22), tpr[c][sr], chs[c].t_pq,
                                                    EXT && kdir ? chs[c].p | ((dpr[c][sr] & 3u) << 10) : chs[c].p);
                                 }
                                 // the ring cursors are wave-uniform: keep them in scalar registers
                                 qt = __builtin_amdgcn_readfirstlane(qt + (uint32_t)__popcll(m));
-                                if (qt - qh >= (uint32_t)kWave) drain(kWave, gm);
+                                if constexpr (kRingK > kRing) {
+                                    if (qt - qh >= 2u * kWave) drain2(gm);
+                                } else {
+                                    if (qt - qh >= (uint32_t)kWave) drain(kWave, gm);
+                                }
                             }
                         }
                     }
@@ -1428,7 +1477,8 @@ size_t lds_need(const SurveyParams &P)
     const uint32_t nc = counter_words<MULTI, FORM>(P);
     return lds_layout(slots * groups, META || ENUM, nc * groups, BLOCK / kWave, P.lut_shift, FORM == kFormPart,
                       FORM == kFormExt && P.dir_words, ENUM,
-                      FORM == kFormExt && (P.outputs & TP_OUT_DEGREE_TABLE))
+                      FORM == kFormExt && (P.outputs & TP_OUT_DEGREE_TABLE),
+                      ring_size<WAVE, BLOCK, META, ENUM, MULTI, FORM>())
         .total;
 }
 
@@ -1441,7 +1491,8 @@ void launch_class(const SurveyParams &P, hipStream_t s, int device)
     const uint32_t nc = counter_words<MULTI, FORM>(P);
     const LdsLayout L = lds_layout(slots * groups, META || ENUM, nc * groups, BLOCK / kWave, P.lut_shift,
                                    FORM == kFormPart, FORM == kFormExt && P.dir_words, ENUM,
-                                   FORM == kFormExt && (P.outputs & TP_OUT_DEGREE_TABLE));
+                                   FORM == kFormExt && (P.outputs & TP_OUT_DEGREE_TABLE),
+                                   ring_size<WAVE, BLOCK, META, ENUM, MULTI, FORM>());
     if (L.total > kLdsLimit)
         fail(TP_ERR_UNSUPPORTED, "tripoll_survey: the requested outputs need more LDS than a workgroup may hold");
     auto kern = survey_kernel<LOG_SLOTS, BLOCK, WAVE, META, ENUM, MULTI, FORM, PIECES>;
