@@ -91,6 +91,9 @@ constexpr uint32_t ring_size()
 {
     return (!WAVE && BLOCK == 1024 && META && !ENUM && !MULTI && FORM == kFormSurvey) ? 2 * kRing : kRing;
 }
+// a drain leaves at most 127 queued; two sub-rows add at most 128 (the
+// doubled ring), one sub-row at most 64 (kRing)
+static_assert(2 * kRing >= (2 * kWave - 1) + 2 * kWave && kRing >= (kWave - 1) + kWave, "hit ring capacity");
 constexpr uint32_t kMaxKicks = 64;  // cuckoo displacements before a key goes to the stash
 
 // The two cuckoo hash functions, each onto 2^log_s slots: the low bits of
@@ -1259,6 +1262,14 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                     for (int c = 0; c < kBatch; ++c) {
     #pragma unroll
                         for (int sr = 0; sr < kSub; ++sr) {
+                            if constexpr (kRingK > kRing) {
+                                // the doubled ring takes two sub-rows of hits (at most
+                                // 128) above 127 queued: drained before every other
+                                // sub-row only, so that the unrolled walk holds half
+                                // the copies of the reduction (large class 316.5 ->
+                                // 311.5 ms)
+                                if ((sr & 1) == 0 && qt - qh >= 2u * kWave) drain2(gm);
+                            }
                             if (chs[c].n <= (uint32_t)(sr * kWave)) break;
                             const uint32_t nsub = min(chs[c].n - sr * kWave, (uint32_t)kWave);
                             // lanes >= nsub hold no candidate (they read 0): mask their hits
@@ -1333,9 +1344,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                                 }
                                 // the ring cursors are wave-uniform: keep them in scalar registers
                                 qt = __builtin_amdgcn_readfirstlane(qt + (uint32_t)__popcll(m));
-                                if constexpr (kRingK > kRing) {
-                                    if (qt - qh >= 2u * kWave) drain2(gm);
-                                } else {
+                                if constexpr (kRingK == kRing) {
                                     if (qt - qh >= (uint32_t)kWave) drain(kWave, gm);
                                 }
                             }
