@@ -46,13 +46,18 @@ def resolve_variant(c: int, v: int) -> int:
 def kernel_key(c: int, v: int, meta: bool, form: int = 0) -> str:
     """Template arguments of the survey kernel that serves class c under
     variant v, as in the rocprofv3 kernel name (spaces removed).  form: 0 the
-    plain survey, 1 the extended reductions, 2 participation; the last
-    argument marks the huge class's kernels, which walk pieces of Adj+(q)."""
+    plain survey, 1 the extended reductions, 2 participation; the next
+    argument marks the huge class's kernels, which walk pieces of Adj+(q);
+    the last one the doubled hit ring, which the 1024-thread workgroups of
+    the plain metadata survey take wherever their counters leave the LDS for
+    it (every output set of these workloads)."""
     v = resolve_variant(c, v)
     log_slots, block, wave = {1: (6, 256, "true"), 2: (12, 1024, "false") if c >= 2 else (10, 256, "false"),
                               3: (0, 256, "false"), 4: (0, 256, "true")}[v]
-    return "survey_kernel<%d,%d,%s,%s,false,false,%d,%s>" % (log_slots, block, wave, "true" if meta else "false", form,
-                                                            "true" if c == 3 else "false")
+    wide = meta and form == 0 and wave == "false" and block == 1024
+    return "survey_kernel<%d,%d,%s,%s,false,false,%d,%s,%s>" % (
+        log_slots, block, wave, "true" if meta else "false", form, "true" if c == 3 else "false",
+        "true" if wide else "false")
 
 
 def log(*a):

@@ -84,12 +84,14 @@ constexpr int kFormPart = 2;
 // The plain metadata survey of the 1024-thread workgroup (large and huge
 // targets, 16 waves per compute unit) keeps twice the ring and reduces its
 // hits two to a lane, 128 at a time, so that the two hits' LDS reads and
-// counter adds overlap (scale-26 large class 327.6 -> 319.5 ms); the
-// other kernels keep kRing and reduce 64 at a time.
-template <bool WAVE, int BLOCK, bool META, bool ENUM, bool MULTI, int FORM>
+// counter adds overlap (scale-26 large class 327.6 -> 319.5 ms), wherever
+// the outputs' counters leave LDS for it (WIDE; not with the open/close
+// histogram and a label table over many labels); the other kernels keep
+// kRing and reduce 64 at a time.
+template <bool WAVE, int BLOCK, bool META, bool ENUM, bool MULTI, int FORM, bool WIDE = true>
 constexpr uint32_t ring_size()
 {
-    return (!WAVE && BLOCK == 1024 && META && !ENUM && !MULTI && FORM == kFormSurvey) ? 2 * kRing : kRing;
+    return (WIDE && !WAVE && BLOCK == 1024 && META && !ENUM && !MULTI && FORM == kFormSurvey) ? 2 * kRing : kRing;
 }
 // a drain leaves at most 127 queued; two sub-rows add at most 128 (the
 // doubled ring), one sub-row at most 64 (kRing)
@@ -501,7 +503,7 @@ struct RecBlock {
 // The per-wave form of the plain survey is held to 64 registers, 8 waves
 // per SIMD: its short tiles wait on chains of dependent loads, and more
 // waves hide them (20,000-graph batch survey 539.6 -> 515.3 ms).
-template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM, bool PIECES>
+template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM, bool PIECES, bool WIDE>
 __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 : 1) void survey_kernel(SurveyParams P)
 {
     constexpr int kSub = Depth<WAVE>::kSub;
@@ -534,7 +536,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
     const uint32_t nc = counter_words<MULTI, FORM>(P);
     const bool kdir = EXT && P.dir_words;  // the directed census
     const bool kbins = EXT && (P.outputs & TP_OUT_DEGREE_TABLE);  // the degree table
-    constexpr uint32_t kRingK = ring_size<WAVE, BLOCK, META, ENUM, MULTI, FORM>();
+    constexpr uint32_t kRingK = ring_size<WAVE, BLOCK, META, ENUM, MULTI, FORM, WIDE>();
     const LdsLayout L =
         lds_layout(kSlots * kGroups, META || ENUM, nc * kGroups, kWaves, P.lut_shift, PART, kdir, ENUM, kbins, kRingK);
     const int tid = threadIdx.x;
@@ -1487,24 +1489,15 @@ size_t lds_need(const SurveyParams &P)
     return lds_layout(slots * groups, META || ENUM, nc * groups, BLOCK / kWave, P.lut_shift, FORM == kFormPart,
                       FORM == kFormExt && P.dir_words, ENUM,
                       FORM == kFormExt && (P.outputs & TP_OUT_DEGREE_TABLE),
-                      ring_size<WAVE, BLOCK, META, ENUM, MULTI, FORM>())
+                      ring_size<WAVE, BLOCK, META, ENUM, MULTI, FORM, false>())
         .total;
 }
 
-template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM, bool PIECES = false>
-void launch_class(const SurveyParams &P, hipStream_t s, int device)
+template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM, bool PIECES, bool WIDE>
+void launch_kernel(const SurveyParams &P, const LdsLayout &L, hipStream_t s, int device)
 {
-    if (P.n_tiles == 0) return;
     constexpr uint32_t groups = WAVE ? BLOCK / kWave : 1;
-    const uint32_t slots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
-    const uint32_t nc = counter_words<MULTI, FORM>(P);
-    const LdsLayout L = lds_layout(slots * groups, META || ENUM, nc * groups, BLOCK / kWave, P.lut_shift,
-                                   FORM == kFormPart, FORM == kFormExt && P.dir_words, ENUM,
-                                   FORM == kFormExt && (P.outputs & TP_OUT_DEGREE_TABLE),
-                                   ring_size<WAVE, BLOCK, META, ENUM, MULTI, FORM>());
-    if (L.total > kLdsLimit)
-        fail(TP_ERR_UNSUPPORTED, "tripoll_survey: the requested outputs need more LDS than a workgroup may hold");
-    auto kern = survey_kernel<LOG_SLOTS, BLOCK, WAVE, META, ENUM, MULTI, FORM, PIECES>;
+    auto kern = survey_kernel<LOG_SLOTS, BLOCK, WAVE, META, ENUM, MULTI, FORM, PIECES, WIDE>;
     // attribute and occupancy queries run once per kernel, device and LDS
     // size, so that a survey recorded into a HIP graph issues launches only
     static std::mutex mu;
@@ -1542,6 +1535,36 @@ void launch_class(const SurveyParams &P, hipStream_t s, int device)
     TP_CHECK_LAUNCH();
     kern<<<(unsigned)grid, BLOCK, L.total, s>>>(Q);
     TP_CHECK_LAUNCH();
+}
+
+
+// Launch a class kernel: with the doubled hit ring where the outputs'
+// counters leave LDS for it, else with the plain ring (whose size every
+// LDS decision above assumes).
+template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM, bool PIECES = false>
+void launch_class(const SurveyParams &P, hipStream_t s, int device)
+{
+    if (P.n_tiles == 0) return;
+    constexpr uint32_t groups = WAVE ? BLOCK / kWave : 1;
+    const uint32_t slots = LOG_SLOTS > 0 ? (2u << LOG_SLOTS) + kStash : 0u;
+    const uint32_t nc = counter_words<MULTI, FORM>(P);
+    auto layout = [&](uint32_t ring) {
+        return lds_layout(slots * groups, META || ENUM, nc * groups, BLOCK / kWave, P.lut_shift, FORM == kFormPart,
+                          FORM == kFormExt && P.dir_words, ENUM, FORM == kFormExt && (P.outputs & TP_OUT_DEGREE_TABLE),
+                          ring);
+    };
+    constexpr uint32_t wide = ring_size<WAVE, BLOCK, META, ENUM, MULTI, FORM, true>();
+    if constexpr (wide > kRing) {
+        const LdsLayout L = layout(wide);
+        if (L.total <= kLdsLimit) {
+            launch_kernel<LOG_SLOTS, BLOCK, WAVE, META, ENUM, MULTI, FORM, PIECES, true>(P, L, s, device);
+            return;
+        }
+    }
+    const LdsLayout L = layout(kRing);
+    if (L.total > kLdsLimit)
+        fail(TP_ERR_UNSUPPORTED, "tripoll_survey: the requested outputs need more LDS than a workgroup may hold");
+    launch_kernel<LOG_SLOTS, BLOCK, WAVE, META, ENUM, MULTI, FORM, PIECES, false>(P, L, s, device);
 }
 
 // The search variant class c runs with under `strategy`.

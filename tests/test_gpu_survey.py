@@ -123,6 +123,45 @@ def test_huge_target_class(torch_cuda):
         assert int(got["label_table"][i]) == e
 
 
+def test_doubled_and_plain_hit_rings_agree(torch_cuda):
+    # K_1200 with 16 label values: small-class and large-class targets.  With
+    # the count and closure histogram, the large class's 1024-thread kernel
+    # queues its hits in the doubled ring.  With every output over 16 labels
+    # its counters (an 816-entry label table, the 1024-word open/close
+    # histogram, an 8 KB label lookup) leave too little LDS for that ring, so
+    # it takes the plain one.  Both surveys must agree, and every output must
+    # match its closed form.
+    n = 1200
+    i, j = np.triu_indices(n, 1)
+    rng = np.random.default_rng(1200)
+    ts = rng.integers(0, 1 << 24, len(i)).astype(np.uint32)
+    vlab = rng.integers(0, 16, n).astype(np.uint8)
+    say("K_1200, 16 labels")
+    with gpu_build(torch_cuda, n, i.astype(np.uint32), j.astype(np.uint32), ts, vlab) as G:
+        st = G.stats()
+        assert st["dplus_max"] == n - 1 and st["class_tiles"][1] > 0 and st["class_tiles"][2] > 0
+        a = gpu_survey(torch_cuda, G, outputs=("count", "close_hist"), n_labels=16)
+        b = gpu_survey(torch_cuda, G, outputs=ALL_OUT, n_labels=16, spread_lt=1 << 30)
+    tri = math.comb(n, 3)
+    assert a["triangles"] == b["triangles"] == tri
+    assert np.array_equal(a["close_hist"], b["close_hist"]) and int(a["close_hist"].sum()) == tri
+    assert int(np.asarray(b["open_close"]).sum()) == tri
+    # spread below 2^30 > every time difference: every triangle
+    assert b["spread_count"] == tri
+    sizes = np.bincount(vlab, minlength=16)
+    from tests.brute import colex_multisets
+    for (x, y, z), k in colex_multisets(16).items():
+        if x == y == z:
+            e = math.comb(int(sizes[x]), 3)
+        elif x == y:
+            e = math.comb(int(sizes[x]), 2) * int(sizes[z])
+        elif y == z:
+            e = int(sizes[x]) * math.comb(int(sizes[y]), 2)
+        else:
+            e = int(sizes[x]) * int(sizes[y]) * int(sizes[z])
+        assert int(b["label_table"][k]) == e
+
+
 def test_huge_targets_random_dense(torch_cuda):
     # the huge targets' out-lists are surveyed in pieces and every record's
     # candidates are cut at the pieces' rank bounds, at irregular places:
