@@ -236,9 +236,12 @@ __host__ __device__ inline LdsLayout lds_layout(uint32_t slots, bool meta, uint3
 // are held in P.copies interleaved copies (bin b, copy c at b * copies + c;
 // lane l adds to copy l % copies), so that the lanes of a wave that hit the
 // same bin spread over several LDS addresses (4 copies: scale-26 survey
-// 485 -> 444 ms).  The host takes 4, 2 or 1 copies, whichever fits LDS.  A
-// multi-request pass holds one batch-layout block per request slot.
+// 485 -> 444 ms).  The host takes 4, 2 or 1 copies, whichever fits LDS, and
+// 8 for the 1024-thread kernels where 8 fit beside the doubled hit ring
+// (scale-26 large class 311.4 -> 308.8 ms).  A multi-request pass holds one
+// batch-layout block per request slot.
 constexpr uint32_t kMaxCopies = 4;
+constexpr uint32_t kMaxCopiesLarge = 8;
 
 struct CounterBase {
     uint32_t table, oc, maxe, deg, dir, total;
@@ -1480,7 +1483,7 @@ uint32_t table_size(uint32_t L) { return (L + 2) * (L + 1) * L / 6; }
 // the kernel's static arrays.
 constexpr size_t kLdsLimit = 160 * 1024 - 4096;
 
-template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM>
+template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM, bool WIDE = false>
 size_t lds_need(const SurveyParams &P)
 {
     constexpr uint32_t groups = WAVE ? BLOCK / kWave : 1;
@@ -1489,7 +1492,7 @@ size_t lds_need(const SurveyParams &P)
     return lds_layout(slots * groups, META || ENUM, nc * groups, BLOCK / kWave, P.lut_shift, FORM == kFormPart,
                       FORM == kFormExt && P.dir_words, ENUM,
                       FORM == kFormExt && (P.outputs & TP_OUT_DEGREE_TABLE),
-                      ring_size<WAVE, BLOCK, META, ENUM, MULTI, FORM, false>())
+                      ring_size<WAVE, BLOCK, META, ENUM, MULTI, FORM, WIDE>())
         .total;
 }
 
@@ -1537,10 +1540,9 @@ void launch_kernel(const SurveyParams &P, const LdsLayout &L, hipStream_t s, int
     TP_CHECK_LAUNCH();
 }
 
-
 // Launch a class kernel: with the doubled hit ring where the outputs'
-// counters leave LDS for it, else with the plain ring (whose size every
-// LDS decision above assumes).
+// counters leave LDS for it, else with the plain ring, whose size every LDS
+// decision before the launch assumes (counter copies, which kernels fit).
 template <int LOG_SLOTS, int BLOCK, bool WAVE, bool META, bool ENUM, bool MULTI, int FORM, bool PIECES = false>
 void launch_class(const SurveyParams &P, hipStream_t s, int device)
 {
@@ -1594,7 +1596,13 @@ void launch_variant(int c, uint32_t v, const SurveyParams &P0, hipStream_t s, in
                                    : v == TP_VAR_GROUP_TABLE ? (c >= kClassLarge ? kLargeLogSlots : kSmallLogSlots)
                                                              : 0;
         const bool wave = v == TP_VAR_WAVE_TABLE || v == TP_VAR_WAVE_SEARCH;
-        for (P.copies = kMaxCopies; P.copies > 1; P.copies /= 2) {
+        uint32_t top = kMaxCopies;
+        if (log_slots == kLargeLogSlots) {
+            P.copies = kMaxCopiesLarge;
+            if (lds_need<kLargeLogSlots, kLargeBlock, false, META, ENUM, MULTI, FORM, true>(P) <= kLdsLimit)
+                top = kMaxCopiesLarge;
+        }
+        for (P.copies = top; P.copies > 1; P.copies /= 2) {
             size_t need = 0;
             if (log_slots == kTinyLogSlots && wave) need = lds_need<kTinyLogSlots, kSmallBlock, true, META, ENUM, MULTI, FORM>(P);
             else if (log_slots == kLargeLogSlots) need = lds_need<kLargeLogSlots, kLargeBlock, false, META, ENUM, MULTI, FORM>(P);
