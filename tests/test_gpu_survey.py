@@ -105,8 +105,16 @@ def test_huge_target_class(torch_cuda):
         st = G.stats()
         assert st["dplus_max"] == n - 1
         got = gpu_survey(torch_cuda, G, outputs=("count", "close_hist", "label_table"), n_labels=4)
+        # every output over 16 labels: the counters leave too little LDS for
+        # the doubled hit ring, so the pieces kernel takes the plain one
+        wide = gpu_survey(torch_cuda, G, outputs=ALL_OUT, n_labels=16, spread_lt=1 << 30)
     assert got["triangles"] == math.comb(n, 3)
     assert int(got["close_hist"].sum()) == math.comb(n, 3)
+    assert wide["triangles"] == got["triangles"] and np.array_equal(wide["close_hist"], got["close_hist"])
+    assert int(np.asarray(wide["open_close"]).sum()) == math.comb(n, 3) and wide["spread_count"] == math.comb(n, 3)
+    # the colex index of a label multiset does not depend on the label count
+    assert np.array_equal(np.asarray(wide["label_table"])[:20], np.asarray(got["label_table"])[:20])
+    assert not np.asarray(wide["label_table"])[20:].any()
     # label table of K_n from class sizes
     sizes = np.bincount(vlab, minlength=4)
     from tests.brute import colex_multisets
