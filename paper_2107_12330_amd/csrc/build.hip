@@ -176,9 +176,21 @@ __global__ __launch_bounds__(kB) void k_dedup_count(const uint64_t *keys, size_t
     }
 }
 
+// Lane l's 64-bit value, in a scalar register (the builtin returns a signed
+// 32-bit int: each half is widened as unsigned).
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l)
+{
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // One pair per run with its earliest time; with direction bits (dbit = 1)
 // also the directions of its copies (bit 0: lower -> higher id, bit 1: the
-// reverse) into udir.
+// reverse) into udir.  The wave keeps its 16 rounds of keys in registers
+// from the count of its heads: the neighbours a head compares with come
+// from the lanes beside it (or the next round's first lane), and only a run
+// of copies is walked in memory.
 __global__ __launch_bounds__(kB) void k_dedup_write(const uint64_t *keys, const uint32_t *vals, size_t n, int dbit,
                                                     const uint64_t *tile_off, uint64_t *ukey, uint32_t *uts,
                                                     uint8_t *udir)
@@ -187,24 +199,50 @@ __global__ __launch_bounds__(kB) void k_dedup_write(const uint64_t *keys, const 
     const int w = threadIdx.x / kWave;
     const unsigned lane = lane_id();
     const size_t wbase = blockIdx.x * kCompTile + (size_t)w * kCompWave;
-    const uint64_t c = wave_heads(keys, n, wbase, dbit);
+    uint64_t kk[kCompItems];
+    uint64_t hm[kCompItems];  // each round's heads
+    uint64_t c = 0;
+#pragma unroll
+    for (int j = 0; j < kCompItems; ++j) {
+        const size_t i = wbase + (size_t)j * kWave + lane;
+        kk[j] = i < n ? keys[i] : 0ull;
+        uint64_t prev = __shfl_up(kk[j], 1, kWave);
+        if (j > 0) {
+            const uint64_t last = readlane64(kk[j - 1], kWave - 1);
+            if (lane == 0) prev = last;
+        } else if (lane == 0 && i < n) {
+            prev = i ? keys[i - 1] : ~kk[j];
+        }
+        hm[j] = __ballot(i < n && (prev >> dbit) != (kk[j] >> dbit));
+        c += (uint64_t)__popcll(hm[j]);
+    }
     if (lane == 0) tmp[w] = c;
     __syncthreads();
     uint64_t pos = tile_off[blockIdx.x];
     for (int x = 0; x < w; ++x) pos += tmp[x];
+#pragma unroll
     for (int j = 0; j < kCompItems; ++j) {
         const size_t i = wbase + (size_t)j * kWave + lane;
-        const uint64_t k = i < n ? keys[i] : 0ull;
-        const bool head = run_head(keys, i, n, k, dbit);
-        const uint64_t b = __ballot(head);
-        if (head) {
+        const uint64_t k = kk[j];
+        // the key after this one: the next lane's, the next round's first, or memory
+        uint64_t next = __shfl_down(k, 1, kWave);
+        if (j + 1 < kCompItems) {
+            const uint64_t first = readlane64(kk[j + 1], 0);
+            if (lane == kWave - 1) next = first;
+        } else if (lane == kWave - 1) {
+            next = i + 1 < n ? keys[i + 1] : 0ull;
+        }
+        const uint64_t b = hm[j];
+        if ((b >> lane) & 1ull) {
             // the earliest time of the run, and its directions
             const uint64_t pk = k >> dbit;
             uint32_t t = vals[i];
             uint32_t d = 1u << (k & (uint64_t)dbit);
-            for (size_t x = i + 1; x < n && (keys[x] >> dbit) == pk; ++x) {
-                t = min(t, vals[x]);
-                d |= 1u << (keys[x] & (uint64_t)dbit);
+            if (i + 1 < n && (next >> dbit) == pk) {
+                for (size_t x = i + 1; x < n && (keys[x] >> dbit) == pk; ++x) {
+                    t = min(t, vals[x]);
+                    d |= 1u << (keys[x] & (uint64_t)dbit);
+                }
             }
             const uint64_t at = pos + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
             ukey[at] = pk;

@@ -712,8 +712,9 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                         base = P.enum_tile_base[cur_tile] - P.enum_chunk_base + atomicAdd(&P.enum_tile_cursor[cur_tile], k);
                     else base = atomicAdd(P.enum_count, (unsigned long long)k);
                 }
-                base = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
-                       __builtin_amdgcn_readfirstlane((uint32_t)base);
+                // (the builtin returns a signed int: each half is widened as unsigned)
+                base = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)base);
                 const unsigned long long at =
                     base + __builtin_amdgcn_mbcnt_hi((uint32_t)(vm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)vm, 0u));
                 if (pass && !P.enum_tile_count && at < P.enum_cap) {
@@ -1179,7 +1180,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
                     if (ENUM) {
                         // the pivot's original id: its rank came with the
                         // record's other gathers
-                        r.p = sload(P.perm + __builtin_amdgcn_readlane(blk_cur.p, l));
+                        r.p = sload(P.perm + (uint32_t)__builtin_amdgcn_readlane(blk_cur.p, l));
                     }
                     return r;
                 };
