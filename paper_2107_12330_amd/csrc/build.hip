@@ -731,29 +731,17 @@ __global__ void k_piece_cut(const uint64_t *inkey, const uint32_t *inpay, int kb
     }
 }
 
-__global__ void k_work_stats(const unsigned long long *work, uint32_t n, unsigned long long *sum,
-                             unsigned long long *nonzero)
-{
-    unsigned long long w = 0, c = 0;
-    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
-        w += work[q];
-        c += work[q] ? 1 : 0;
-    }
-    w = wave_sum(w);
-    c = wave_sum(c);
-    if (lane_id() == 0) {
-        if (w) atomicAdd(sum, w);
-        if (c) atomicAdd(nonzero, c);
-    }
-}
-
-// Per-class totals of the plan: records, staged out-list entries, probes.
+// Per-class totals of the plan: records, staged out-list entries, probes;
+// then the probes of all targets and the number of targets with any.
 __global__ void k_plan_stats(const uint64_t *cptr, const unsigned long long *work, const uint64_t *rowptr,
                              const uint64_t *fbase, const uint64_t *pos, const uint32_t *tcnt, uint32_t n,
-                             TileCaps caps, unsigned long long *out /* [3][classes] */)
+                             TileCaps caps, unsigned long long *out /* [3][classes], probes, targets */)
 {
-    unsigned long long rec[kNumClasses] = {}, stg[kNumClasses] = {}, prb[kNumClasses] = {};
+    unsigned long long rec[kNumClasses] = {}, stg[kNumClasses] = {}, prb[kNumClasses] = {}, wall = 0, wnz = 0;
     for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+        const unsigned long long wq = work[q];
+        wall += wq;
+        wnz += wq ? 1 : 0;
         const uint64_t dq = rowptr[q + 1] - rowptr[q];
         const int c = class_of(dq);
         const uint32_t t = tcnt[(size_t)c * n + q];
@@ -779,7 +767,7 @@ __global__ void k_plan_stats(const uint64_t *cptr, const unsigned long long *wor
             if (i == c) {
                 rec[i] += nrec;
                 stg[i] += staged;
-                prb[i] += work[q];
+                prb[i] += wq;
             }
         }
     }
@@ -791,6 +779,12 @@ __global__ void k_plan_stats(const uint64_t *cptr, const unsigned long long *wor
             if (b) atomicAdd(&out[1 * kNumClasses + i], b);
             if (c) atomicAdd(&out[2 * kNumClasses + i], c);
         }
+    }
+    wall = wave_sum(wall);
+    wnz = wave_sum(wnz);
+    if (lane_id() == 0) {
+        if (wall) atomicAdd(&out[3 * kNumClasses], wall);
+        if (wnz) atomicAdd(&out[3 * kNumClasses + 1], wnz);
     }
 }
 
@@ -919,8 +913,6 @@ void plan_graph(tp_graph *g, const PlanCfg &cfg, hipStream_t s)
     TP_HIP(hipMemsetAsync(pst.get(), 0, (kStat + 2) * sizeof(unsigned long long), s));
     k_plan_stats<<<grid_for(n, kB), kB, 0, s>>>(cptr.get(), work.get(), g->rowptr.get(), fbase.get(), pos.get(),
                                                 tcnt.get(), n, caps, pst.get());
-    TP_CHECK_LAUNCH();
-    k_work_stats<<<grid_for(n, kB), kB, 0, s>>>(work.get(), n, pst.get() + kStat, pst.get() + kStat + 1);
     TP_CHECK_LAUNCH();
     unsigned long long h[kStat + 2];
     TP_HIP(hipMemcpyAsync(h, pst.get(), sizeof(h), hipMemcpyDeviceToHost, s));
