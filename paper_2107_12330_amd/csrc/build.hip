@@ -370,17 +370,22 @@ __device__ __forceinline__ uint32_t degree_bin(uint32_t d)
 // Ranks are in degree order, so the degree bins are ranges of ranks:
 // first[k] = the first rank whose bin is >= k (first[] is pre-filled with
 // 2^32 - 1 for bins above the largest).  Rank i writes the bins it opens.
-// In a batch (rank_gid set) each graph's ranks are a range of their own in
-// degree order, so each graph g gets its own 32 bounds at first[32 g + k],
-// and a graph's first rank opens every bin up to its own.
-__global__ void k_dbin_rank(const uint32_t *deg, const uint32_t *perm, uint32_t n, const uint32_t *rank_gid,
-                            uint32_t *first)
+// In a batch each graph's ranks are a range of their own in degree order,
+// so each graph g gets its own 32 bounds at first[32 g + k], and a graph's
+// first rank opens every bin up to its own.  Rank i's degree (bits
+// [nb, gshift)) and graph (bits from gshift) are read from its sorted order
+// key, in rank order.
+__global__ void k_dbin_rank(const uint64_t *skey, uint32_t n, int nb, int gshift, bool batch, uint32_t *first)
 {
+    const uint64_t dmask = (1ull << (gshift - nb)) - 1;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t b = degree_bin(deg[perm[i]]);
-        const uint32_t g = rank_gid ? rank_gid[i] : 0u;
-        const bool opens = i == 0 || (rank_gid && rank_gid[i - 1] != g);
-        const int prev = opens ? -1 : (int)degree_bin(deg[perm[i - 1]]);
+        const uint64_t key = skey[i];
+        const uint32_t b = degree_bin((uint32_t)((key >> nb) & dmask));
+        const uint32_t g = batch ? (uint32_t)(key >> gshift) : 0u;
+        uint64_t pkey = 0;
+        if (i) pkey = skey[i - 1];
+        const bool opens = i == 0 || (batch && (uint32_t)(pkey >> gshift) != g);
+        const int prev = opens ? -1 : (int)degree_bin((uint32_t)((pkey >> nb) & dmask));
         for (int k = prev + 1; k <= (int)b; ++k) first[(size_t)g * 32 + k] = (uint32_t)i;
     }
 }
@@ -397,12 +402,12 @@ __global__ void fill_u32(uint32_t *p, size_t n, uint32_t v)
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-// graph id of every rank in a batch
-__global__ void k_rank_graph(const uint32_t *perm, uint32_t n, const uint32_t *voff, uint32_t n_graphs,
-                             uint32_t *rank_gid)
+// graph id of every rank in a batch: the bits above gshift of its sorted
+// order key
+__global__ void k_rank_graph(const uint64_t *skey, uint32_t n, int gshift, uint32_t *rank_gid)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        rank_gid[i] = graph_of_vertex(voff, n_graphs, perm[i]);
+        rank_gid[i] = (uint32_t)(skey[i] >> gshift);
 }
 
 // ------------------------------------------------------------ phase 4
@@ -1110,6 +1115,7 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
                                                    hb ? hb->n_graphs : 0u, el->tie_hash, rkeyA.get(), rvalA.get());
         TP_CHECK_LAUNCH();
         const bool rb = radix_sort_pairs(rkeyA.get(), rvalA.get(), rkeyB.get(), rvalB.get(), n, rbits, s);
+        const uint64_t *skey = rb ? rkeyB.get() : rkeyA.get();
         g->perm = rb ? std::move(rvalB) : std::move(rvalA);
         g->rlab.reset(n, s);
         k_rank_scatter<<<grid_for(n, kB), kB, 0, s>>>(g->perm.get(), n, vlab, rank.get(), g->rlab.get());
@@ -1117,8 +1123,7 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
         if (hb) {
             g->n_graphs = hb->n_graphs;
             g->rank_gid.reset(n, s);
-            k_rank_graph<<<grid_for(n, kB), kB, 0, s>>>(g->perm.get(), n, d_voff.get(), hb->n_graphs,
-                                                       g->rank_gid.get());
+            k_rank_graph<<<grid_for(n, kB), kB, 0, s>>>(skey, n, gshift, g->rank_gid.get());
             TP_CHECK_LAUNCH();
         }
         {
@@ -1130,8 +1135,7 @@ static void build_impl(const tp_edge_list *el, hipStream_t s, tp_graph **out, co
             g->dbin_rank.reset(nbins, s);
             fill_u32<<<grid_for(nbins, kB), kB, 0, s>>>(g->dbin_rank.get(), nbins, 0xffffffffu);
             TP_CHECK_LAUNCH();
-            k_dbin_rank<<<grid_for(n, kB), kB, 0, s>>>(deg.get(), g->perm.get(), n, hb ? g->rank_gid.get() : nullptr,
-                                                       g->dbin_rank.get());
+            k_dbin_rank<<<grid_for(n, kB), kB, 0, s>>>(skey, n, nb, gshift, hb != nullptr, g->dbin_rank.get());
             TP_CHECK_LAUNCH();
         }
     }
