@@ -738,9 +738,14 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
         qh = __builtin_amdgcn_readfirstlane(qh + count);
     };
     // reduce 128 queued hits, two per lane (the doubled ring of the plain
-    // survey): both hits' reads are issued before either is reduced
+    // survey): both hits' reads are issued before either is reduced.  The
+    // wave runs it at raised priority, so that its chains of LDS reads and
+    // adds issue ahead of the other waves' probing (large class 309.3 ->
+    // 302.1 ms; priority 3 no better, and the same for the one-hit drains of
+    // the other kernels slowed the batch survey)
     auto drain2 = [&](auto gm) {
         constexpr bool G = decltype(gm)::value;
+        __builtin_amdgcn_s_setprio(2);
         const uint4 e0 = ring[(qh + lane) & (kRingK - 1)];
         const uint4 e1 = ring[(qh + kWave + lane) & (kRingK - 1)];
         const uint32_t w0 = e0.x & 0x3fffffu, w1 = e1.x & 0x3fffffu;
@@ -763,6 +768,7 @@ __global__ __launch_bounds__(BLOCK, (WAVE && FORM == kFormSurvey && !ENUM) ? 8 :
         my_tri += tri;
         my_spread += spread;
         qh = __builtin_amdgcn_readfirstlane(qh + 2 * kWave);
+        __builtin_amdgcn_s_setprio(0);
     };
     auto drain_queued = [&]() {
         if constexpr (kRingK > kRing) {
